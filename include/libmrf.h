@@ -1,0 +1,182 @@
+/*
+ * libmrf — MRF dictionary generating and searching on one MI355X (gfx950).
+ *
+ * C ABI. Every function returns an int status (MRF_OK = 0); no exception
+ * crosses the boundary. mrf_last_error() returns a thread-local message for
+ * the last failing call on the calling thread.
+ *
+ * Ownership: the caller owns every device array passed in (voxels,
+ * dictionaries, outputs, workspaces) and libmrf never frees them. libmrf owns
+ * the opaque handles (context, sequence with its resident step tables,
+ * schedule, server). Device pointers are plain hipMalloc'ed (or torch) device
+ * memory on the context's device; host pointers are ordinary host memory.
+ *
+ * Streams: `void* stream` is a hipStream_t (NULL = the default stream). All
+ * device work of a call is enqueued on it and is asynchronous unless stated;
+ * outputs are valid after the stream has been synchronised. Calls on one
+ * context are serialised by the caller.
+ *
+ * Method (arxiv 1506.05393):
+ *   - signal model: inversion-recovery bSSFP train (Methods) simulated with
+ *     the Bloch model of the Appendix (Eq. A1, A2; hard-pulse RF);
+ *   - distance: |complex correlation| of Theory Eq. 1 (CC);
+ *   - brute-force search: the entry of maximal CC over the whole grid
+ *     (Introduction; Experiment 2);
+ *   - MRF-ZOOM: parameter-separable coarse-to-fine search (Theory: MRF ZOOM;
+ *     Methods: Experiment 2 steps 1-5; Experiment 3 neighbour prior).
+ *
+ * Units: times in ms, frequencies in Hz, angles in degrees.
+ * Grid entry index: k = ((i_t1*n_t2 + i_t2)*n_df + i_df)*max(n_b1,1) + i_b1.
+ */
+#ifndef LIBMRF_H
+#define LIBMRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MRF_OK = 0,
+  MRF_ERR_INVALID = 1,     /* bad argument (null pointer, size, range, dtype) */
+  MRF_ERR_OOM = 2,         /* device or host allocation failed */
+  MRF_ERR_DEVICE = 3,      /* a HIP call failed */
+  MRF_ERR_NOT_READY = 4,   /* result not available yet */
+  MRF_ERR_REJECTED = 5,    /* request can never be admitted */
+  MRF_ERR_UNSUPPORTED = 6, /* valid but not supported in this build */
+  MRF_ERR_CANCELLED = 7
+};
+
+typedef enum { MRF_F32 = 0, MRF_BF16 = 1 } mrf_dtype;
+
+const char* mrf_status_str(int status);
+const char* mrf_last_error(void);
+/* library version string */
+const char* mrf_version(void);
+
+typedef struct mrf_context mrf_context;
+typedef struct mrf_sequence mrf_sequence;
+
+/* Bind a context to HIP device `device` (makes it current on this thread). */
+int mrf_context_create(int device, mrf_context** out);
+int mrf_context_destroy(mrf_context* ctx);
+
+/* Acquisition sequence (Methods: IR-bSSFP; Theory: the same flip angles,
+ * phases, TR and TE are used to acquire and to simulate). Host arrays of n
+ * values, copied at creation. Requires 0 < te_ms[j] < tr_ms[j]. With
+ * inversion = 1 the longitudinal magnetisation is ideally inverted at t = 0
+ * and evolves freely for ti_ms >= 0 before the first pulse. */
+typedef struct {
+  int32_t n;
+  const double* fa_deg;
+  const double* phase_deg;
+  const double* tr_ms;
+  const double* te_ms;
+  int32_t inversion;
+  double ti_ms;
+} mrf_sequence_desc;
+
+int mrf_sequence_create(mrf_context* ctx, const mrf_sequence_desc* desc, mrf_sequence** out);
+int mrf_sequence_destroy(mrf_sequence* seq);
+
+/* Parameter grid: one strictly increasing host value list per axis
+ * (T1 ms > 0, T2 ms > 0, df Hz, B1 scale of every flip angle). b1.n == 0
+ * means B1 = 1. T1 or T2 may be +inf (no relaxation). */
+typedef struct {
+  int32_t n;
+  const double* v;
+} mrf_axis;
+typedef struct {
+  mrf_axis t1_ms, t2_ms, df_hz, b1;
+} mrf_grid;
+
+/* Number of grid entries, or -1 if the grid is invalid. */
+int64_t mrf_grid_size(const mrf_grid* grid);
+
+/* ------------------------------------------------------------------------
+ * Dictionary generation (Appendix Eq. A2 per entry; brute-force DGS).
+ *
+ * Simulates entries [entry_begin, entry_begin + entry_count) of `grid` over
+ * the first n_tr readouts (n_tr <= sequence n). FP32 state; the relaxation
+ * and precession factors are computed once per grid value in FP64 and
+ * rounded to FP32; the norm is accumulated in FP64.
+ *
+ * Layouts (entry e = k - entry_begin, 0 <= e < entry_count <= ld):
+ *   MRF_F32  : planar, time-major. re[j*ld + e] = Re d_j, im[j*ld + e] = Im d_j,
+ *              j < n_tr (re and im are separate [n_tr][ld] float arrays).
+ *   MRF_BF16 : packed blocks of 4 readouts, re holds the whole dictionary:
+ *              element ((b*ld + e)*4 + q)*2 + {0: Re, 1: Im} of readout
+ *              j = 4b + q, bf16 round-to-nearest-even; im must be NULL.
+ *              n_tr must be a multiple of 4.
+ * Values are the raw signal (M0 = 1) unless unit_norm = 1, in which case each
+ * entry is divided by its norm (two passes). norm (device, FP64
+ * [entry_count], or NULL) receives the raw norm ||d||.
+ * ---------------------------------------------------------------------- */
+int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                            int32_t n_tr, int64_t entry_begin, int64_t entry_count,
+                            mrf_dtype dtype, void* re, void* im, int64_t ld,
+                            double* norm, int32_t unit_norm, void* stream);
+
+/* Simulate fingerprints at arbitrary (not necessarily on-grid) parameter
+ * values: params is a device FP64 array [count][4] = (T1 ms, T2 ms, df Hz,
+ * B1). Output complex64 out[i*ld_out + j], j < n_tr (raw signal, M0 = 1). */
+int mrf_simulate_signals(mrf_context* ctx, const mrf_sequence* seq, int32_t n_tr,
+                         const double* params, int64_t count, void* out, int64_t ld_out,
+                         void* stream);
+
+/* ------------------------------------------------------------------------
+ * Brute-force matching (Theory Eq. 1; Introduction: exhaustive search).
+ *
+ * For each voxel v (complex64 vox[v*ld_vox + j], j < n_tr) and every entry k
+ * of the dictionary view, CC_vk = |sum_j v_j conj(d_kj)| / (||v|| ||d_k||).
+ * The entry of maximal CC is returned (ties: lower k). Computed as a complex
+ * GEMM on MFMA with the per-voxel running top-k fused into its epilogue; the
+ * voxel x entry score matrix is never written.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  mrf_dtype dtype;    /* layout as produced by mrf_simulate_dictionary */
+  int32_t n_tr;       /* readouts used (<= readouts stored) */
+  int64_t n_entries;  /* entries 0..n_entries-1 (global index = entry_base + e) */
+  int64_t ld;
+  const void* re;
+  const void* im;     /* NULL for MRF_BF16 */
+  const double* norm; /* raw norms [n_entries] (FP64), or NULL for unit-norm entries */
+  int64_t entry_base; /* grid index of entry 0 */
+} mrf_dict_view;
+
+/* Per-voxel outputs (device arrays of n_vox; any but idx may be NULL).
+ * idx: int64 grid index; cc: CC of that entry; margin: CC(best) - CC(runner-up)
+ * (FP32 search) or of the rescored candidates (BF16 search); pd_re/pd_im:
+ * proton density <v, d>/||d||^2 (Theory: PD from the signal scale);
+ * n_sim: entries evaluated (ZOOM). */
+typedef struct {
+  int64_t* idx;
+  float* cc;
+  float* margin;
+  float* pd_re;
+  float* pd_im;
+  int32_t* n_sim;
+} mrf_result_view;
+
+/* Workspace bytes needed by mrf_match_bruteforce for these sizes. */
+int mrf_match_workspace(mrf_context* ctx, const mrf_dict_view* dict, int32_t n_vox,
+                        int32_t top_k, size_t* bytes);
+
+/* top_k in [1, 64]: the kept candidate list per voxel (at least 2 internally
+ * for the margin). With a BF16 dictionary top_k must be >= 2 and seq/grid
+ * are required: the top_k BF16 candidates of each voxel are re-simulated in
+ * FP32 and re-scored exactly, and the best of them is returned. topk_idx /
+ * topk_cc (device [n_vox][top_k], optional) receive the candidate list
+ * (FP32: exact scores; BF16: the BF16 GEMM's CC estimates). */
+int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* dict, const void* vox,
+                         int32_t n_vox, int64_t ld_vox, int32_t top_k,
+                         const mrf_sequence* seq, const mrf_grid* grid, mrf_result_view out,
+                         int64_t* topk_idx, float* topk_cc, void* workspace,
+                         size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,103 @@
+"""ctypes declarations of libmrf's C ABI (include/libmrf.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Importing this module fails loudly when libmrf.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrf.so")
+
+MRF_OK = 0
+MRF_F32, MRF_BF16 = 0, 1
+STATUS = {0: "MRF_OK", 1: "MRF_ERR_INVALID", 2: "MRF_ERR_OOM", 3: "MRF_ERR_DEVICE",
+          4: "MRF_ERR_NOT_READY", 5: "MRF_ERR_REJECTED", 6: "MRF_ERR_UNSUPPORTED",
+          7: "MRF_ERR_CANCELLED"}
+
+
+class MRFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SequenceDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("fa_deg", C.POINTER(C.c_double)),
+                ("phase_deg", C.POINTER(C.c_double)), ("tr_ms", C.POINTER(C.c_double)),
+                ("te_ms", C.POINTER(C.c_double)), ("inversion", C.c_int32),
+                ("ti_ms", C.c_double)]
+
+
+class Axis(C.Structure):
+    _fields_ = [("n", C.c_int32), ("v", C.POINTER(C.c_double))]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("t1_ms", Axis), ("t2_ms", Axis), ("df_hz", Axis), ("b1", Axis)]
+
+
+class DictView(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("n_tr", C.c_int32), ("n_entries", C.c_int64),
+                ("ld", C.c_int64), ("re", C.c_void_p), ("im", C.c_void_p),
+                ("norm", C.c_void_p), ("entry_base", C.c_int64)]
+
+
+class ResultView(C.Structure):
+    _fields_ = [("idx", C.c_void_p), ("cc", C.c_void_p), ("margin", C.c_void_p),
+                ("pd_re", C.c_void_p), ("pd_im", C.c_void_p), ("n_sim", C.c_void_p)]
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("mrf_status_str", C.c_char_p, [C.c_int]),
+    ("mrf_last_error", C.c_char_p, []),
+    ("mrf_version", C.c_char_p, []),
+    ("mrf_context_create", C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+    ("mrf_context_destroy", C.c_int, [C.c_void_p]),
+    ("mrf_sequence_create", C.c_int, [C.c_void_p, C.POINTER(SequenceDesc), C.POINTER(C.c_void_p)]),
+    ("mrf_sequence_destroy", C.c_int, [C.c_void_p]),
+    ("mrf_grid_size", C.c_int64, [C.POINTER(GridDesc)]),
+    ("mrf_simulate_dictionary", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int64, C.c_int64, C.c_int,
+      C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("mrf_simulate_signals", C.c_int,
+     [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+      C.c_void_p]),
+    ("mrf_match_workspace", C.c_int,
+     [C.c_void_p, C.POINTER(DictView), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    ("mrf_match_bruteforce", C.c_int,
+     [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
+      C.POINTER(GridDesc), ResultView, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
+]
+
+
+def load():
+    """Load libmrf.so and declare every exported symbol (raises if missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libmrf.so is not built ({LIB_PATH}); run "
+                              "python -c 'import __graft_entry__; __graft_entry__.build()'")
+        lib = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_names():
+    return [s[0] for s in _SIGS]
+
+
+def check(status: int):
+    if status != MRF_OK:
+        msg = load().mrf_last_error().decode(errors="replace")
+        raise MRFError(status, msg)

@@ -1,0 +1,245 @@
+"""Python binding of libmrf: torch tensors in, torch tensors out.
+
+PyTorch provides device memory and streams only; every step of the method
+runs in libmrf's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self._lib = L.load()
+        h = C.c_void_p()
+        L.check(self._lib.mrf_context_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if self.handle:
+            self._lib.mrf_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sequence:
+    """A sequence resident in libmrf (host description + device copy)."""
+
+    def __init__(self, ctx: Context, seq):
+        self.ctx = ctx
+        self.seq = seq
+        self._keep = [np.ascontiguousarray(x, np.float64) for x in
+                      (seq.fa_deg, seq.phase_deg, seq.tr_ms, seq.te_ms)]
+        d = L.SequenceDesc(len(self._keep[0]), *[_dp(x) for x in self._keep],
+                           int(seq.inversion), float(seq.ti_ms))
+        h = C.c_void_p()
+        L.check(ctx._lib.mrf_sequence_create(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+        self.n = len(self._keep[0])
+
+    def close(self):
+        if self.handle:
+            self.ctx._lib.mrf_sequence_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GridArg:
+    """ctypes view of an inputs.Grid (keeps the numpy buffers alive)."""
+
+    def __init__(self, grid):
+        self.grid = grid
+        self._keep = [np.ascontiguousarray(a, np.float64) for a in
+                      (grid.t1_ms, grid.t2_ms, grid.df_hz, grid.b1)]
+        ax = [L.Axis(len(a), _dp(a) if len(a) else None) for a in self._keep]
+        self.desc = L.GridDesc(*ax)
+
+    @property
+    def ptr(self):
+        return C.byref(self.desc)
+
+
+@dataclasses.dataclass
+class Dictionary:
+    """A simulated dictionary in HBM.
+
+    f32 : re, im float32 [n_tr, ld] (planar, time-major)
+    bf16: packed bfloat16 blocks viewed as int16 [n_tr/4, ld, 4, 2]
+    norm: float64 [n_entries] raw norms (None when the entries are unit-norm)
+    """
+    dtype: str
+    n_tr: int
+    n_entries: int
+    ld: int
+    re: torch.Tensor
+    im: Optional[torch.Tensor]
+    norm: Optional[torch.Tensor]
+    entry_base: int = 0
+
+    def view(self, n_tr: Optional[int] = None) -> L.DictView:
+        n = self.n_tr if n_tr is None else int(n_tr)
+        return L.DictView(L.MRF_F32 if self.dtype == "f32" else L.MRF_BF16, n, self.n_entries,
+                          self.ld, self.re.data_ptr(),
+                          self.im.data_ptr() if self.im is not None else None,
+                          self.norm.data_ptr() if self.norm is not None else None,
+                          self.entry_base)
+
+    @property
+    def nbytes(self) -> int:
+        b = self.re.numel() * self.re.element_size()
+        if self.im is not None:
+            b += self.im.numel() * self.im.element_size()
+        return b
+
+
+def _round_up(x: int, m: int) -> int:
+    return (x + m - 1) // m * m
+
+
+def alloc_dictionary(n_tr: int, n_entries: int, dtype: str = "f32", device="cuda",
+                     ld: Optional[int] = None, with_norm: bool = True) -> Dictionary:
+    ld = _round_up(max(n_entries, 1), 256) if ld is None else int(ld)
+    if dtype == "f32":
+        re = torch.empty((n_tr, ld), dtype=torch.float32, device=device)
+        im = torch.empty((n_tr, ld), dtype=torch.float32, device=device)
+    elif dtype == "bf16":
+        if n_tr % 4:
+            raise ValueError("BF16 dictionaries need n_tr % 4 == 0")
+        re = torch.empty((n_tr // 4, ld, 4, 2), dtype=torch.int16, device=device)
+        im = None
+    else:
+        raise ValueError(dtype)
+    norm = torch.empty(n_entries, dtype=torch.float64, device=device) if with_norm else None
+    return Dictionary(dtype, n_tr, n_entries, ld, re, im, norm)
+
+
+def simulate_dictionary(ctx: Context, seq: Sequence, grid, n_tr: Optional[int] = None,
+                        dtype: str = "f32", entry_begin: int = 0,
+                        entry_count: Optional[int] = None, unit_norm: bool = False,
+                        out: Optional[Dictionary] = None, stream=None) -> Dictionary:
+    n_tr = seq.n if n_tr is None else int(n_tr)
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    count = g.grid.size - entry_begin if entry_count is None else int(entry_count)
+    d = out if out is not None else alloc_dictionary(n_tr, count, dtype, ctx.device,
+                                                     with_norm=True)
+    d.entry_base = int(entry_begin)
+    L.check(ctx._lib.mrf_simulate_dictionary(
+        ctx.handle, seq.handle, g.ptr, n_tr, int(entry_begin), count,
+        L.MRF_F32 if dtype == "f32" else L.MRF_BF16, d.re.data_ptr(),
+        d.im.data_ptr() if d.im is not None else None, d.ld,
+        d.norm.data_ptr() if d.norm is not None else None, int(bool(unit_norm)),
+        _stream_ptr(stream)))
+    if unit_norm:
+        d_norm_raw = d.norm
+        d.norm = None
+        d.raw_norm = d_norm_raw  # type: ignore[attr-defined]
+    return d
+
+
+def simulate_signals(ctx: Context, seq: Sequence, params: torch.Tensor,
+                     n_tr: Optional[int] = None, stream=None) -> torch.Tensor:
+    """params: float64 cuda [count, 4] (T1, T2, df, B1) -> complex64 [count, n_tr]."""
+    n_tr = seq.n if n_tr is None else int(n_tr)
+    params = params.to(device=ctx.device, dtype=torch.float64).contiguous()
+    out = torch.empty((params.shape[0], n_tr), dtype=torch.complex64, device=ctx.device)
+    L.check(ctx._lib.mrf_simulate_signals(ctx.handle, seq.handle, n_tr, params.data_ptr(),
+                                          params.shape[0], out.data_ptr(), n_tr,
+                                          _stream_ptr(stream)))
+    return out
+
+
+def match_workspace_bytes(ctx: Context, d: Dictionary, n_vox: int, top_k: int,
+                          n_tr: Optional[int] = None) -> int:
+    v = d.view(n_tr)
+    b = C.c_size_t()
+    L.check(ctx._lib.mrf_match_workspace(ctx.handle, C.byref(v), int(n_vox), int(top_k),
+                                         C.byref(b)))
+    return int(b.value)
+
+
+class Workspace:
+    """A reusable device byte buffer (grown on demand)."""
+
+    def __init__(self, device):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def _result_tensors(n_vox: int, device, with_nsim=False):
+    return dict(idx=torch.empty(n_vox, dtype=torch.int64, device=device),
+                cc=torch.empty(n_vox, dtype=torch.float32, device=device),
+                margin=torch.empty(n_vox, dtype=torch.float32, device=device),
+                pd_re=torch.empty(n_vox, dtype=torch.float32, device=device),
+                pd_im=torch.empty(n_vox, dtype=torch.float32, device=device),
+                **({"n_sim": torch.empty(n_vox, dtype=torch.int32, device=device)}
+                   if with_nsim else {}))
+
+
+def _result_view(r: dict) -> L.ResultView:
+    p = lambda k: r[k].data_ptr() if k in r and r[k] is not None else None
+    return L.ResultView(p("idx"), p("cc"), p("margin"), p("pd_re"), p("pd_im"), p("n_sim"))
+
+
+def match_bruteforce(ctx: Context, d: Dictionary, vox: torch.Tensor, top_k: int = 1,
+                     seq: Optional[Sequence] = None, grid=None, n_tr: Optional[int] = None,
+                     workspace: Optional[Workspace] = None, with_topk: bool = False,
+                     out: Optional[dict] = None, stream=None) -> dict:
+    """vox: complex64 cuda [n_vox, >= n_tr]. Returns a dict of device tensors."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda:
+        raise ValueError("vox must be a complex64 CUDA tensor")
+    if vox.stride(1) != 1:
+        raise ValueError("vox rows must be contiguous")
+    n_vox = vox.shape[0]
+    v = d.view(n_tr)
+    ws = workspace if workspace is not None else Workspace(ctx.device)
+    nb = match_workspace_bytes(ctx, d, n_vox, top_k, n_tr)
+    buf = ws.get(nb)
+    r = out if out is not None else _result_tensors(n_vox, ctx.device)
+    tk_i = tk_c = None
+    if with_topk:
+        tk_i = torch.empty((n_vox, top_k), dtype=torch.int64, device=ctx.device)
+        tk_c = torch.empty((n_vox, top_k), dtype=torch.float32, device=ctx.device)
+        r["topk_idx"], r["topk_cc"] = tk_i, tk_c
+    g = None
+    if grid is not None:
+        g = grid if isinstance(grid, GridArg) else GridArg(grid)
+        r["_grid"] = g
+    L.check(ctx._lib.mrf_match_bruteforce(
+        ctx.handle, C.byref(v), vox.data_ptr(), n_vox, vox.stride(0), int(top_k),
+        seq.handle if seq is not None else None, g.ptr if g is not None else None,
+        _result_view(r), tk_i.data_ptr() if tk_i is not None else None,
+        tk_c.data_ptr() if tk_c is not None else None, buf.data_ptr(), buf.numel(),
+        _stream_ptr(stream)))
+    return r

@@ -1,0 +1,77 @@
+// Internal definitions shared by the libmrf translation units (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/libmrf.h"
+
+namespace mrf {
+
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define MRF_CHECK_ARG(cond, ...)      \
+  do {                                \
+    if (!(cond)) {                    \
+      ::mrf::set_error(__VA_ARGS__);  \
+      return MRF_ERR_INVALID;         \
+    }                                 \
+  } while (0)
+
+#define MRF_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::mrf::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),  \
+                       __FILE__, __LINE__);                                    \
+      return MRF_ERR_DEVICE;                                                   \
+    }                                                                          \
+  } while (0)
+
+// Device tables of one (sequence, grid, n_tr): per-readout factors, FP64
+// computed and rounded to FP32 once (layouts step-major, see tables.hip).
+struct Tables {
+  uint64_t key = 0;
+  int32_t n_tr = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;  // n4 >= 1
+  int32_t inversion = 1;
+  float2* t1 = nullptr;   // [n_tr][n1]  (1-E1 over TE, 1-E1 over TR-TE)
+  float* t1ti = nullptr;  // [n1]        (1-E1 over TI)
+  float2* t2 = nullptr;   // [n_tr][n2]  (1-E2 over TE, 1-E2 over TR-TE)
+  float4* df = nullptr;   // [n_tr][n3]  (cos-1, sin over TE, cos-1, sin over TR-TE)
+  float* rf = nullptr;    // [n4][n_tr][9] pulse rotation matrix
+  void* block = nullptr;  // one allocation holding all of the above
+};
+
+}  // namespace mrf
+
+struct mrf_context {
+  int device = 0;
+  int n_cu = 0;
+  int warp = 64;
+};
+
+struct mrf_sequence {
+  mrf_context* ctx = nullptr;
+  int32_t n = 0;
+  std::vector<double> fa, ph, tr, te;
+  int32_t inversion = 1;
+  double ti = 0.0;
+  double omega_hz = 0.0;  // 1000 / min TR: CC pseudo-period in df (Property II)
+  double* dev = nullptr;  // device FP64 [4][n]: TE, TR-TE, flip angle, RF phase
+  std::mutex mu;
+  std::vector<mrf::Tables> cache;  // small LRU keyed by grid contents and n_tr
+};
+
+namespace mrf {
+// Validate a grid (axis lengths, strictly increasing, finite where required).
+int check_grid(const mrf_grid* g);
+// Tables of (seq, grid, n_tr), built (on `stream`) on first use and cached.
+int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t stream,
+               const Tables** out);
+int64_t grid_size_checked(const mrf_grid* g);
+}  // namespace mrf

@@ -1,0 +1,530 @@
+// Brute-force matching (Theory Eq. 1, exhaustive search): K2 voxel packing,
+// K3 complex GEMM on MFMA with a fused per-voxel top-k epilogue, K4 merge.
+//
+// The complex inner products s_vk = sum_j vhat_j conj(d_kj) are a real GEMM
+// C = A^T B with K = 2 n_tr: for readout j and plane g (0: real, 1: imaginary)
+//   B[g][j][k] = Re/Im d_kj (the dictionary's planar layout),
+//   A[g][j][2v]   = (Re vhat_j, Im vhat_j)[g]   -> C[2v][k]   = Re s_vk
+//   A[g][j][2v+1] = (Im vhat_j, -Re vhat_j)[g]  -> C[2v+1][k] = Im s_vk
+// so CC_vk^2 = (C[2v][k]^2 + C[2v+1][k]^2) / ||d_k||^2. The score matrix is
+// never written: every workgroup keeps the running top-k of its voxels over
+// its share of the entries and writes only those lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "match_kernels.h"
+
+namespace mrf {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// Tile geometry of the FP32 GEMM.
+// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement over a 128-row x
+// 128-column tile; each wave owns 64 x 64 = 2 x 2 blocks of 32 x 32
+// (v_mfma_f32_32x32x2_f32: per instruction lanes 0-31 carry plane 0 and lanes
+// 32-63 plane 1 of one readout, so one instruction = one readout of K).
+// ---------------------------------------------------------------------------
+constexpr int BM = 128;     // rows (64 voxels)
+constexpr int BN = 128;     // entries
+constexpr int KC = 32;      // readouts per LDS chunk
+constexpr int KK_MAX = 16;  // longest candidate list kept in the epilogue
+
+struct MatchArgs {
+  const float* A;       // [2][n_tr_pad][m_pad]
+  const float* Bre;     // [n_tr][ld]
+  const float* Bim;
+  const double* norm;   // [n_entries] or NULL
+  int32_t n_tr, n_tr_pad, m_pad, n_vox_pad;
+  int64_t ld, n_entries;
+  int32_t n_row_tiles, n_chunks, n_col_tiles, kk;
+  float* part_s;        // [n_chunks][2][n_vox_pad][kk]
+  int32_t* part_i;
+};
+
+__device__ __forceinline__ bool beats(float s, int32_t i, float t, int32_t j) {
+  return s > t || (s == t && i < j);
+}
+
+// Insert (s, e) into the wave's list for voxel slot `vl` (lists in LDS,
+// sorted best first; lanes < kk each own one position). Uniform control flow.
+__device__ __forceinline__ void list_insert(float* ls, int32_t* li, int kk, int lane, float s,
+                                            int32_t e) {
+  float cs = -1.0f;
+  int32_t ci = 0x7fffffff;
+  if (lane < kk) {
+    cs = ls[lane];
+    ci = li[lane];
+  }
+  const bool better_here = (lane < kk) && beats(cs, ci, s, e);
+  const uint64_t m = __ballot(better_here);
+  const int p = __popcll(m);  // entries that stay ahead of the new one
+  if (p >= kk) return;
+  // shift down by one from p, then place the new entry
+  const float ps = __shfl_up(cs, 1);
+  const int32_t pi = __shfl_up(ci, 1);
+  if (lane < kk) {
+    if (lane == p) {
+      ls[lane] = s;
+      li[lane] = e;
+    } else if (lane > p) {
+      ls[lane] = ps;
+      li[lane] = pi;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
+  // XCD-aware mapping: consecutive workgroup ids go to different XCDs
+  // (round robin over 8), so the row tiles of one column chunk are grouped on
+  // one XCD and share its L2 for the dictionary tiles.
+  const int w = blockIdx.x;
+  const int xcd = w & 7;
+  const int slot = w >> 3;
+  const int rt = slot % a.n_row_tiles;
+  const int chunk = xcd + 8 * (slot / a.n_row_tiles);
+  if (chunk >= a.n_chunks) return;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* As = (float*)smem;                    // [2 buf][2 g][KC][BM]
+  float* Bs = As + 2 * 2 * KC * BM;            // [2 buf][2 g][KC][BN]
+  float* Ls = Bs + 2 * 2 * KC * BN;            // [4 waves][32 voxels][KK_MAX]
+  int32_t* Li = (int32_t*)(Ls + 4 * 32 * KK_MAX);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = a.kk;
+  const int row0 = rt * BM;
+
+  float* myLs = Ls + wave * 32 * KK_MAX;
+  int32_t* myLi = Li + wave * 32 * KK_MAX;
+  for (int i = lane; i < 32 * KK_MAX; i += 64) {
+    myLs[i] = -1.0f;
+    myLi[i] = 0x7fffffff;
+  }
+  float thr[16];  // per lane: current k-th best of its 16 voxels
+#pragma unroll
+  for (int i = 0; i < 16; ++i) thr[i] = -1.0f;
+
+  const int ct_begin = (int)((int64_t)chunk * a.n_col_tiles / a.n_chunks);
+  const int ct_end = (int)((int64_t)(chunk + 1) * a.n_col_tiles / a.n_chunks);
+  const int n_kc = a.n_tr_pad / KC;
+
+  for (int ct = ct_begin; ct < ct_end; ++ct) {
+    const int64_t col0 = (int64_t)ct * BN;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    float4 ra[8], rb[8];
+    auto gload = [&](int c) {
+      const int s0 = c * KC;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int idx = i * 256 + tid;  // [g][s][c4] with 32 float4 per row
+        const int g = idx >> 10;        // / (KC * 32)
+        const int s = (idx >> 5) & (KC - 1);
+        const int c4 = idx & 31;
+        ra[i] = *(const float4*)(a.A + ((int64_t)g * a.n_tr_pad + s0 + s) * a.m_pad + row0 + 4 * c4);
+        const int64_t col = col0 + 4 * c4;
+        const float* bp = g ? a.Bim : a.Bre;
+        if (s0 + s < a.n_tr && col + 4 <= a.ld)
+          rb[i] = *(const float4*)(bp + (int64_t)(s0 + s) * a.ld + col);
+        else
+          rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    auto sstore = [&](int buf) {
+      float* as = As + buf * 2 * KC * BM;
+      float* bs = Bs + buf * 2 * KC * BN;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int idx = i * 256 + tid;
+        *(float4*)(as + 4 * idx) = ra[i];
+        *(float4*)(bs + 4 * idx) = rb[i];
+      }
+    };
+
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int c = 0; c < n_kc; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < n_kc) gload(c + 1);
+      const float* as = As + buf * 2 * KC * BM + (lane >> 5) * KC * BM + wr * 64 + (lane & 31);
+      const float* bs = Bs + buf * 2 * KC * BN + (lane >> 5) * KC * BN + wc * 64 + (lane & 31);
+#pragma unroll 8
+      for (int s = 0; s < KC; ++s) {
+        const float a0 = as[s * BM], a1 = as[s * BM + 32];
+        const float b0 = bs[s * BN], b1 = bs[s * BN + 32];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+      if (c + 1 < n_kc) sstore(buf ^ 1);
+      __syncthreads();
+    }
+
+    // ---- epilogue: scores of this tile, threshold filter, list insertion ----
+    float inv[2];
+    int32_t ecol[2];
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) {
+      const int64_t e = col0 + wc * 64 + bn * 32 + (lane & 31);
+      ecol[bn] = (int32_t)e;
+      if (e < a.n_entries) {
+        double n = a.norm ? a.norm[e] : 1.0;
+        inv[bn] = n > 0.0 ? (float)(1.0 / (n * n)) : 0.0f;
+      } else {
+        inv[bn] = -1.0f;  // marks a padding column
+      }
+    }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm) {
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          // rows 8*(q/2) + 4*h + 2*(q%2) + {0,1}: voxel (4*(q/2) + 2*h + q%2) of the block
+          const int r = 4 * (q >> 1) + 2 * (q & 1);
+          const float re = acc[bm][bn][r], im = acc[bm][bn][r + 1];
+          const float sc = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
+          const int t = bm * 8 + q;
+          const bool cand = sc > thr[t];
+          uint64_t m = __ballot(cand);
+          while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const float s = __shfl(sc, src);
+            const int32_t e = __shfl(ecol[bn], src);
+            // voxel slot of lane src within this wave's 32 voxels
+            const int vl = bm * 16 + 4 * (q >> 1) + 2 * (src >> 5) + (q & 1);
+            list_insert(myLs + vl * KK_MAX, myLi + vl * KK_MAX, kk, lane, s, e);
+          }
+        }
+      }
+    }
+    // refresh thresholds (k-th best of each voxel this lane holds)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int vl = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
+        thr[bm * 8 + q] = myLs[vl * KK_MAX + kk - 1];
+      }
+  }
+
+  // write this wave's lists: partial[chunk][wc][voxel][kk]
+  for (int i = lane; i < 32 * kk; i += 64) {
+    const int vl = i / kk, p = i % kk;
+    const int v = (row0 + wr * 64) / 2 + vl;
+    if (v < a.n_vox_pad) {
+      const int64_t o = (((int64_t)chunk * 2 + wc) * a.n_vox_pad + v) * kk + p;
+      a.part_s[o] = myLs[vl * KK_MAX + p];
+      a.part_i[o] = myLi[vl * KK_MAX + p];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2: voxel normalisation and packing of the A operand. One wave per voxel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_pack_f32(const float2* __restrict__ vox, int64_t ld_vox,
+                                                 int32_t n_vox, int32_t n_tr, int32_t n_tr_pad,
+                                                 int32_t m_pad, float* __restrict__ A,
+                                                 double* __restrict__ vnorm) {
+  const int v = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s2 = 0.0;
+  if (v < n_vox) {
+    for (int j = lane; j < n_tr; j += 64) {
+      const float2 x = vox[(int64_t)v * ld_vox + j];
+      s2 = fma((double)x.x, (double)x.x, s2);
+      s2 = fma((double)x.y, (double)x.y, s2);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+  const double nv = sqrt(s2);
+  const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
+  if (lane == 0 && v < n_vox) vnorm[v] = nv;
+  for (int j = lane; j < n_tr_pad; j += 64) {
+    float2 x = make_float2(0.f, 0.f);
+    if (v < n_vox && j < n_tr) x = vox[(int64_t)v * ld_vox + j];
+    const float xr = x.x * inv, xi = x.y * inv;
+    *(float2*)(A + (int64_t)j * m_pad + 2 * v) = make_float2(xr, xi);
+    *(float2*)(A + ((int64_t)n_tr_pad + j) * m_pad + 2 * v) = make_float2(xi, -xr);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: merge the partial lists of every chunk into the final top-k per voxel.
+// ---------------------------------------------------------------------------
+struct MergeArgs {
+  const float* part_s;
+  const int32_t* part_i;
+  int32_t n_lists, n_vox, n_vox_pad, kk, top_k;
+  int64_t entry_base;
+  float* best_s;     // [n_vox][kk] workspace copy of the merged list
+  int32_t* best_i;
+  int64_t* idx;
+  float* cc;
+  float* margin;
+  int64_t* topk_idx;
+  float* topk_cc;
+};
+
+__global__ __launch_bounds__(64) void k_merge(MergeArgs a) {
+  const int v = blockIdx.x * 64 + threadIdx.x;
+  if (v >= a.n_vox) return;
+  float ls[KK_MAX];
+  int32_t li[KK_MAX];
+  for (int p = 0; p < KK_MAX; ++p) {
+    ls[p] = -1.0f;
+    li[p] = 0x7fffffff;
+  }
+  for (int l = 0; l < a.n_lists; ++l) {
+    const int64_t o = ((int64_t)l * a.n_vox_pad + v) * a.kk;
+    for (int p = 0; p < a.kk; ++p) {
+      float s = a.part_s[o + p];
+      int32_t e = a.part_i[o + p];
+      if (e == 0x7fffffff) break;
+      if (!beats(s, e, ls[a.kk - 1], li[a.kk - 1])) break;  // lists are sorted
+      int q = a.kk - 1;
+      while (q > 0 && beats(s, e, ls[q - 1], li[q - 1])) {
+        ls[q] = ls[q - 1];
+        li[q] = li[q - 1];
+        --q;
+      }
+      ls[q] = s;
+      li[q] = e;
+    }
+  }
+  for (int p = 0; p < a.kk; ++p) {
+    a.best_s[(int64_t)v * a.kk + p] = ls[p];
+    a.best_i[(int64_t)v * a.kk + p] = li[p];
+  }
+  const float c1 = sqrtf(fmaxf(ls[0], 0.0f));
+  if (a.idx) a.idx[v] = li[0] == 0x7fffffff ? -1 : a.entry_base + li[0];
+  if (a.cc) a.cc[v] = c1;
+  if (a.margin) a.margin[v] = li[1] == 0x7fffffff ? INFINITY : c1 - sqrtf(fmaxf(ls[1], 0.0f));
+  for (int p = 0; p < a.top_k; ++p) {
+    if (a.topk_idx)
+      a.topk_idx[(int64_t)v * a.top_k + p] = li[p] == 0x7fffffff ? -1 : a.entry_base + li[p];
+    if (a.topk_cc) a.topk_cc[(int64_t)v * a.top_k + p] = sqrtf(fmaxf(ls[p], 0.0f));
+  }
+}
+
+// PD = <v, d> / ||d||^2 of the best entry (Theory: PD from the signal scale).
+// One wave per voxel; FP32 planar dictionary.
+__global__ __launch_bounds__(64) void k_pd_f32(const float2* __restrict__ vox, int64_t ld_vox,
+                                               int32_t n_vox, int32_t n_tr, const float* Bre,
+                                               const float* Bim, int64_t ld,
+                                               const int32_t* best_i, int32_t kk,
+                                               const double* norm, float* pd_re, float* pd_im) {
+  const int v = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (v >= n_vox) return;
+  const int32_t e = best_i[(int64_t)v * kk];
+  double sr = 0.0, si = 0.0, n2 = 0.0;
+  if (e != 0x7fffffff) {
+    for (int j = lane; j < n_tr; j += 64) {
+      const float2 x = vox[(int64_t)v * ld_vox + j];
+      const double dr = Bre[(int64_t)j * ld + e], di = Bim[(int64_t)j * ld + e];
+      sr += (double)x.x * dr + (double)x.y * di;
+      si += (double)x.y * dr - (double)x.x * di;
+      n2 += dr * dr + di * di;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o);
+    si += __shfl_xor(si, o);
+    n2 += __shfl_xor(n2, o);
+  }
+  if (lane == 0) {
+    // n_tr may be a prefix of the stored entries: use the prefix norm
+    (void)norm;
+    const double d2 = n2;
+    if (pd_re) pd_re[v] = d2 > 0.0 ? (float)(sr / d2) : 0.0f;
+    if (pd_im) pd_im[v] = d2 > 0.0 ? (float)(si / d2) : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+  int32_t n_tr_pad, m_pad, n_vox_pad, n_row_tiles, n_col_tiles, n_chunks, kk;
+  size_t off_A, off_vn, off_ps, off_pi, off_bs, off_bi, total;
+};
+
+static Plan make_plan(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu) {
+  Plan p;
+  p.kk = std::max(top_k, 2);
+  p.n_tr_pad = (d->n_tr + KC - 1) / KC * KC;
+  p.m_pad = std::max((2 * n_vox + BM - 1) / BM * BM, BM);
+  p.n_vox_pad = p.m_pad / 2;
+  p.n_row_tiles = p.m_pad / BM;
+  p.n_col_tiles = (int32_t)((d->n_entries + BN - 1) / BN);
+  // enough chunks to give every CU several workgroups, a multiple of 8 (XCDs)
+  int want = (4 * n_cu + p.n_row_tiles - 1) / p.n_row_tiles;
+  want = std::min(want, std::max(p.n_col_tiles, 1));
+  p.n_chunks = std::max(8, (want + 7) / 8 * 8);
+  size_t o = 0;
+  p.off_A = o;
+  o = al(o + sizeof(float) * 2 * (size_t)p.n_tr_pad * p.m_pad);
+  p.off_vn = o;
+  o = al(o + sizeof(double) * (size_t)p.n_vox_pad);
+  const size_t np = (size_t)p.n_chunks * 2 * p.n_vox_pad * p.kk;
+  p.off_ps = o;
+  o = al(o + sizeof(float) * np);
+  p.off_pi = o;
+  o = al(o + sizeof(int32_t) * np);
+  p.off_bs = o;
+  o = al(o + sizeof(float) * (size_t)p.n_vox_pad * p.kk);
+  p.off_bi = o;
+  o = al(o + sizeof(int32_t) * (size_t)p.n_vox_pad * p.kk);
+  p.total = o;
+  return p;
+}
+
+static int check_view(const mrf_dict_view* d) {
+  MRF_CHECK_ARG(d != nullptr, "dictionary view is NULL");
+  MRF_CHECK_ARG(d->dtype == MRF_F32 || d->dtype == MRF_BF16, "unknown dictionary dtype");
+  MRF_CHECK_ARG(d->n_tr >= 1, "dictionary n_tr must be >= 1");
+  MRF_CHECK_ARG(d->n_entries >= 1 && d->n_entries <= 0x7ffffffe,
+                "dictionary n_entries (%lld) out of range", (long long)d->n_entries);
+  MRF_CHECK_ARG(d->ld >= d->n_entries, "dictionary ld must be >= n_entries");
+  MRF_CHECK_ARG(d->ld % 4 == 0, "dictionary ld must be a multiple of 4");
+  MRF_CHECK_ARG(d->re != nullptr, "dictionary re is NULL");
+  MRF_CHECK_ARG(((uintptr_t)d->re & 15) == 0, "dictionary re must be 16-byte aligned");
+  if (d->dtype == MRF_F32) {
+    MRF_CHECK_ARG(d->im != nullptr, "dictionary im is NULL");
+    MRF_CHECK_ARG(((uintptr_t)d->im & 15) == 0, "dictionary im must be 16-byte aligned");
+  } else {
+    MRF_CHECK_ARG(d->im == nullptr, "im must be NULL for a packed BF16 dictionary");
+    MRF_CHECK_ARG(d->n_tr % 4 == 0, "BF16 dictionary n_tr must be a multiple of 4");
+  }
+  MRF_CHECK_ARG(d->entry_base >= 0, "entry_base must be >= 0");
+  return MRF_OK;
+}
+
+}  // namespace mrf
+
+using namespace mrf;
+
+extern "C" int mrf_match_workspace(mrf_context* ctx, const mrf_dict_view* d, int32_t n_vox,
+                                   int32_t top_k, size_t* bytes) {
+  MRF_CHECK_ARG(ctx && bytes, "NULL argument");
+  int rc = check_view(d);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
+  MRF_CHECK_ARG(top_k >= 1 && top_k <= KK_MAX, "top_k must be in [1, %d]", KK_MAX);
+  if (d->dtype == MRF_BF16) {
+    *bytes = bf16_workspace_bytes(d, n_vox, top_k, ctx->n_cu);
+    return MRF_OK;
+  }
+  *bytes = make_plan(d, n_vox, top_k, ctx->n_cu).total;
+  return MRF_OK;
+}
+
+extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, const void* vox,
+                                    int32_t n_vox, int64_t ld_vox, int32_t top_k,
+                                    const mrf_sequence* seq, const mrf_grid* grid,
+                                    mrf_result_view out, int64_t* topk_idx, float* topk_cc,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  MRF_CHECK_ARG(ctx != nullptr, "context is NULL");
+  int rc = check_view(d);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
+  MRF_CHECK_ARG(top_k >= 1 && top_k <= KK_MAX, "top_k must be in [1, %d]", KK_MAX);
+  if (n_vox == 0) return MRF_OK;
+  MRF_CHECK_ARG(vox != nullptr, "vox is NULL");
+  MRF_CHECK_ARG(ld_vox >= d->n_tr, "ld_vox (%lld) must be >= n_tr (%d)", (long long)ld_vox, d->n_tr);
+  MRF_CHECK_ARG(out.idx != nullptr, "out.idx is NULL");
+  MRF_CHECK_ARG(workspace != nullptr, "workspace is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (d->dtype == MRF_BF16) {
+    return match_bf16(ctx, d, vox, n_vox, ld_vox, top_k, seq, grid, out, topk_idx, topk_cc,
+                      workspace, ws_bytes, st);
+  }
+  const Plan p = make_plan(d, n_vox, top_k, ctx->n_cu);
+  MRF_CHECK_ARG(ws_bytes >= p.total, "workspace too small (%zu < %zu bytes)", ws_bytes, p.total);
+  char* ws = (char*)workspace;
+  float* A = (float*)(ws + p.off_A);
+  double* vn = (double*)(ws + p.off_vn);
+  float* ps = (float*)(ws + p.off_ps);
+  int32_t* pi = (int32_t*)(ws + p.off_pi);
+  float* bs = (float*)(ws + p.off_bs);
+  int32_t* bi = (int32_t*)(ws + p.off_bi);
+
+  hipLaunchKernelGGL(k_pack_f32, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox, ld_vox,
+                     n_vox, d->n_tr, p.n_tr_pad, p.m_pad, A, vn);
+  MRF_HIP(hipGetLastError());
+
+  MatchArgs a;
+  a.A = A;
+  a.Bre = (const float*)d->re;
+  a.Bim = (const float*)d->im;
+  a.norm = d->norm;
+  a.n_tr = d->n_tr;
+  a.n_tr_pad = p.n_tr_pad;
+  a.m_pad = p.m_pad;
+  a.n_vox_pad = p.n_vox_pad;
+  a.ld = d->ld;
+  a.n_entries = d->n_entries;
+  a.n_row_tiles = p.n_row_tiles;
+  a.n_chunks = p.n_chunks;
+  a.n_col_tiles = p.n_col_tiles;
+  a.kk = p.kk;
+  a.part_s = ps;
+  a.part_i = pi;
+  const int grid_wg = p.n_row_tiles * p.n_chunks;
+  const size_t lds = sizeof(float) * (2 * 2 * KC * BM + 2 * 2 * KC * BN) +
+                     (sizeof(float) + sizeof(int32_t)) * 4 * 32 * KK_MAX;
+  static bool attr_set = false;
+  if (!attr_set) {
+    MRF_HIP(hipFuncSetAttribute((const void*)k_match_f32,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_match_f32, dim3(grid_wg), dim3(256), lds, st, a);
+  MRF_HIP(hipGetLastError());
+
+  MergeArgs m;
+  m.part_s = ps;
+  m.part_i = pi;
+  m.n_lists = p.n_chunks * 2;
+  m.n_vox = n_vox;
+  m.n_vox_pad = p.n_vox_pad;
+  m.kk = p.kk;
+  m.top_k = top_k;
+  m.entry_base = d->entry_base;
+  m.best_s = bs;
+  m.best_i = bi;
+  m.idx = out.idx;
+  m.cc = out.cc;
+  m.margin = out.margin;
+  m.topk_idx = topk_idx;
+  m.topk_cc = topk_cc;
+  hipLaunchKernelGGL(k_merge, dim3((n_vox + 63) / 64), dim3(64), 0, st, m);
+  MRF_HIP(hipGetLastError());
+  if (out.pd_re || out.pd_im) {
+    hipLaunchKernelGGL(k_pd_f32, dim3(n_vox), dim3(64), 0, st, (const float2*)vox, ld_vox, n_vox,
+                       d->n_tr, (const float*)d->re, (const float*)d->im, d->ld, bi, p.kk,
+                       d->norm, out.pd_re, out.pd_im);
+    MRF_HIP(hipGetLastError());
+  }
+  return MRF_OK;
+}

@@ -1,0 +1,14 @@
+// Declarations shared by the FP32 and BF16 matching translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mrf {
+size_t bf16_workspace_bytes(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu);
+int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_t n_vox,
+               int64_t ld_vox, int32_t top_k, const mrf_sequence* seq, const mrf_grid* grid,
+               mrf_result_view out, int64_t* topk_idx, float* topk_cc, void* workspace,
+               size_t ws_bytes, hipStream_t stream);
+}  // namespace mrf

@@ -1,0 +1,71 @@
+"""The benchmark workloads: sequence, grid and phantom of each, by name.
+
+Every workload is seeded and synthetic. The paper's Experiment 3 maps come
+from a structural brain image that is not available; the smooth phantoms with
+elliptical tissue regions stand in for those 64x64 slices.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import inputs as I
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    seq: I.Sequence
+    grid: I.Grid
+    phantom: I.Phantom
+    n_tr: int
+    note: str = ""
+
+
+def small_dgs(on_grid: bool = True) -> Workload:
+    """16x16 phantom of 4 tissue classes, N = 200, 60 x 40 x 21 = 50,400 entries,
+    SNR 20 (plain DGS: brute force and ZOOM on the same data)."""
+    seq = I.make_sequence(200, 0)
+    grid = I.make_grid(I.grid_linspace(100, 2000, 60), I.grid_geomspace(20, 400, 40),
+                       I.grid_arange(-40, 40, 4))
+    ph = I.phantom_quadrants(grid, 16, 100, snr=20.0, on_grid=on_grid)
+    return Workload("dgs16x16_N200_E50400", seq, grid, ph, 200)
+
+
+def slice64() -> Workload:
+    """64x64 smooth phantom, N = 1000, 391 x 399 x 81 = 12,636,729 entries, SNR 30."""
+    seq = I.make_sequence(1000, 1)
+    grid = I.make_grid(I.grid_arange(100, 4000, 10), I.grid_arange(10, 2000, 5),
+                       I.grid_arange(-40, 40, 1))
+    ph = I.phantom_smooth(64, 101, snr=30.0)
+    return Workload("slice64x64_N1000_E12636729", seq, grid, ph, 1000)
+
+
+def slice64_small_grid(n1: int = 60, n2: int = 60, n3: int = 81) -> Workload:
+    """The 64x64 slice against a coarser grid spanning the same ranges (tests)."""
+    w = slice64()
+    grid = I.make_grid(I.grid_linspace(100, 4000, n1), I.grid_linspace(10, 2000, n2),
+                       I.grid_linspace(-40, 40, n3))
+    return Workload(f"slice64x64_N1000_E{grid.size}", w.seq, grid, w.phantom, 1000)
+
+
+def volume(n_slices: int = 8, side: int = 256) -> Workload:
+    """8 slices of 256x256, N = 1000, 4 parameters incl. B1 (ZOOM only; the
+    3901 x 1991 x 241 x 121 grid is never materialised)."""
+    seq = I.make_sequence(1000, 300)
+    grid = I.make_grid(I.grid_arange(100, 4000, 1), I.grid_arange(10, 2000, 1),
+                       I.grid_arange(-60, 60, 0.5), I.grid_arange(0.7, 1.3, 0.005))
+    ph = I.phantom_volume(n_slices, side, 300, snr=25.0)
+    return Workload(f"volume{n_slices}x{side}x{side}_N1000_B1", seq, grid, ph, 1000)
+
+
+def serving_grid() -> I.Grid:
+    """Resident serving dictionaries: 196 x 200 x 41 = 1,607,200 entries."""
+    return I.make_grid(I.grid_arange(100, 4000, 20), I.grid_arange(10, 2000, 10),
+                       I.grid_arange(-40, 40, 2))
+
+
+def phantom_params(ph: I.Phantom) -> np.ndarray:
+    """[n_vox, 4] float64 truth parameters (T1, T2, df, B1)."""
+    return np.stack([ph.t1, ph.t2, ph.df, ph.b1], axis=1).astype(np.float64)

@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every symbol the header declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libmrf.h")
+LIB = os.path.join(ROOT, "paper_1506_05393_amd", "libmrf.so")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(mrf_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("mrf_simulate_dictionary", "mrf_match_bruteforce", "mrf_context_create",
+              "mrf_sequence_create", "mrf_grid_size", "mrf_last_error"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmrf.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmrf.so not built")
+def test_binding_declares_every_header_symbol():
+    from paper_1506_05393_amd import _lib
+    assert sorted(_lib.exported_names()) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmrf.so not built")
+def test_host_only_calls_without_gpu():
+    """Calls that touch no device: status strings and grid validation."""
+    import numpy as np
+    from paper_1506_05393_amd import _lib, api, inputs
+    lib = _lib.load()
+    assert lib.mrf_status_str(0) == b"ok"
+    assert lib.mrf_version().startswith(b"libmrf")
+    g = inputs.make_grid([100.0, 200.0, 300.0], [10.0, 20.0], [-4.0, 0.0, 4.0, 8.0])
+    assert lib.mrf_grid_size(api.GridArg(g).ptr) == 24
+    g4 = inputs.make_grid([100.0], [10.0], [0.0], [0.9, 1.0, 1.1])
+    assert lib.mrf_grid_size(api.GridArg(g4).ptr) == 3
+    bad = inputs.Grid(np.array([200.0, 100.0]), np.array([10.0]), np.array([0.0]))
+    assert lib.mrf_grid_size(api.GridArg(bad).ptr) == -1
+    assert b"strictly increasing" in lib.mrf_last_error()
+    neg = inputs.Grid(np.array([-1.0]), np.array([10.0]), np.array([0.0]))
+    assert lib.mrf_grid_size(api.GridArg(neg).ptr) == -1

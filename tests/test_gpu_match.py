@@ -1,0 +1,157 @@
+"""GPU parity of brute-force matching (K2 + K3 MFMA GEMM + K4) against the oracle.
+
+Bar: on voxels whose oracle top-2 CC margin exceeds 1e-5 the GPU returns the
+oracle's argmax index, and |CC| agrees within 1e-5 on every voxel.
+"""
+import numpy as np
+import pytest
+
+from paper_1506_05393_amd import inputs as I
+from tests.gpu_common import need_gpu, oracle_fingerprints, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+CC_TOL = 1e-5
+MARGIN = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    from paper_1506_05393_amd import api
+    return api.Context(0)
+
+
+def _check(res, ref, label):
+    idx = res["idx"].cpu().numpy()
+    cc = res["cc"].cpu().numpy().astype(np.float64)
+    pinned = ref["margin"] > MARGIN
+    agree = idx == ref["idx"]
+    print(f"{label}: pinned {pinned.sum()}/{len(idx)}, agreement pinned "
+          f"{agree[pinned].mean():.4f} all {agree.mean():.4f}, max |dCC| "
+          f"{np.abs(cc - ref['cc']).max():.2e}")
+    assert bool(np.all(agree[pinned])), np.flatnonzero(pinned & ~agree)[:10]
+    dcc = float(np.abs(cc - ref["cc"]).max())
+    assert dcc < CC_TOL, dcc
+    # where the indices differ the two entries are within the margin rule
+    gap = ref["cc"][~agree] - cc[~agree]
+    assert bool(np.all(gap <= MARGIN + CC_TOL)), float(gap.max())
+    return agree
+
+
+@pytest.mark.parametrize("on_grid", [True, False])
+def test_bruteforce_f32_small_workload(ctx, orc, on_grid):
+    from paper_1506_05393_amd import api, workloads
+    w = workloads.small_dgs(on_grid)
+    V = oracle_fingerprints(orc, w.seq, w.phantom)
+    ref = orc.bruteforce(w.seq, w.grid, V, top_k=4, threads=8)
+    sq = api.Sequence(ctx, w.seq)
+    d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+    res = api.match_bruteforce(ctx, d, to_dev(V), top_k=4, with_topk=True)
+    torch.cuda.synchronize()
+    _check(res, ref, f"small on_grid={on_grid}")
+    mg = res["margin"].cpu().numpy()
+    mg_err = float(np.abs(mg - ref["margin"]).max())
+    assert mg_err < 2 * CC_TOL, mg_err
+    pd = (res["pd_re"] + 1j * res["pd_im"]).cpu().numpy()
+    same = res["idx"].cpu().numpy() == ref["idx"]
+    pd_err = float(np.abs(pd - ref["pd"])[same].max())
+    assert pd_err < 1e-4 * float(np.abs(ref["pd"]).max()), pd_err
+    tk = res["topk_idx"].cpu().numpy()
+    assert np.all(tk[:, 0] == res["idx"].cpu().numpy())
+    tkc = res["topk_cc"].cpu().numpy()
+    assert bool(np.all(np.diff(tkc, axis=1) <= 0))
+    tk_err = float(np.abs(tkc - ref["topk_cc"]).max())
+    assert tk_err < CC_TOL, tk_err
+
+
+def test_bruteforce_ragged_shapes(ctx, orc):
+    """Voxel count, entry count and n_tr all off the tile sizes; zero voxel."""
+    from paper_1506_05393_amd import api
+    seq = I.make_sequence(57, 21)
+    grid = I.make_grid(I.grid_linspace(200, 2500, 7), I.grid_geomspace(15, 600, 5),
+                       I.grid_arange(-36, 36, 6))
+    ph = I.phantom_quadrants(grid, 6, 7, snr=15.0, on_grid=False)
+    V = oracle_fingerprints(orc, seq, ph)
+    V = np.concatenate([V[:36], np.zeros((1, 57), np.complex64)])
+    ref = orc.bruteforce(seq, grid, V, top_k=5)
+    sq = api.Sequence(ctx, seq)
+    d = api.simulate_dictionary(ctx, sq, grid, dtype="f32")
+    res = api.match_bruteforce(ctx, d, to_dev(V), top_k=5, with_topk=True)
+    torch.cuda.synchronize()
+    agree = _check(res, ref, "ragged")
+    # the zero voxel scores 0 everywhere: lowest index, CC 0
+    assert res["idx"][-1].item() == 0 and res["cc"][-1].item() == 0.0
+
+
+def test_bruteforce_prefix_view(ctx, orc):
+    """A view of the first n_tr readouts of a longer dictionary, with the
+    norms of that prefix."""
+    from paper_1506_05393_amd import api, workloads
+    w = workloads.small_dgs(False)
+    n_tr = 120
+    V = oracle_fingerprints(orc, w.seq, w.phantom, n_tr=n_tr)
+    ref = orc.bruteforce(w.seq, w.grid, V, n_tr=n_tr, threads=8)
+    sq = api.Sequence(ctx, w.seq)
+    d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+    pre = api.simulate_dictionary(ctx, sq, w.grid, n_tr=n_tr, dtype="f32")
+    d.norm = pre.norm  # prefix norms
+    res = api.match_bruteforce(ctx, d, to_dev(V), n_tr=n_tr)
+    torch.cuda.synchronize()
+    _check(res, ref, "prefix")
+
+
+def test_bruteforce_noise_free_on_grid_exact(ctx, orc):
+    from paper_1506_05393_amd import api, workloads
+    w = workloads.small_dgs(True)
+    V = oracle_fingerprints(orc, w.seq, w.phantom, noise=False)
+    sq = api.Sequence(ctx, w.seq)
+    d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+    res = api.match_bruteforce(ctx, d, to_dev(V))
+    ref = orc.bruteforce(w.seq, w.grid, V, threads=8)
+    pinned = ref["margin"] > MARGIN
+    assert np.all(res["idx"].cpu().numpy()[pinned] == w.phantom.truth_idx[pinned])
+    assert np.abs(res["cc"].cpu().numpy() - 1.0).max() < CC_TOL
+
+
+def test_invalid_match_arguments(ctx):
+    from paper_1506_05393_amd import api, _lib
+    seq = I.make_sequence(40, 1)
+    grid = I.make_grid([500.0, 900.0], [50.0], [0.0, 4.0])
+    sq = api.Sequence(ctx, seq)
+    d = api.simulate_dictionary(ctx, sq, grid)
+    v = torch.zeros((3, 40), dtype=torch.complex64, device="cuda")
+    with pytest.raises(_lib.MRFError, match="top_k"):
+        api.match_bruteforce(ctx, d, v, top_k=0)
+    with pytest.raises(_lib.MRFError, match="top_k"):
+        api.match_bruteforce(ctx, d, v, top_k=17)
+    with pytest.raises(_lib.MRFError, match="ld_vox"):
+        api.match_bruteforce(ctx, d, torch.zeros((3, 30), dtype=torch.complex64, device="cuda"))
+    ws = api.Workspace(ctx.device)
+    ws.buf = torch.empty(16, dtype=torch.uint8, device="cuda")
+    import ctypes as C
+    view = d.view()
+    r = api._result_tensors(3, ctx.device)
+    st = ctx._lib.mrf_match_bruteforce(ctx.handle, C.byref(view), v.data_ptr(), 3, 40, 1, None,
+                                       None, api._result_view(r), None, None, ws.buf.data_ptr(),
+                                       16, None)
+    assert st == 1 and b"workspace too small" in ctx._lib.mrf_last_error()
+
+
+def test_full_size_bruteforce_sampled(ctx, orc):
+    """64x64 slice, N = 1000, 12,636,729 entries (FP32, resident): all 4096
+    voxels on the GPU; 8 sampled voxels by the streaming oracle."""
+    from paper_1506_05393_amd import api, workloads
+    w = workloads.slice64()
+    sample = np.random.default_rng(5).choice(w.phantom.n_vox, 8, replace=False)
+    sample.sort()
+    V = oracle_fingerprints(orc, w.seq, w.phantom)
+    Vs = V[sample]
+    sq = api.Sequence(ctx, w.seq)
+    d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+    res = api.match_bruteforce(ctx, d, to_dev(V), top_k=2)
+    torch.cuda.synchronize()
+    ref = orc.bruteforce(w.seq, w.grid, Vs, top_k=2, threads=0)
+    sub = {k: v[sample] for k, v in res.items() if isinstance(v, torch.Tensor)}
+    _check(sub, ref, "full-size sample")
+    del d
+    torch.cuda.empty_cache()
