@@ -176,6 +176,17 @@ int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* dict, const void
                          int64_t* topk_idx, float* topk_cc, void* workspace,
                          size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing. When enabled, every launch of a named kernel
+ * ("k_sim_dict", "k_match_f32", "k_match_bf16", "k_rescore", "k_zoom", ...)
+ * is bracketed by HIP events recorded on the stream it is launched on.
+ * mrf_profile_read waits for those events and returns the summed elapsed
+ * time and launch count since the last reset (reset = 1 clears them).
+ * ---------------------------------------------------------------------- */
+int mrf_profile_enable(mrf_context* ctx, int32_t enable);
+int mrf_profile_read(mrf_context* ctx, const char* kernel, int32_t reset, double* total_ms,
+                     int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,9 @@ _SIGS = [
      [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
       C.POINTER(GridDesc), ResultView, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("mrf_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
+    ("mrf_profile_read", C.c_int,
+     [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 ]
 
 

@@ -37,6 +37,17 @@ class Context:
             self._lib.mrf_context_destroy(self.handle)
             self.handle = None
 
+    def profile(self, enable: bool = True):
+        L.check(self._lib.mrf_profile_enable(self.handle, int(bool(enable))))
+
+    def profile_read(self, kernel: str, reset: bool = True):
+        """(total ms, launches) of a named kernel since the last reset."""
+        ms = C.c_double()
+        n = C.c_int64()
+        L.check(self._lib.mrf_profile_read(self.handle, kernel.encode(), int(bool(reset)),
+                                           C.byref(ms), C.byref(n)))
+        return float(ms.value), int(n.value)
+
     def __del__(self):
         try:
             self.close()

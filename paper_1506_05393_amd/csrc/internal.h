@@ -53,7 +53,30 @@ struct mrf_context {
   int device = 0;
   int n_cu = 0;
   int warp = 64;
+  // kernel timing (mrf_profile_*)
+  bool prof_on = false;
+  std::mutex prof_mu;
+  struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof;
 };
+
+namespace mrf {
+// Brackets one kernel launch with events on `stream` when profiling is on.
+class ProfScope {
+ public:
+  ProfScope(mrf_context* ctx, const char* name, hipStream_t stream);
+  ~ProfScope();
+
+ private:
+  mrf_context* ctx_;
+  const char* name_;
+  hipStream_t stream_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+}  // namespace mrf
 
 struct mrf_sequence {
   mrf_context* ctx = nullptr;

@@ -469,8 +469,11 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   float* bs = (float*)(ws + p.off_bs);
   int32_t* bi = (int32_t*)(ws + p.off_bi);
 
-  hipLaunchKernelGGL(k_pack_f32, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox, ld_vox,
-                     n_vox, d->n_tr, p.n_tr_pad, p.m_pad, A, vn);
+  {
+    ProfScope prof(ctx, "k_pack_f32", st);
+    hipLaunchKernelGGL(k_pack_f32, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox, ld_vox,
+                       n_vox, d->n_tr, p.n_tr_pad, p.m_pad, A, vn);
+  }
   MRF_HIP(hipGetLastError());
 
   MatchArgs a;
@@ -499,7 +502,10 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_match_f32, dim3(grid_wg), dim3(256), lds, st, a);
+  {
+    ProfScope prof(ctx, "k_match_f32", st);
+    hipLaunchKernelGGL(k_match_f32, dim3(grid_wg), dim3(256), lds, st, a);
+  }
   MRF_HIP(hipGetLastError());
 
   MergeArgs m;
@@ -518,7 +524,10 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   m.margin = out.margin;
   m.topk_idx = topk_idx;
   m.topk_cc = topk_cc;
-  hipLaunchKernelGGL(k_merge, dim3((n_vox + 63) / 64), dim3(64), 0, st, m);
+  {
+    ProfScope prof(ctx, "k_merge", st);
+    hipLaunchKernelGGL(k_merge, dim3((n_vox + 63) / 64), dim3(64), 0, st, m);
+  }
   MRF_HIP(hipGetLastError());
   if (out.pd_re || out.pd_im) {
     hipLaunchKernelGGL(k_pd_f32, dim3(n_vox), dim3(64), 0, st, (const float2*)vox, ld_vox, n_vox,

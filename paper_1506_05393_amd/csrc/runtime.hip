@@ -263,11 +263,65 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   return MRF_OK;
 }
 
+ProfScope::ProfScope(mrf_context* ctx, const char* name, hipStream_t stream)
+    : ctx_(ctx), name_(name), stream_(stream) {
+  if (!ctx_ || !ctx_->prof_on) return;
+  if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
+    a_ = b_ = nullptr;
+    return;
+  }
+  (void)hipEventRecord(a_, stream_);
+}
+
+ProfScope::~ProfScope() {
+  if (!a_ || !b_) return;
+  (void)hipEventRecord(b_, stream_);
+  std::lock_guard<std::mutex> lock(ctx_->prof_mu);
+  ctx_->prof.push_back({name_, a_, b_});
+}
+
 }  // namespace mrf
 
 using namespace mrf;
 
 extern "C" {
+
+int mrf_profile_enable(mrf_context* ctx, int32_t enable) {
+  MRF_CHECK_ARG(ctx != nullptr, "context is NULL");
+  ctx->prof_on = enable != 0;
+  return MRF_OK;
+}
+
+int mrf_profile_read(mrf_context* ctx, const char* kernel, int32_t reset, double* total_ms,
+                     int64_t* launches) {
+  MRF_CHECK_ARG(ctx && kernel, "NULL argument");
+  std::lock_guard<std::mutex> lock(ctx->prof_mu);
+  double ms = 0.0;
+  int64_t n = 0;
+  for (auto& r : ctx->prof) {
+    if (r.name != kernel) continue;
+    MRF_HIP(hipEventSynchronize(r.b));
+    float t = 0.0f;
+    MRF_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++n;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (reset) {
+    std::vector<mrf_context::ProfRec> keep;
+    for (auto& r : ctx->prof) {
+      if (r.name == kernel) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    ctx->prof.swap(keep);
+  }
+  return MRF_OK;
+}
 
 const char* mrf_status_str(int s) {
   switch (s) {
@@ -309,6 +363,11 @@ int mrf_context_create(int device, mrf_context** out) {
 }
 
 int mrf_context_destroy(mrf_context* ctx) {
+  if (!ctx) return MRF_OK;
+  for (auto& r : ctx->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
   delete ctx;
   return MRF_OK;
 }

@@ -159,8 +159,9 @@ __global__ __launch_bounds__(256) void k_sim_signals(SigArgs a) {
   }
 }
 
-int launch_sim_dict(const Tables& t, int64_t k0, int64_t count, mrf_dtype dtype, void* re,
-                    void* im, int64_t ld, double* norm, int unit_norm, hipStream_t stream) {
+int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count,
+                    mrf_dtype dtype, void* re, void* im, int64_t ld, double* norm, int unit_norm,
+                    hipStream_t stream) {
   if (count == 0) return MRF_OK;
   SimArgs a;
   a.t1 = t.t1;
@@ -187,6 +188,7 @@ int launch_sim_dict(const Tables& t, int64_t k0, int64_t count, mrf_dtype dtype,
     set_error("too many entries in one call");
     return MRF_ERR_INVALID;
   }
+  ProfScope prof(ctx, "k_sim_dict", stream);
   if (dtype == MRF_F32)
     hipLaunchKernelGGL(k_sim_dict<1>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
   else
@@ -226,7 +228,7 @@ extern "C" int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq
   const Tables* t = nullptr;
   rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &t);
   if (rc) return rc;
-  return launch_sim_dict(*t, entry_begin, entry_count, dtype, re, im, ld, norm, unit_norm ? 1 : 0,
+  return launch_sim_dict(ctx, *t, entry_begin, entry_count, dtype, re, im, ld, norm, unit_norm ? 1 : 0,
                          (hipStream_t)stream);
 }
 
