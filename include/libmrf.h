@@ -177,6 +177,83 @@ int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* dict, const void
                          size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * MRF-ZOOM (Theory: MRF ZOOM; Methods: Experiment 2 zooming steps 1-5;
+ * Experiment 3 neighbour prior).
+ *
+ * A per-voxel search in grid-index space that simulates candidate entries on
+ * the fly (no stored dictionary) and maximises CC (Eq. 1). The schedule is a
+ * list of stages applied to the current centre c (index tuple over T1, T2,
+ * df, B1 = axes 0..3):
+ *   SCAN_STRIDE(axis, s)     : evaluate lo, lo+s, lo+2s, ... <= hi on the axis;
+ *                              the centre moves to the maximum (ties: lowest index)
+ *   SCAN_WINDOW(axis, s, w)  : evaluate c + m s, 0 < |m s| <= w; move to the
+ *                              maximum if it beats the centre (ties keep the centre,
+ *                              then the lowest index)
+ *   SCAN_HOPS(axis, hop)     : evaluate c + round_half_away(k hop), k != 0, in range
+ *                              (the +-k*omega hops of the df search); as WINDOW
+ *   ZOOM1(axis, s)           : hill climb: compare C with C-s, C+s, move to the
+ *                              strictly larger (ties: the lower side), repeat
+ *   ZOOM2(a0, a1, s0, s1)    : hill climb over the 8 neighbours in the order
+ *                              L, R, D, U, LD, LU, RD, RU (first maximum wins)
+ * With pruned = 1 the evaluation-saving move rules of the Theory section are
+ * used (R first in 1-D; L, D first in 2-D). Each start in starts[] runs the
+ * stage list, then the outer list is repeated (at most outer_max times) until
+ * the centre no longer changes; the best final CC wins (ties: lower index).
+ * Out-of-range points are skipped. Each distinct entry is simulated once per
+ * voxel (n_sim counts them).
+ * ---------------------------------------------------------------------- */
+enum {
+  MRF_SCAN_STRIDE = 0,
+  MRF_SCAN_WINDOW = 1,
+  MRF_SCAN_HOPS = 2,
+  MRF_ZOOM1 = 3,
+  MRF_ZOOM2 = 4
+};
+#define MRF_ZOOM_MAX_STAGES 32
+#define MRF_ZOOM_MAX_STARTS 16
+
+typedef struct {
+  int32_t kind, axis0, axis1, step0, step1, window;
+  double hop;
+} mrf_zoom_stage;
+
+typedef struct {
+  int32_t n_stages;
+  mrf_zoom_stage stages[MRF_ZOOM_MAX_STAGES];
+  int32_t n_outer;
+  mrf_zoom_stage outer[MRF_ZOOM_MAX_STAGES];
+  int32_t outer_max;
+  int32_t n_starts;
+  int32_t starts[MRF_ZOOM_MAX_STARTS][4];
+  int32_t pruned;
+  /* neighbour prior (Experiment 3): with init_idx given, each axis with
+   * prior_half[a] >= 0 is restricted to init +- prior_half[a] index steps */
+  int32_t prior_half[4];
+} mrf_zoom_schedule;
+
+/* The schedule of Methods, Experiment 2 (zooming steps 1-5) for `grid`, in
+ * index steps: physical steps r become max(1, round_half_away(r / step)) with
+ * step = (max - min)/(n - 1) per axis; omega = 1000 / min TR Hz; start at the
+ * grid values nearest to T1 = 1000 ms, T2 = 500 ms. With a B1 axis, B1 zooms
+ * at 0.1 ... 0.005 follow the interleaved 1-D zooms, and [2-D unit zoom, B1
+ * unit zoom, fine df scan] is repeated up to 3 times. */
+int mrf_zoom_schedule_paper(const mrf_grid* grid, const mrf_sequence* seq,
+                            mrf_zoom_schedule* out);
+
+int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_t n_vox, int32_t n_tr,
+                       size_t* bytes);
+
+/* vox: complex64 [n_vox][ld_vox] (first n_tr readouts used). init_idx:
+ * device int32 [n_vox][4] prior centres, or NULL (then the schedule's
+ * starts are used). Outputs (out): idx, cc, margin (= the smallest decision
+ * margin along the voxel's path: best minus runner-up CC among the values
+ * compared by one decision), pd_re/pd_im of the found entry, n_sim. */
+int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                    const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                    int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
+                    mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing. When enabled, every launch of a named kernel
  * ("k_sim_dict", "k_match_f32", "k_match_bf16", "k_rescore", "k_zoom", ...)
  * is bracketed by HIP events recorded on the stream it is launched on.

@@ -104,3 +104,32 @@ def check(status: int):
     if status != MRF_OK:
         msg = load().mrf_last_error().decode(errors="replace")
         raise MRFError(status, msg)
+
+
+ZOOM_MAX_STAGES, ZOOM_MAX_STARTS = 32, 16
+
+
+class ZoomStage(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("axis0", C.c_int32), ("axis1", C.c_int32),
+                ("step0", C.c_int32), ("step1", C.c_int32), ("window", C.c_int32),
+                ("hop", C.c_double)]
+
+
+class ZoomSchedule(C.Structure):
+    _fields_ = [("n_stages", C.c_int32), ("stages", ZoomStage * ZOOM_MAX_STAGES),
+                ("n_outer", C.c_int32), ("outer", ZoomStage * ZOOM_MAX_STAGES),
+                ("outer_max", C.c_int32), ("n_starts", C.c_int32),
+                ("starts", (C.c_int32 * 4) * ZOOM_MAX_STARTS), ("pruned", C.c_int32),
+                ("prior_half", C.c_int32 * 4)]
+
+
+_SIGS += [
+    ("mrf_zoom_schedule_paper", C.c_int,
+     [C.POINTER(GridDesc), C.c_void_p, C.POINTER(ZoomSchedule)]),
+    ("mrf_zoom_workspace", C.c_int,
+     [C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    ("mrf_zoom_search", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
+      C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
+]

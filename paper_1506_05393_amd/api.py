@@ -254,3 +254,77 @@ def match_bruteforce(ctx: Context, d: Dictionary, vox: torch.Tensor, top_k: int 
         tk_c.data_ptr() if tk_c is not None else None, buf.data_ptr(), buf.numel(),
         _stream_ptr(stream)))
     return r
+
+
+# ---------------------------------------------------------------- ZOOM -----
+
+STAGE_KINDS = {"scan_stride": 0, "scan_window": 1, "scan_hops": 2, "zoom1": 3, "zoom2": 4}
+
+
+def schedule_to_dict(s: "L.ZoomSchedule") -> dict:
+    st = lambda x: dict(kind=x.kind, axis0=x.axis0, axis1=x.axis1, step0=x.step0,
+                        step1=x.step1, window=x.window, hop=x.hop)
+    return dict(stages=[st(s.stages[i]) for i in range(s.n_stages)],
+                outer=[st(s.outer[i]) for i in range(s.n_outer)], outer_max=s.outer_max,
+                starts=[list(s.starts[i]) for i in range(s.n_starts)], pruned=s.pruned,
+                prior_half=list(s.prior_half))
+
+
+def schedule_from_dict(d: dict) -> "L.ZoomSchedule":
+    s = L.ZoomSchedule()
+    if len(d["stages"]) > L.ZOOM_MAX_STAGES or len(d.get("outer", [])) > L.ZOOM_MAX_STAGES:
+        raise ValueError("too many stages")
+    mk = lambda x: L.ZoomStage(x["kind"], x["axis0"], x.get("axis1", 0), x.get("step0", 0),
+                               x.get("step1", 0), x.get("window", 0), x.get("hop", 0.0))
+    s.n_stages = len(d["stages"])
+    for i, x in enumerate(d["stages"]):
+        s.stages[i] = mk(x)
+    s.n_outer = len(d.get("outer", []))
+    for i, x in enumerate(d.get("outer", [])):
+        s.outer[i] = mk(x)
+    s.outer_max = int(d.get("outer_max", 0))
+    starts = d.get("starts", [[0, 0, 0, 0]])
+    s.n_starts = len(starts)
+    for i, st in enumerate(starts):
+        for a in range(4):
+            s.starts[i][a] = int(st[a])
+    s.pruned = int(d.get("pruned", 0))
+    for a, h in enumerate(d.get("prior_half", [-1, -1, -1, -1])):
+        s.prior_half[a] = int(h)
+    return s
+
+
+def schedule_paper(ctx: Context, seq: Sequence, grid) -> dict:
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    s = L.ZoomSchedule()
+    L.check(ctx._lib.mrf_zoom_schedule_paper(g.ptr, seq.handle, C.byref(s)))
+    return schedule_to_dict(s)
+
+
+def zoom_search(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, sched: Optional[dict] = None,
+                n_tr: Optional[int] = None, init: Optional[torch.Tensor] = None,
+                workspace: Optional[Workspace] = None, out: Optional[dict] = None,
+                stream=None) -> dict:
+    """MRF-ZOOM per voxel. vox: complex64 cuda [n_vox, >= n_tr]; init: int32 cuda
+    [n_vox, 4] prior centres. Returns idx, cc, margin (min decision margin),
+    pd_re, pd_im, n_sim."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda or vox.stride(1) != 1:
+        raise ValueError("vox must be a complex64 CUDA tensor with contiguous rows")
+    n_tr = seq.n if n_tr is None else int(n_tr)
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    sd = schedule_paper(ctx, seq, g) if sched is None else sched
+    s = schedule_from_dict(sd)
+    n_vox = vox.shape[0]
+    nb = C.c_size_t()
+    L.check(ctx._lib.mrf_zoom_workspace(ctx.handle, g.ptr, n_vox, n_tr, C.byref(nb)))
+    ws = workspace if workspace is not None else Workspace(ctx.device)
+    buf = ws.get(int(nb.value))
+    r = out if out is not None else _result_tensors(n_vox, ctx.device, with_nsim=True)
+    if init is not None:
+        init = init.to(device=ctx.device, dtype=torch.int32).contiguous()
+        r["_init"] = init
+    L.check(ctx._lib.mrf_zoom_search(
+        ctx.handle, seq.handle, g.ptr, C.byref(s), vox.data_ptr(), n_vox, vox.stride(0), n_tr,
+        init.data_ptr() if init is not None else None, _result_view(r), buf.data_ptr(),
+        buf.numel(), _stream_ptr(stream)))
+    return r

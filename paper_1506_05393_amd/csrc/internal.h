@@ -44,6 +44,11 @@ struct Tables {
   float2* t2 = nullptr;   // [n_tr][n2]  (1-E2 over TE, 1-E2 over TR-TE)
   float4* df = nullptr;   // [n_tr][n3]  (cos-1, sin over TE, cos-1, sin over TR-TE)
   float* rf = nullptr;    // [n4][n_tr][9] pulse rotation matrix
+  // entry-major copies (one row per axis value) for kernels whose lanes walk
+  // different entries through the readouts (ZOOM, re-scoring)
+  float2* t1T = nullptr;  // [n1][n_tr]
+  float2* t2T = nullptr;  // [n2][n_tr]
+  float4* dfT = nullptr;  // [n3][n_tr]
   void* block = nullptr;  // one allocation holding all of the above
 };
 

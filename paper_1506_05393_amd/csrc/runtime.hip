@@ -90,6 +90,9 @@ struct K0Args {
   float2* t2;
   float4* df;
   float* rf;
+  float2* t1T;
+  float2* t2T;
+  float4* dfT;
 };
 
 __global__ void k_step_tables(K0Args a) {
@@ -103,8 +106,10 @@ __global__ void k_step_tables(K0Args a) {
     int64_t u = t;
     if (u < n_t1) {
       int j = (int)(u / a.n1), i = (int)(u % a.n1);
-      a.t1[u] = make_float2((float)one_minus_exp(a.ta[j], a.ax1[i]),
-                            (float)one_minus_exp(a.tb[j], a.ax1[i]));
+      const float2 f = make_float2((float)one_minus_exp(a.ta[j], a.ax1[i]),
+                                   (float)one_minus_exp(a.tb[j], a.ax1[i]));
+      a.t1[u] = f;
+      a.t1T[(int64_t)i * a.n_tr + j] = f;
       continue;
     }
     u -= n_t1;
@@ -115,8 +120,10 @@ __global__ void k_step_tables(K0Args a) {
     u -= a.n1;
     if (u < n_t2) {
       int j = (int)(u / a.n2), i = (int)(u % a.n2);
-      a.t2[u] = make_float2((float)one_minus_exp(a.ta[j], a.ax2[i]),
-                            (float)one_minus_exp(a.tb[j], a.ax2[i]));
+      const float2 f = make_float2((float)one_minus_exp(a.ta[j], a.ax2[i]),
+                                   (float)one_minus_exp(a.tb[j], a.ax2[i]));
+      a.t2[u] = f;
+      a.t2T[(int64_t)i * a.n_tr + j] = f;
       continue;
     }
     u -= n_t2;
@@ -126,6 +133,7 @@ __global__ void k_step_tables(K0Args a) {
       precession(a.ta[j], a.ax3[i], &f.x, &f.y);
       precession(a.tb[j], a.ax3[i], &f.z, &f.w);
       a.df[u] = f;
+      a.dfT[(int64_t)i * a.n_tr + j] = f;
       continue;
     }
     u -= n_df;
@@ -192,7 +200,10 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   size_t o_t2 = align256(o_ti + sizeof(float) * t.n1);
   size_t o_df = align256(o_t2 + sizeof(float2) * nt * t.n2);
   size_t o_rf = align256(o_df + sizeof(float4) * nt * t.n3);
-  size_t o_in = align256(o_rf + sizeof(float) * 9 * nt * t.n4);
+  size_t o_t1T = align256(o_rf + sizeof(float) * 9 * nt * t.n4);
+  size_t o_t2T = align256(o_t1T + sizeof(float2) * nt * t.n1);
+  size_t o_dfT = align256(o_t2T + sizeof(float2) * nt * t.n2);
+  size_t o_in = align256(o_dfT + sizeof(float4) * nt * t.n3);
   // staged FP64 inputs: ta, tb, fa, ph, ax1..ax4
   const size_t n_in = 4 * nt + t.n1 + t.n2 + t.n3 + t.n4;
   size_t total = o_in + sizeof(double) * n_in;
@@ -206,6 +217,9 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   t.t2 = (float2*)(base + o_t2);
   t.df = (float4*)(base + o_df);
   t.rf = (float*)(base + o_rf);
+  t.t1T = (float2*)(base + o_t1T);
+  t.t2T = (float2*)(base + o_t2T);
+  t.dfT = (float4*)(base + o_dfT);
   std::vector<double> in(n_in);
   double* p = in.data();
   for (int32_t j = 0; j < n_tr; ++j) {
@@ -242,6 +256,9 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
     a.t2 = t.t2;
     a.df = t.df;
     a.rf = t.rf;
+    a.t1T = t.t1T;
+    a.t2T = t.t2T;
+    a.dfT = t.dfT;
     int64_t work = (int64_t)nt * (t.n1 + t.n2 + t.n3 + t.n4) + t.n1;
     int blocks = (int)std::min<int64_t>((work + 255) / 256, 4096);
     hipLaunchKernelGGL(k_step_tables, dim3(blocks), dim3(256), 0, stream, a);

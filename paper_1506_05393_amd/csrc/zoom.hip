@@ -1,0 +1,828 @@
+// K6: MRF-ZOOM (Theory: MRF ZOOM; Methods: Experiment 2 zooming steps 1-5;
+// Experiment 3 neighbour prior) as a persistent kernel.
+//
+// One wavefront per voxel, pulled from an atomic queue so that voxels with
+// uneven numbers of evaluations balance across the machine. The stage machine
+// runs in wave-uniform control flow; each decision's candidate entries are
+// evaluated one per lane (rounds of 64), simulated on the fly with the same
+// step function as the dictionary kernel (bit-identical entries), with the
+// correlation against the unit-norm voxel accumulated inside the readout loop.
+// The unit-norm voxel lives in LDS; each wave owns a memo (entry -> CC, so
+// every distinct entry is simulated once per voxel) in global memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "bloch.h"
+#include "internal.h"
+
+namespace mrf {
+
+struct ZoomArgs {
+  const float2* t1T;
+  const float* t1ti;
+  const float2* t2T;
+  const float4* dfT;
+  const float* rf;
+  int32_t n_tr, inversion;
+  int32_t dims[4];
+  const float2* vox;
+  int64_t ld_vox;
+  int32_t n_vox;
+  const int32_t* init;
+  int64_t* idx;
+  float* cc;
+  float* margin;
+  float* pd_re;
+  float* pd_im;
+  int32_t* n_sim;
+  int32_t* counter;
+  int32_t memo_cap;  // slots per wave, power of two
+  int64_t* memo_keys;  // [grid blocks][memo_cap]
+  float* memo_vals;
+  const mrf_zoom_schedule* sch;  // device copy (workspace)
+};
+
+__device__ __forceinline__ int32_t round_half_away(double x) {
+  return (int32_t)(x >= 0.0 ? floor(x + 0.5) : -floor(-x + 0.5));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// (best, runner-up) of the values held by the lanes
+__device__ __forceinline__ void wave_top2(float v, float& b1, float& b2) {
+  float a1 = v, a2 = -INFINITY;
+  for (int o = 32; o > 0; o >>= 1) {
+    const float c1 = __shfl_xor(a1, o), c2 = __shfl_xor(a2, o);
+    const float n1 = fmaxf(a1, c1);
+    const float n2 = fmaxf(fminf(a1, c1), fmaxf(a2, c2));
+    a1 = n1;
+    a2 = n2;
+  }
+  b1 = a1;
+  b2 = a2;
+}
+
+// first lane holding the maximum (ties: lowest lane); -1 if all are -inf
+__device__ __forceinline__ int wave_first_max(float v, float& best) {
+  best = wave_max(v);
+  if (!(best > -INFINITY)) return -1;
+  const uint64_t m = __ballot(v == best);
+  return __ffsll((unsigned long long)m) - 1;
+}
+
+// The fields of ZoomArgs the engine needs, copied into registers (taking the
+// address of the kernel argument block would force a private-memory copy).
+struct EngineParams {
+  const float2* t1T;
+  const float* t1ti;
+  const float2* t2T;
+  const float4* dfT;
+  const float* rf;
+  int32_t n_tr, inversion, memo_cap;
+  int32_t dims[4];
+};
+
+struct Engine {
+  EngineParams pa;
+
+  static constexpr int64_t kIndexMask = ((int64_t)1 << 40) - 1;
+  const float2* vs;  // unit-norm voxel in LDS
+  int64_t* mkey;     // this wave's memo (global memory)
+  float* mval;
+  int64_t tag;       // voxel serial << 40
+  float* nbv;  // [8] neighbour values of one pruned move (LDS)
+  int32_t lane;
+  int32_t memo_count;
+  int32_t n_sim;
+  bool overflow;
+  int32_t lo[4], hi[4];
+  int32_t c[4];
+  float cval;
+  bool cknown;
+  float mm;  // smallest decision margin
+
+  __device__ int64_t key(const int32_t* i) const {
+    return (((int64_t)i[0] * pa.dims[1] + i[1]) * pa.dims[2] + i[2]) * pa.dims[3] + i[3];
+  }
+  __device__ bool in_range(const int32_t* i) const {
+    for (int q = 0; q < 4; ++q)
+      if (i[q] < lo[q] || i[q] > hi[q]) return false;
+    return true;
+  }
+
+  // CC of this lane's entry against the voxel (Eq. 1 with a unit-norm voxel)
+  __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
+                               double* pn2 = nullptr) const {
+    const int32_t n = pa.n_tr;
+    const float2* p1 = pa.t1T + (int64_t)i[0] * n;
+    const float2* p2 = pa.t2T + (int64_t)i[1] * n;
+    const float4* pd = pa.dfT + (int64_t)i[2] * n;
+    const float* R = pa.rf + (int64_t)i[3] * n * 9;
+    Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
+    float dr = 0.0f, di = 0.0f;
+    double n2 = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+      const float2 r1 = p1[j];
+      const float2 r2 = p2[j];
+      const float4 pc = pd[j];
+      rf_pulse(m, R + 9 * j);
+      free_evolve(m, pc.x, pc.y, r2.x, r1.x);
+      const float2 v = vs[j];
+      // v conj(d): (vr + i vi)(x - i y)
+      dr = fmaf(v.x, m.x, fmaf(v.y, m.y, dr));
+      di = fmaf(v.y, m.x, fmaf(-v.x, m.y, di));
+      n2 = fma((double)m.x, (double)m.x, n2);
+      n2 = fma((double)m.y, (double)m.y, n2);
+      free_evolve(m, pc.z, pc.w, r2.y, r1.y);
+    }
+    if (pdr) *pdr = dr;
+    if (pdi) *pdi = di;
+    if (pn2) *pn2 = n2;
+    if (!(n2 > 0.0)) return 0.0f;
+    return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
+  }
+
+  // Memo: this wave's private open-addressing table in global memory. A slot
+  // holds (voxel serial << 40 | entry index); slots of earlier voxels count
+  // as empty, so the table is never cleared between voxels. Loads and stores
+  // are device-coherent (they bypass the non-coherent L1).
+  __device__ uint32_t memo_home(int64_t k) const {
+    return (uint32_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(pa.memo_cap - 1);
+  }
+  __device__ int64_t memo_ld_key(uint32_t s) const {
+    return __hip_atomic_load(mkey + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  // Wave-level evaluation: every lane with `valid` asks for the value at i.
+  __device__ float eval(bool valid, const int32_t* i) {
+    float val = -INFINITY;
+    bool need = false;
+    int64_t k = -1;
+    const int32_t cap = pa.memo_cap;
+    if (valid && in_range(i)) {
+      k = key(i);
+      const int64_t tagged = tag | k;
+      uint32_t s = memo_home(k);
+      need = true;
+      for (int32_t probe = 0; probe < cap; ++probe) {
+        const int64_t mk = memo_ld_key(s);
+        if (mk == tagged) {
+          val = __hip_atomic_load(mval + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          need = false;
+          break;
+        }
+        if ((mk & ~kIndexMask) != tag) break;  // empty for this voxel
+        s = (s + 1) & (cap - 1);
+      }
+    }
+    if (need) val = simulate_cc(i);
+    uint64_t m = __ballot(need);
+    n_sim += __popcll(m);
+    while (m) {
+      const int src = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int64_t ks = __shfl(k, src);
+      const float vv = __shfl(val, src);
+      if (memo_count * 4 < cap * 3) {
+        if (lane == 0) {
+          uint32_t s = memo_home(ks);
+          while ((memo_ld_key(s) & ~kIndexMask) == tag) s = (s + 1) & (cap - 1);
+          __hip_atomic_store(mval + s, vv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(mkey + s, tag | ks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++memo_count;
+      } else {
+        overflow = true;
+      }
+    }
+    __syncthreads();  // one wave per block: the memo stores complete before later loads
+    return val;
+  }
+
+  __device__ void need_centre() {
+    if (!cknown) {
+      const float v = eval(lane == 0, c);
+      cval = __shfl(v, 0);
+      cknown = true;
+    }
+  }
+
+  __device__ void log_top2(float v, bool include_centre) {
+    float b1, b2;
+    wave_top2(v, b1, b2);
+    const int nf = __popcll(__ballot(v > -INFINITY));
+    if (include_centre) {
+      const float c1 = cval;
+      const float n1 = fmaxf(b1, c1);
+      const float n2 = fmaxf(fminf(b1, c1), b2);
+      b1 = n1;
+      b2 = n2;
+    }
+    if (nf + (include_centre ? 1 : 0) >= 2) mm = fminf(mm, b1 - b2);
+  }
+  __device__ void log_pair(float x, float y) {
+    if (x > -INFINITY && y > -INFINITY) mm = fminf(mm, fabsf(x - y));
+  }
+
+  // ---- stages --------------------------------------------------------------
+  __device__ void scan_stride(int ax, int s) {
+    s = s > 0 ? s : 1;
+    const int32_t count = (hi[ax] - lo[ax]) / s + 1;
+    float best = -INFINITY, r1 = -INFINITY, r2 = -INFINITY;
+    int32_t bp = c[ax];
+    int nf = 0;
+    for (int32_t base = 0; base < count; base += 64) {
+      const int32_t q = base + lane;
+      int32_t p[4] = {c[0], c[1], c[2], c[3]};
+      p[ax] = lo[ax] + q * s;
+      const float v = eval(q < count, p);
+      float rb;
+      const int src = wave_first_max(v, rb);
+      if (src >= 0 && rb > best) {  // earlier rounds hold lower indices: keep them on ties
+        best = rb;
+        bp = __shfl(p[ax], src);
+      }
+      float t1, t2;
+      wave_top2(v, t1, t2);
+      const float n1 = fmaxf(r1, t1), n2 = fmaxf(fminf(r1, t1), fmaxf(r2, t2));
+      r1 = n1;
+      r2 = n2;
+      nf += __popcll(__ballot(v > -INFINITY));
+    }
+    if (nf >= 2) mm = fminf(mm, r1 - r2);
+    if (best > -INFINITY) {
+      c[ax] = bp;
+      cval = best;
+      cknown = true;
+    }
+  }
+
+  // points given by a per-lane generator, in increasing index order; the
+  // centre is kept on ties, then the lowest index wins
+  template <typename Gen>
+  __device__ void scan_points(int ax, int32_t count, Gen gen) {
+    need_centre();
+    float best = cval, r1 = cval, r2 = -INFINITY;
+    int32_t bp = c[ax];
+    int nf = 1;
+    for (int32_t base = 0; base < count; base += 64) {
+      const int32_t q = base + lane;
+      int32_t p[4] = {c[0], c[1], c[2], c[3]};
+      p[ax] = q < count ? gen(q) : c[ax];
+      const float v = eval(q < count, p);
+      float rb;
+      const int src = wave_first_max(v, rb);
+      if (src >= 0 && rb > best) {
+        best = rb;
+        bp = __shfl(p[ax], src);
+      }
+      float t1, t2;
+      wave_top2(v, t1, t2);
+      const float n1 = fmaxf(r1, t1), n2 = fmaxf(fminf(r1, t1), fmaxf(r2, t2));
+      r1 = n1;
+      r2 = n2;
+      nf += __popcll(__ballot(v > -INFINITY));
+    }
+    if (nf >= 2) mm = fminf(mm, r1 - r2);
+    c[ax] = bp;
+    cval = best;
+  }
+
+  __device__ void scan_window(int ax, int s, int w) {
+    s = s > 0 ? s : 1;
+    const int32_t M = w / s;
+    const int32_t cc0 = c[ax];
+    // m in [m_lo, m_hi] \ {0} with lo <= c + m s <= hi
+    int32_t m_lo = -M, m_hi = M;
+    while (m_lo < 0 && cc0 + m_lo * s < lo[ax]) ++m_lo;
+    while (m_hi > 0 && cc0 + m_hi * s > hi[ax]) --m_hi;
+    const bool has0 = m_lo <= 0 && m_hi >= 0;
+    const int32_t count = (m_hi - m_lo + 1) - (has0 ? 1 : 0);
+    scan_points(ax, count, [&](int32_t q) {
+      int32_t m = m_lo + q;
+      if (has0 && m >= 0) m += 1;
+      return cc0 + m * s;
+    });
+  }
+
+  __device__ void scan_hops(int ax, double h) {
+    h = h >= 1.0 ? h : 1.0;
+    const int32_t cc0 = c[ax];
+    int32_t nneg = 0, npos = 0;
+    while (cc0 + round_half_away(-(double)(nneg + 1) * h) >= lo[ax]) ++nneg;
+    while (cc0 + round_half_away((double)(npos + 1) * h) <= hi[ax]) ++npos;
+    scan_points(ax, nneg + npos, [&](int32_t q) {
+      if (q < nneg) return cc0 + round_half_away(-(double)(nneg - q) * h);
+      return cc0 + round_half_away((double)(q - nneg + 1) * h);
+    });
+  }
+
+  __device__ void move_to(const int32_t* p, float v) {
+    for (int q = 0; q < 4; ++q) c[q] = p[q];
+    cval = v;
+  }
+
+  __device__ void zoom1(int ax, int s, bool pruned) {
+    s = s > 0 ? s : 1;
+    need_centre();
+    for (int guard = 0; guard < (1 << 20); ++guard) {
+      int32_t L[4] = {c[0], c[1], c[2], c[3]}, R[4] = {c[0], c[1], c[2], c[3]};
+      L[ax] -= s;
+      R[ax] += s;
+      if (pruned) {
+        const float vr = __shfl(eval(lane == 0, R), 0);
+        log_pair(vr, cval);
+        if (vr > cval) {
+          move_to(R, vr);
+          continue;
+        }
+        const float vl = __shfl(eval(lane == 0, L), 0);
+        log_pair(vl, cval);
+        if (vl > cval) {
+          move_to(L, vl);
+          continue;
+        }
+        break;
+      }
+      const int32_t* P = lane == 0 ? L : R;
+      const float v = eval(lane < 2, P);
+      log_top2(lane < 2 ? v : -INFINITY, true);
+      const float vl = __shfl(v, 0), vr = __shfl(v, 1);
+      const bool right = vr > vl;
+      const float bv = right ? vr : vl;
+      if (bv > cval)
+        move_to(right ? R : L, bv);
+      else
+        break;
+    }
+  }
+
+  // offsets of neighbour w in the order L, R, D, U, LD, LU, RD, RU
+  __device__ static int nb_d0(int w) { return (w == 0 || w == 4 || w == 5) ? -1 : ((w == 1 || w >= 6) ? 1 : 0); }
+  __device__ static int nb_d1(int w) { return (w == 2 || w == 4 || w == 6) ? -1 : ((w == 3 || w == 5 || w == 7) ? 1 : 0); }
+  __device__ void neighbour(int w, int a0, int a1, int s0, int s1, int32_t* p) const {
+    for (int q = 0; q < 4; ++q) p[q] = c[q] + (q == a0 ? nb_d0(w) * s0 : 0) + (q == a1 ? nb_d1(w) * s1 : 0);
+  }
+
+  // evaluate the neighbours in `mask` (bit w = neighbour w), one per lane
+  __device__ void eval_nb(uint32_t mask, int a0, int a1, int s0, int s1) {
+    int32_t p[4];
+    neighbour(lane & 7, a0, a1, s0, s1, p);
+    const bool mine = lane < 8 && ((mask >> lane) & 1u);
+    const float v = eval(mine, p);
+    if (mine) nbv[lane] = v;
+    __syncthreads();
+  }
+
+  __device__ void zoom2(int a0, int a1, int s0, int s1, bool pruned) {
+    s0 = s0 > 0 ? s0 : 1;
+    s1 = s1 > 0 ? s1 : 1;
+    need_centre();
+    enum { NL = 0, NR, ND, NU, NLD, NLU, NRD, NRU };
+    for (int guard = 0; guard < (1 << 20); ++guard) {
+      if (!pruned) {
+        int32_t p[4];
+        neighbour(lane & 7, a0, a1, s0, s1, p);
+        const float v = eval(lane < 8, p);
+        log_top2(lane < 8 ? v : -INFINITY, true);
+        float bv;
+        const int src = wave_first_max(lane < 8 ? v : -INFINITY, bv);
+        if (src >= 0 && bv > cval) {
+          int32_t q[4];
+          neighbour(src, a0, a1, s0, s1, q);
+          move_to(q, bv);
+        } else {
+          break;
+        }
+        continue;
+      }
+      // evaluation-saving rules (Theory section)
+      float* v = nbv;
+      if (lane < 8) v[lane] = -INFINITY;
+      __syncthreads();
+      const float C = cval;
+      eval_nb((1u << NL) | (1u << ND), a0, a1, s0, s1);
+      log_pair(v[NL], C);
+      log_pair(v[ND], C);
+      const bool upL = v[NL] > C, upD = v[ND] > C;
+      int target = -1;
+      uint32_t cand = 0;
+      if (upL && upD) {
+        cand = (1u << NL) | (1u << ND);
+        eval_nb(1u << NLD, a0, a1, s0, s1);
+        log_pair(v[NLD], C);
+        if (v[NLD] > C) target = NLD;
+      } else if (!upL && !upD) {
+        eval_nb((1u << NR) | (1u << NU), a0, a1, s0, s1);
+        log_pair(v[NR], C);
+        log_pair(v[NU], C);
+        const bool upR = v[NR] > C, upU = v[NU] > C;
+        if (!upR && !upU) break;
+        if (upR && upU) {
+          cand = (1u << NR) | (1u << NU);
+          eval_nb(1u << NRU, a0, a1, s0, s1);
+          log_pair(v[NRU], C);
+          if (v[NRU] > C) target = NRU;
+        } else {
+          target = upR ? NR : NU;
+        }
+      } else if (upL) {
+        cand = 1u << NL;
+        eval_nb(1u << NU, a0, a1, s0, s1);
+        log_pair(v[NU], C);
+        if (v[NU] > C) {
+          cand |= 1u << NU;
+          eval_nb(1u << NLU, a0, a1, s0, s1);
+          log_pair(v[NLU], C);
+          if (v[NLU] > C) target = NLU;
+        } else {
+          target = NL;
+        }
+      } else {
+        cand = 1u << ND;
+        eval_nb(1u << NR, a0, a1, s0, s1);
+        log_pair(v[NR], C);
+        if (v[NR] > C) {
+          cand |= 1u << NR;
+          eval_nb(1u << NRD, a0, a1, s0, s1);
+          log_pair(v[NRD], C);
+          if (v[NRD] > C) target = NRD;
+        } else {
+          target = ND;
+        }
+      }
+      if (target < 0) {
+        float bv = -INFINITY;
+        for (int w = 0; w < 8; ++w)
+          if (((cand >> w) & 1u) && v[w] > bv) {
+            bv = v[w];
+            target = w;
+          }
+        if (target < 0 || !(bv > C)) break;
+      }
+      int32_t q[4];
+      neighbour(target, a0, a1, s0, s1, q);
+      move_to(q, v[target]);
+    }
+  }
+
+  __device__ void run_stage(const mrf_zoom_stage& st, bool pruned) {
+    switch (st.kind) {
+      case MRF_SCAN_STRIDE: scan_stride(st.axis0, st.step0); break;
+      case MRF_SCAN_WINDOW: scan_window(st.axis0, st.step0, st.window); break;
+      case MRF_SCAN_HOPS: scan_hops(st.axis0, st.hop); break;
+      case MRF_ZOOM1: zoom1(st.axis0, st.step0, pruned); break;
+      case MRF_ZOOM2: zoom2(st.axis0, st.axis1, st.step0, st.step1, pruned); break;
+      default: break;
+    }
+  }
+};
+
+// Resets the work counter and stores the schedule (passed by value, so it is
+// captured at launch) where the search kernel reads it.
+__global__ void k_zoom_init(int32_t* counter, mrf_zoom_schedule sch, mrf_zoom_schedule* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *counter = 0;
+    *dst = sch;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int32_t n = a.n_tr;
+  float2* vs = (float2*)sm;
+  int64_t* fin_k = (int64_t*)(sm + ((size_t)n * sizeof(float2) + 15) / 16 * 16);  // [MAX_STARTS]
+  float* fin_v = (float*)(fin_k + MRF_ZOOM_MAX_STARTS);                            // [MAX_STARTS]
+  float* nbv = fin_v + MRF_ZOOM_MAX_STARTS;                                       // [8]
+  const int lane = threadIdx.x;
+  const mrf_zoom_schedule* __restrict__ S = a.sch;
+  // this wave's memo; serial 0 marks never-used slots
+  int64_t* mkey = a.memo_keys + (int64_t)blockIdx.x * a.memo_cap;
+  float* mval = a.memo_vals + (int64_t)blockIdx.x * a.memo_cap;
+  for (int32_t i = lane; i < a.memo_cap; i += 64)
+    __hip_atomic_store(mkey + i, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  int64_t serial = 0;
+
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    v = __shfl(v, 0);
+    if (v >= a.n_vox) break;
+
+    // unit-norm voxel (norm in FP64) into LDS
+    const float2* src = a.vox + (int64_t)v * a.ld_vox;
+    double s2 = 0.0;
+    for (int32_t j = lane; j < n; j += 64) {
+      const float2 x = src[j];
+      s2 = fma((double)x.x, (double)x.x, s2);
+      s2 = fma((double)x.y, (double)x.y, s2);
+    }
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    const double nv = sqrt(s2);
+    const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
+    for (int32_t j = lane; j < n; j += 64) {
+      const float2 x = src[j];
+      vs[j] = make_float2(x.x * inv, x.y * inv);
+    }
+    ++serial;
+    __syncthreads();
+
+    Engine e;
+    e.pa.t1T = a.t1T;
+    e.pa.t1ti = a.t1ti;
+    e.pa.t2T = a.t2T;
+    e.pa.dfT = a.dfT;
+    e.pa.rf = a.rf;
+    e.pa.n_tr = a.n_tr;
+    e.pa.inversion = a.inversion;
+    e.pa.memo_cap = a.memo_cap;
+    for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
+
+    e.vs = vs;
+    e.mkey = mkey;
+    e.mval = mval;
+    e.tag = serial << 40;
+    e.nbv = nbv;
+    e.lane = lane;
+    e.memo_count = 0;
+    e.n_sim = 0;
+    e.overflow = false;
+    e.mm = INFINITY;
+    const int32_t* init = a.init ? a.init + 4 * (int64_t)v : nullptr;
+    for (int q = 0; q < 4; ++q) {
+      e.lo[q] = 0;
+      e.hi[q] = a.dims[q] - 1;
+      if (init && S->prior_half[q] >= 0) {
+        e.lo[q] = max(0, init[q] - S->prior_half[q]);
+        e.hi[q] = min(a.dims[q] - 1, init[q] + S->prior_half[q]);
+      }
+    }
+    const int n_starts = init ? 1 : S->n_starts;
+    float bv = -INFINITY;
+    int64_t bk = INT64_MAX;
+    int32_t bi[4] = {0, 0, 0, 0};
+    for (int st = 0; st < n_starts; ++st) {
+      const int32_t* s0 = init ? init : S->starts[st];
+      for (int q = 0; q < 4; ++q) e.c[q] = min(max(s0[q], e.lo[q]), e.hi[q]);
+      e.cknown = false;
+      for (int i = 0; i < S->n_stages; ++i) e.run_stage(S->stages[i], S->pruned != 0);
+      for (int r = 0; r < S->outer_max && S->n_outer > 0; ++r) {
+        const int32_t b0 = e.c[0], b1 = e.c[1], b2 = e.c[2], b3 = e.c[3];
+        for (int i = 0; i < S->n_outer; ++i) e.run_stage(S->outer[i], S->pruned != 0);
+        if (b0 == e.c[0] && b1 == e.c[1] && b2 == e.c[2] && b3 == e.c[3]) break;
+      }
+      e.need_centre();
+      const int64_t k = e.key(e.c);
+      if (lane == 0) {
+        fin_v[st] = e.cval;
+        fin_k[st] = k;
+      }
+      if (e.cval > bv || (e.cval == bv && k < bk)) {
+        bv = e.cval;
+        bk = k;
+        for (int q = 0; q < 4; ++q) bi[q] = e.c[q];
+      }
+    }
+    __syncthreads();
+    for (int st = 0; st < n_starts; ++st)
+      if (fin_k[st] != bk) e.log_pair(bv, fin_v[st]);
+
+    // proton density of the found entry: <v, d> / ||d||^2
+    float dr = 0.0f, di = 0.0f;
+    double n2 = 0.0;
+    if (lane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
+    if (lane == 0) {
+      a.idx[v] = bk;
+      if (a.cc) a.cc[v] = bv;
+      if (a.margin) a.margin[v] = e.mm;
+      if (a.n_sim) a.n_sim[v] = e.overflow ? -e.n_sim : e.n_sim;
+      if (a.pd_re) a.pd_re[v] = n2 > 0.0 ? (float)(nv * (double)dr / n2) : 0.0f;
+      if (a.pd_im) a.pd_im[v] = n2 > 0.0 ? (float)(nv * (double)di / n2) : 0.0f;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int32_t h_round_half_away(double x) {
+  return (int32_t)(x >= 0.0 ? std::floor(x + 0.5) : -std::floor(-x + 0.5));
+}
+
+static int32_t h_idx_step(double r, const mrf_axis& ax) {
+  if (ax.n < 2) return 1;
+  const double d = (ax.v[ax.n - 1] - ax.v[0]) / (double)(ax.n - 1);
+  return std::max(1, h_round_half_away(r / d));
+}
+
+static int32_t h_nearest(const mrf_axis& ax, double v) {
+  int32_t b = 0;
+  for (int32_t i = 1; i < ax.n; ++i)
+    if (std::fabs(ax.v[i] - v) < std::fabs(ax.v[b] - v)) b = i;
+  return b;
+}
+
+static mrf_zoom_stage stage(int32_t kind, int32_t a0, int32_t a1, int32_t s0, int32_t s1,
+                            int32_t w, double hop) {
+  mrf_zoom_stage s;
+  s.kind = kind;
+  s.axis0 = a0;
+  s.axis1 = a1;
+  s.step0 = s0;
+  s.step1 = s1;
+  s.window = w;
+  s.hop = hop;
+  return s;
+}
+
+// Launch plan: LDS per wave, persistent grid size and workspace layout
+// (work counter | schedule copy | memo keys | memo values).
+struct ZoomPlan {
+  size_t lds;
+  int blocks;
+  int32_t cap;
+  size_t off_sched, off_keys, off_vals, total;
+};
+
+static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_entries) {
+  ZoomPlan p;
+  // memo slots per wave: fine 4-parameter grids make long unit-step walks
+  p.cap = grid_entries > ((int64_t)1 << 26) ? 32768 : 4096;
+  p.lds = ((size_t)n_tr * sizeof(float2) + 15) / 16 * 16 +
+          MRF_ZOOM_MAX_STARTS * (sizeof(float) + sizeof(int64_t)) + 8 * sizeof(float) + 16;
+  const int per_cu = std::max(1, std::min(16, (int)((160 * 1024) / p.lds)));
+  p.blocks = std::max(1, std::min(n_vox, n_cu * per_cu));
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  p.off_sched = 256;
+  p.off_keys = al(p.off_sched + sizeof(mrf_zoom_schedule));
+  p.off_vals = al(p.off_keys + sizeof(int64_t) * (size_t)p.blocks * p.cap);
+  p.total = al(p.off_vals + sizeof(float) * (size_t)p.blocks * p.cap);
+  return p;
+}
+
+}  // namespace mrf
+
+using namespace mrf;
+
+extern "C" int mrf_zoom_schedule_paper(const mrf_grid* g, const mrf_sequence* seq,
+                                       mrf_zoom_schedule* o) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  MRF_CHECK_ARG(seq && o, "NULL argument");
+  *o = mrf_zoom_schedule();
+  const double omega = seq->omega_hz;  // 1000 / min TR
+  const mrf_axis &T1 = g->t1_ms, &T2 = g->t2_ms, &DF = g->df_hz;
+  const double ddf = DF.n > 1 ? (DF.v[DF.n - 1] - DF.v[0]) / (double)(DF.n - 1) : 1.0;
+  int k = 0;
+  // step 1: df at the starting T1/T2 (scan, narrow window, +-k omega hops)
+  o->stages[k++] = stage(MRF_SCAN_STRIDE, 2, 0, h_idx_step(60.0, DF), 0, 0, 0.0);
+  o->stages[k++] = stage(MRF_SCAN_WINDOW, 2, 0, h_idx_step(3.0, DF), 0, h_idx_step(75.0, DF), 0.0);
+  const double hop = omega / ddf;
+  o->stages[k++] = stage(MRF_SCAN_HOPS, 2, 0, 0, 0, 0, hop < 1.0 ? 1.0 : hop);
+  // step 2: 2-D zoom at 200 then 100 ms
+  o->stages[k++] = stage(MRF_ZOOM2, 0, 1, h_idx_step(200.0, T1), h_idx_step(200.0, T2), 0, 0.0);
+  o->stages[k++] = stage(MRF_ZOOM2, 0, 1, h_idx_step(100.0, T1), h_idx_step(100.0, T2), 0, 0.0);
+  // step 3: unit-step df scan over +-omega/2
+  o->stages[k++] = stage(MRF_SCAN_WINDOW, 2, 0, 1, 0, h_idx_step(0.5 * omega, DF), 0.0);
+  // step 4: interleaved 1-D zooms
+  o->stages[k++] = stage(MRF_ZOOM1, 0, 0, h_idx_step(100.0, T1), 0, 0, 0.0);
+  o->stages[k++] = stage(MRF_ZOOM1, 1, 0, h_idx_step(100.0, T2), 0, 0, 0.0);
+  const double fine[3] = {50.0, 20.0, 10.0};
+  for (double r : fine) o->stages[k++] = stage(MRF_ZOOM1, 0, 0, h_idx_step(r, T1), 0, 0, 0.0);
+  for (double r : fine) o->stages[k++] = stage(MRF_ZOOM1, 1, 0, h_idx_step(r, T2), 0, 0, 0.0);
+  if (g->b1.n > 1) {
+    const double b1s[5] = {0.1, 0.05, 0.02, 0.01, 0.005};
+    for (double r : b1s) o->stages[k++] = stage(MRF_ZOOM1, 3, 0, h_idx_step(r, g->b1), 0, 0, 0.0);
+  }
+  // step 5: final 2-D zoom at the finest resolution
+  o->stages[k++] = stage(MRF_ZOOM2, 0, 1, 1, 1, 0, 0.0);
+  o->n_stages = k;
+  if (g->b1.n > 1) {
+    o->outer[0] = stage(MRF_ZOOM2, 0, 1, 1, 1, 0, 0.0);
+    o->outer[1] = stage(MRF_ZOOM1, 3, 0, 1, 0, 0, 0.0);
+    o->outer[2] = stage(MRF_SCAN_WINDOW, 2, 0, 1, 0, h_idx_step(0.5 * omega, DF), 0.0);
+    o->n_outer = 3;
+    o->outer_max = 3;
+  }
+  o->n_starts = 1;
+  o->starts[0][0] = h_nearest(T1, 1000.0);
+  o->starts[0][1] = h_nearest(T2, 500.0);
+  o->starts[0][2] = 0;
+  o->starts[0][3] = g->b1.n > 1 ? h_nearest(g->b1, 1.0) : 0;
+  o->pruned = 0;
+  for (int a = 0; a < 4; ++a) o->prior_half[a] = -1;
+  return MRF_OK;
+}
+
+static int check_schedule(const mrf_zoom_schedule* s, const int32_t* dims) {
+  MRF_CHECK_ARG(s != nullptr, "schedule is NULL");
+  MRF_CHECK_ARG(s->n_stages >= 0 && s->n_stages <= MRF_ZOOM_MAX_STAGES, "bad n_stages");
+  MRF_CHECK_ARG(s->n_outer >= 0 && s->n_outer <= MRF_ZOOM_MAX_STAGES, "bad n_outer");
+  MRF_CHECK_ARG(s->outer_max >= 0 && s->outer_max <= 64, "outer_max must be in [0, 64]");
+  MRF_CHECK_ARG(s->n_starts >= 1 && s->n_starts <= MRF_ZOOM_MAX_STARTS, "bad n_starts");
+  for (int l = 0; l < 2; ++l) {
+    const mrf_zoom_stage* st = l ? s->outer : s->stages;
+    const int n = l ? s->n_outer : s->n_stages;
+    for (int i = 0; i < n; ++i) {
+      MRF_CHECK_ARG(st[i].kind >= MRF_SCAN_STRIDE && st[i].kind <= MRF_ZOOM2,
+                    "stage %d: unknown kind %d", i, st[i].kind);
+      MRF_CHECK_ARG(st[i].axis0 >= 0 && st[i].axis0 < 4 && st[i].axis1 >= 0 && st[i].axis1 < 4,
+                    "stage %d: axis out of range", i);
+      MRF_CHECK_ARG(st[i].kind != MRF_ZOOM2 || st[i].axis0 != st[i].axis1,
+                    "stage %d: a 2-D zoom needs two different axes", i);
+      MRF_CHECK_ARG(st[i].window >= 0 && std::isfinite(st[i].hop), "stage %d: bad window/hop", i);
+    }
+  }
+  for (int i = 0; i < s->n_starts; ++i)
+    for (int a = 0; a < 4; ++a)
+      MRF_CHECK_ARG(s->starts[i][a] >= 0 && s->starts[i][a] < dims[a],
+                    "start %d: index %d out of range on axis %d", i, s->starts[i][a], a);
+  return MRF_OK;
+}
+
+extern "C" int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_t n_vox,
+                                  int32_t n_tr, size_t* bytes) {
+  MRF_CHECK_ARG(ctx && bytes, "NULL argument");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_vox >= 0 && n_tr >= 1, "bad sizes");
+  *bytes = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid)).total;
+  return MRF_OK;
+}
+
+extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                               const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                               int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
+                               mrf_result_view out, void* workspace, size_t ws_bytes,
+                               void* stream) {
+  MRF_CHECK_ARG(ctx && seq, "context and sequence must not be NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  const int32_t dims[4] = {grid->t1_ms.n, grid->t2_ms.n, grid->df_hz.n,
+                           grid->b1.n > 0 ? grid->b1.n : 1};
+  rc = check_schedule(sched, dims);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_tr >= 1 && n_tr <= seq->n, "n_tr %d must be in [1, %d]", n_tr, seq->n);
+  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
+  if (n_vox == 0) return MRF_OK;
+  MRF_CHECK_ARG(vox != nullptr && out.idx != nullptr, "vox and out.idx must not be NULL");
+  MRF_CHECK_ARG(ld_vox >= n_tr, "ld_vox must be >= n_tr");
+  const ZoomPlan plan = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid));
+  MRF_CHECK_ARG(workspace != nullptr && ws_bytes >= plan.total,
+                "workspace too small (%zu < %zu bytes)", ws_bytes, plan.total);
+  MRF_CHECK_ARG(plan.lds <= 64 * 1024, "n_tr %d too long for the ZOOM kernel", n_tr);
+  hipStream_t st = (hipStream_t)stream;
+  const Tables* t = nullptr;
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, st, &t);
+  if (rc) return rc;
+
+  ZoomArgs a;
+  a.t1T = t->t1T;
+  a.t1ti = t->t1ti;
+  a.t2T = t->t2T;
+  a.dfT = t->dfT;
+  a.rf = t->rf;
+  a.n_tr = n_tr;
+  a.inversion = t->inversion;
+  for (int q = 0; q < 4; ++q) a.dims[q] = dims[q];
+  a.vox = (const float2*)vox;
+  a.ld_vox = ld_vox;
+  a.n_vox = n_vox;
+  a.init = init_idx;
+  a.idx = out.idx;
+  a.cc = out.cc;
+  a.margin = out.margin;
+  a.pd_re = out.pd_re;
+  a.pd_im = out.pd_im;
+  a.n_sim = out.n_sim;
+  char* ws = (char*)workspace;
+  a.counter = (int32_t*)ws;
+  a.memo_cap = plan.cap;
+  a.memo_keys = (int64_t*)(ws + plan.off_keys);
+  a.memo_vals = (float*)(ws + plan.off_vals);
+  mrf_zoom_schedule* dsch = (mrf_zoom_schedule*)(ws + plan.off_sched);
+  a.sch = dsch;
+  const int blocks = plan.blocks;
+  const size_t lds = plan.lds;
+  hipLaunchKernelGGL(k_zoom_init, dim3(1), dim3(64), 0, st, a.counter, *sched, dsch);
+  MRF_HIP(hipGetLastError());
+  static bool attr = false;
+  if (!attr) {
+    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                64 * 1024));
+    attr = true;
+  }
+  {
+    ProfScope prof(ctx, "k_zoom", st);
+    hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
+  }
+  MRF_HIP(hipGetLastError());
+  return MRF_OK;
+}
