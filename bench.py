@@ -102,8 +102,11 @@ def main():
     n_vox, N, E = vox.shape[0], w.n_tr, w.grid.size
     d32 = api.alloc_dictionary(N, E, "f32")
     ws = api.Workspace(ctx.device)
+    wsz = api.Workspace(ctx.device)
     out32 = api._result_tensors(n_vox, ctx.device)
+    outz = api._result_tensors(n_vox, ctx.device, with_nsim=True)
     ga = api.GridArg(w.grid)
+    sched = api.schedule_paper(ctx, sq, ga)
     torch.cuda.synchronize()
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -117,6 +120,9 @@ def main():
         marks[-1][1].record()
         api.match_bruteforce(ctx, d32, vox, top_k=2, workspace=ws, out=out32)
         marks.append(("match_f32", ev()))
+        marks[-1][1].record()
+        api.zoom_search(ctx, sq, ga, vox, sched=sched, workspace=wsz, out=outz)
+        marks.append(("zoom", ev()))
         marks[-1][1].record()
         if record:
             rows.setdefault("_marks", []).append(marks)
@@ -136,6 +142,18 @@ def main():
     wall = time.perf_counter() - t0
     ctx.profile(False)
     log(f"timed {args.steps} steps in {wall:.2f} s")
+
+    # single-slice ZOOM latency over repeated calls
+    zl = []
+    for _ in range(20):
+        a_, b_ = ev(), ev()
+        a_.record()
+        api.zoom_search(ctx, sq, ga, vox, sched=sched, workspace=wsz, out=outz)
+        b_.record()
+        zl.append((a_, b_))
+    torch.cuda.synchronize()
+    zl = [a_.elapsed_time(b_) for a_, b_ in zl]
+    nsim = outz["n_sim"].cpu().numpy()
 
     per_row = {}
     step_ms = []
@@ -165,7 +183,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "voxels": n_vox, "n_tr": N, "entries": E,
-                   "step": "dictionary generation FP32 + brute-force matching FP32"},
+                   "step": "dictionary generation FP32 + brute-force matching FP32 + MRF-ZOOM"},
         "roofline": {"bound": "mfma", "kernel": "k_match_f32", "achieved": achieved,
                      "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp32_mfma_tflops"], "traffic": None,
@@ -176,6 +194,11 @@ def main():
         "dict_gen": {"kernel": "k_sim_dict", "avg_ms": sim_avg,
                      "GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
                      "frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"]},
+        "zoom_voxels_per_s": n_vox / (float(np.median(zl)) * 1e-3),
+        "zoom": {"schedule": "paper (Methods, Experiment 2 steps 1-5)",
+                 "n_sim_mean": float(nsim.mean()), "n_sim_max": int(nsim.max()),
+                 "slice_ms_p50": float(np.percentile(zl, 50)),
+                 "slice_ms_p99": float(np.percentile(zl, 99)), "repeats": len(zl)},
         "slice_latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                              "p99": float(np.percentile(step_ms, 99))},
         "paper_context": "paper: 116.72 s per 1731-voxel 64x64 slice (ZOOM, df dictionary) on a "
