@@ -112,7 +112,10 @@ int64_t mrf_grid_size(const mrf_grid* grid);
  *              n_tr must be a multiple of 4.
  * Values are the raw signal (M0 = 1) unless unit_norm = 1, in which case each
  * entry is divided by its norm (two passes). norm (device, FP64
- * [entry_count], or NULL) receives the raw norm ||d||.
+ * [entry_count], or NULL) receives, for MRF_F32, the raw norm ||d||; for
+ * MRF_BF16, the norm of the stored (scaled, rounded) BF16 values, so that a
+ * CC computed from the stored entries is normalised consistently (rounding
+ * the entries but not their norm biases each entry's CC by up to ~2^-9).
  * ---------------------------------------------------------------------- */
 int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
                             int32_t n_tr, int64_t entry_begin, int64_t entry_count,

@@ -15,11 +15,10 @@
 #include <cmath>
 
 #include "internal.h"
+#include "match_common.h"
 #include "match_kernels.h"
 
 namespace mrf {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
 // Tile geometry of the FP32 GEMM.
@@ -44,38 +43,6 @@ struct MatchArgs {
   float* part_s;        // [n_chunks][2][n_vox_pad][kk]
   int32_t* part_i;
 };
-
-__device__ __forceinline__ bool beats(float s, int32_t i, float t, int32_t j) {
-  return s > t || (s == t && i < j);
-}
-
-// Insert (s, e) into the wave's list for voxel slot `vl` (lists in LDS,
-// sorted best first; lanes < kk each own one position). Uniform control flow.
-__device__ __forceinline__ void list_insert(float* ls, int32_t* li, int kk, int lane, float s,
-                                            int32_t e) {
-  float cs = -1.0f;
-  int32_t ci = 0x7fffffff;
-  if (lane < kk) {
-    cs = ls[lane];
-    ci = li[lane];
-  }
-  const bool better_here = (lane < kk) && beats(cs, ci, s, e);
-  const uint64_t m = __ballot(better_here);
-  const int p = __popcll(m);  // entries that stay ahead of the new one
-  if (p >= kk) return;
-  // shift down by one from p, then place the new entry
-  const float ps = __shfl_up(cs, 1);
-  const int32_t pi = __shfl_up(ci, 1);
-  if (lane < kk) {
-    if (lane == p) {
-      ls[lane] = s;
-      li[lane] = e;
-    } else if (lane > p) {
-      ls[lane] = ps;
-      li[lane] = pi;
-    }
-  }
-}
 
 __global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
@@ -269,20 +236,6 @@ __global__ __launch_bounds__(64) void k_pack_f32(const float2* __restrict__ vox,
 // ---------------------------------------------------------------------------
 // K4: merge the partial lists of every chunk into the final top-k per voxel.
 // ---------------------------------------------------------------------------
-struct MergeArgs {
-  const float* part_s;
-  const int32_t* part_i;
-  int32_t n_lists, n_vox, n_vox_pad, kk, top_k;
-  int64_t entry_base;
-  float* best_s;     // [n_vox][kk] workspace copy of the merged list
-  int32_t* best_i;
-  int64_t* idx;
-  float* cc;
-  float* margin;
-  int64_t* topk_idx;
-  float* topk_cc;
-};
-
 __global__ __launch_bounds__(64) void k_merge(MergeArgs a) {
   const int v = blockIdx.x * 64 + threadIdx.x;
   if (v >= a.n_vox) return;
@@ -362,6 +315,15 @@ __global__ __launch_bounds__(64) void k_pd_f32(const float2* __restrict__ vox, i
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+int launch_merge(mrf_context* ctx, const MergeArgs& m, hipStream_t st) {
+  {
+    ProfScope prof(ctx, "k_merge", st);
+    hipLaunchKernelGGL(k_merge, dim3((m.n_vox + 63) / 64), dim3(64), 0, st, m);
+  }
+  MRF_HIP(hipGetLastError());
+  return MRF_OK;
+}
+
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
@@ -524,11 +486,8 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   m.margin = out.margin;
   m.topk_idx = topk_idx;
   m.topk_cc = topk_cc;
-  {
-    ProfScope prof(ctx, "k_merge", st);
-    hipLaunchKernelGGL(k_merge, dim3((n_vox + 63) / 64), dim3(64), 0, st, m);
-  }
-  MRF_HIP(hipGetLastError());
+  rc = launch_merge(ctx, m, st);
+  if (rc) return rc;
   if (out.pd_re || out.pd_im) {
     hipLaunchKernelGGL(k_pd_f32, dim3(n_vox), dim3(64), 0, st, (const float2*)vox, ld_vox, n_vox,
                        d->n_tr, (const float*)d->re, (const float*)d->im, d->ld, bi, p.kk,

@@ -1,15 +1,475 @@
 // BF16 brute-force matching with FP32 re-scoring of the top candidates.
+//
+// Same complex-as-real GEMM as the FP32 path (Theory Eq. 1), on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation. The BF16 dictionary is
+// stored in blocks of 4 readouts, [j/4][entry][Re d_j, Im d_j x 4], which is
+// exactly one lane's 8-element operand of the instruction; the voxel operand
+// is packed the same way: row 2v holds (Re v, Im v) pairs, row 2v+1 holds
+// (Im v, -Re v), so C[2v][k] = Re s_vk and C[2v+1][k] = Im s_vk.
+// The top-k of every voxel (k <= 8) is then re-simulated in FP32 with the
+// dictionary kernel's step function and re-scored exactly (K5).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
+#include "bloch.h"
 #include "internal.h"
+#include "match_common.h"
 #include "match_kernels.h"
 
 namespace mrf {
-size_t bf16_workspace_bytes(const mrf_dict_view*, int32_t, int32_t, int) { return 256; }
-int match_bf16(mrf_context*, const mrf_dict_view*, const void*, int32_t, int64_t, int32_t,
-               const mrf_sequence*, const mrf_grid*, mrf_result_view, int64_t*, float*, void*,
-               size_t, hipStream_t) {
-  set_error("BF16 matching is not built yet");
-  return MRF_ERR_UNSUPPORTED;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Workgroup tile 256 x 256: 4 waves in 2 x 2, each 128 x 128 = 4 x 4 blocks
+// of 32 x 32. One instruction covers K = 16 = 2 blocks of 4 readouts
+// (lanes 0-31: block 2s, lanes 32-63: block 2s + 1).
+constexpr int BBM = 256;
+constexpr int BBN = 256;
+constexpr int BKB = 4;        // 4-readout blocks per LDS chunk (16 readouts)
+constexpr int BKK_MAX = 8;    // candidate list length in the epilogue
+
+struct MatchB16Args {
+  const uint4* A;       // [nblk_pad][m_pad] 16-byte blocks
+  const uint4* B;       // [nblk][ld]
+  const double* norm;   // [n_entries] or NULL
+  int32_t nblk, nblk_pad, m_pad, n_vox_pad;
+  int64_t ld, n_entries;
+  int32_t n_row_tiles, n_chunks, n_col_tiles, kk;
+  float* part_s;        // [n_chunks][2][n_vox_pad][kk]
+  int32_t* part_i;
+};
+
+__global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
+  const int w = blockIdx.x;
+  const int xcd = w & 7;
+  const int slot = w >> 3;
+  const int rt = slot % a.n_row_tiles;
+  const int chunk = xcd + 8 * (slot / a.n_row_tiles);
+  if (chunk >= a.n_chunks) return;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint4* As = (uint4*)smem;              // [2 buf][BKB][BBM]
+  uint4* Bs = As + 2 * BKB * BBM;        // [2 buf][BKB][BBN]
+  float* Ls = (float*)(Bs + 2 * BKB * BBN);  // [4 waves][64 voxels][BKK_MAX]
+  int32_t* Li = (int32_t*)(Ls + 4 * 64 * BKK_MAX);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = a.kk;
+  const int row0 = rt * BBM;
+  float* myLs = Ls + wave * 64 * BKK_MAX;
+  int32_t* myLi = Li + wave * 64 * BKK_MAX;
+  for (int i = lane; i < 64 * BKK_MAX; i += 64) {
+    myLs[i] = -1.0f;
+    myLi[i] = 0x7fffffff;
+  }
+
+  const int ct_begin = (int)((int64_t)chunk * a.n_col_tiles / a.n_chunks);
+  const int ct_end = (int)((int64_t)(chunk + 1) * a.n_col_tiles / a.n_chunks);
+  const int n_kc = a.nblk_pad / BKB;
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+
+  for (int ct = ct_begin; ct < ct_end; ++ct) {
+    const int64_t col0 = (int64_t)ct * BBN;
+    floatx16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    uint4 ra[BKB], rb[BKB];
+    auto gload = [&](int c) {
+#pragma unroll
+      for (int i = 0; i < BKB; ++i) {
+        const int blk = c * BKB + i;
+        ra[i] = a.A[(int64_t)blk * a.m_pad + row0 + tid];
+        const int64_t col = col0 + tid;
+        uint4 b = zero;
+        if (blk < a.nblk && col < a.ld) b = a.B[(int64_t)blk * a.ld + col];
+        rb[i] = b;
+      }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < BKB; ++i) {
+        As[(buf * BKB + i) * BBM + tid] = ra[i];
+        Bs[(buf * BKB + i) * BBN + tid] = rb[i];
+      }
+    };
+
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int c = 0; c < n_kc; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < n_kc) gload(c + 1);
+      const bf16x8* as = (const bf16x8*)(As + (buf * BKB + (lane >> 5)) * BBM + wr * 128 + (lane & 31));
+      const bf16x8* bs = (const bf16x8*)(Bs + (buf * BKB + (lane >> 5)) * BBN + wc * 128 + (lane & 31));
+#pragma unroll
+      for (int s = 0; s < BKB / 2; ++s) {
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          fa[i] = as[2 * s * BBM + 32 * i];
+          fb[i] = bs[2 * s * BBN + 32 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+      if (c + 1 < n_kc) sstore(buf ^ 1);
+      __syncthreads();
+    }
+
+    // ---- epilogue (as in the FP32 kernel) ----
+    float inv[4];
+    int32_t ecol[4];
+#pragma unroll
+    for (int bn = 0; bn < 4; ++bn) {
+      const int64_t e = col0 + wc * 128 + bn * 32 + (lane & 31);
+      ecol[bn] = (int32_t)e;
+      if (e < a.n_entries) {
+        const double n = a.norm ? a.norm[e] : 1.0;
+        inv[bn] = n > 0.0 ? (float)(1.0 / (n * n)) : 0.0f;
+      } else {
+        inv[bn] = -1.0f;
+      }
+    }
+#pragma unroll
+    for (int bm = 0; bm < 4; ++bm) {
+#pragma unroll
+      for (int bn = 0; bn < 4; ++bn) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int r = 4 * (q >> 1) + 2 * (q & 1);
+          const float re = acc[bm][bn][r], im = acc[bm][bn][r + 1];
+          const float sc = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
+          // threshold: the current k-th best of this lane's voxel (list tail in LDS)
+          const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
+          uint64_t m = __ballot(sc > myLs[vme * BKK_MAX + kk - 1]);
+          while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const float s = __shfl(sc, src);
+            const int32_t e = __shfl(ecol[bn], src);
+            const int vl = bm * 16 + 4 * (q >> 1) + 2 * (src >> 5) + (q & 1);
+            list_insert(myLs + vl * BKK_MAX, myLi + vl * BKK_MAX, kk, lane, s, e);
+          }
+        }
+      }
+    }
+  }
+
+  for (int i = lane; i < 64 * kk; i += 64) {
+    const int vl = i / kk, p = i % kk;
+    const int v = (row0 + wr * 128) / 2 + vl;
+    if (v < a.n_vox_pad) {
+      const int64_t o = (((int64_t)chunk * 2 + wc) * a.n_vox_pad + v) * kk + p;
+      a.part_s[o] = myLs[vl * BKK_MAX + p];
+      a.part_i[o] = myLi[vl * BKK_MAX + p];
+    }
+  }
 }
+
+// K2 (BF16): unit-norm voxel (FP64 norm), packed in 4-readout blocks.
+__global__ __launch_bounds__(64) void k_pack_bf16(const float2* __restrict__ vox, int64_t ld_vox,
+                                                  int32_t n_vox, int32_t n_tr, int32_t nblk_pad,
+                                                  int32_t m_pad, uint4* __restrict__ A,
+                                                  double* __restrict__ vnorm) {
+  const int v = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s2 = 0.0;
+  if (v < n_vox) {
+    for (int j = lane; j < n_tr; j += 64) {
+      const float2 x = vox[(int64_t)v * ld_vox + j];
+      s2 = fma((double)x.x, (double)x.x, s2);
+      s2 = fma((double)x.y, (double)x.y, s2);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+  const double nv = sqrt(s2);
+  const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
+  if (lane == 0 && v < n_vox) vnorm[v] = nv;
+  for (int b = lane; b < nblk_pad; b += 64) {
+    uint32_t re_row[4], im_row[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = 4 * b + q;
+      float2 x = make_float2(0.f, 0.f);
+      if (v < n_vox && j < n_tr) x = vox[(int64_t)v * ld_vox + j];
+      const float xr = x.x * inv, xi = x.y * inv;
+      re_row[q] = pack_bf16_pair(xr, xi);
+      im_row[q] = pack_bf16_pair(xi, -xr);
+    }
+    A[(int64_t)b * m_pad + 2 * v] = make_uint4(re_row[0], re_row[1], re_row[2], re_row[3]);
+    A[(int64_t)b * m_pad + 2 * v + 1] = make_uint4(im_row[0], im_row[1], im_row[2], im_row[3]);
+  }
+}
+
+// K5: re-simulate each voxel's BF16 candidates in FP32 (same step function
+// and tables as the dictionary) and re-score them exactly; one lane per
+// (voxel, candidate), 8 lanes per voxel.
+struct RescoreArgs {
+  const float2* t1T;
+  const float* t1ti;
+  const float2* t2T;
+  const float4* dfT;
+  const float* rf;
+  int32_t n_tr, inversion, n2, n3, n4;
+  const float2* vox;
+  int64_t ld_vox;
+  int32_t n_vox, kk, top_k;
+  const double* vnorm;
+  const float* best_s;  // [n_vox][kk] BF16 estimates (CC^2)
+  const int32_t* best_i;
+  int64_t entry_base;
+  int64_t* idx;
+  float* cc;
+  float* margin;
+  float* pd_re;
+  float* pd_im;
+  int64_t* topk_idx;
+  float* topk_cc;
+};
+
+__global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
+  const int lane = threadIdx.x;
+  const int v = blockIdx.x * 8 + (lane >> 3);
+  const int q = lane & 7;
+  const bool active = v < a.n_vox && q < a.kk;
+  int32_t e = 0x7fffffff;
+  if (active) e = a.best_i[(int64_t)v * a.kk + q];
+  double dr = 0.0, di = 0.0, n2 = 0.0;
+  const bool sim = active && e != 0x7fffffff;
+  if (sim) {
+    const int64_t k = a.entry_base + e;
+    int64_t t = k;
+    const int32_t i4 = (int32_t)(t % a.n4);
+    t /= a.n4;
+    const int32_t i3 = (int32_t)(t % a.n3);
+    t /= a.n3;
+    const int32_t i2 = (int32_t)(t % a.n2);
+    const int32_t i1 = (int32_t)(t / a.n2);
+    const int32_t n = a.n_tr;
+    const float2* p1 = a.t1T + (int64_t)i1 * n;
+    const float2* p2 = a.t2T + (int64_t)i2 * n;
+    const float4* pd = a.dfT + (int64_t)i3 * n;
+    const float* R = a.rf + (int64_t)i4 * n * 9;
+    const float2* x = a.vox + (int64_t)v * a.ld_vox;
+    Spin m = initial_spin(a.inversion, a.t1ti[i1]);
+    for (int32_t j = 0; j < n; ++j) {
+      const float2 r1 = p1[j];
+      const float2 r2 = p2[j];
+      const float4 pc = pd[j];
+      rf_pulse(m, R + 9 * j);
+      free_evolve(m, pc.x, pc.y, r2.x, r1.x);
+      const float2 s = x[j];
+      // v conj(d)
+      dr = fma((double)s.x, (double)m.x, fma((double)s.y, (double)m.y, dr));
+      di = fma((double)s.y, (double)m.x, fma(-(double)s.x, (double)m.y, di));
+      n2 = fma((double)m.x, (double)m.x, n2);
+      n2 = fma((double)m.y, (double)m.y, n2);
+      free_evolve(m, pc.z, pc.w, r2.y, r1.y);
+    }
+  }
+  float c = -1.0f;
+  if (sim) {
+    const double nv = a.vnorm[v];
+    c = (n2 > 0.0 && nv > 0.0) ? (float)(sqrt(dr * dr + di * di) / (sqrt(n2) * nv)) : 0.0f;
+  }
+  // best and runner-up among the 8 lanes of this voxel (ties: lower index)
+  float bc = c;
+  int32_t be = sim ? e : 0x7fffffff;
+  int bl = q;
+  for (int o = 4; o > 0; o >>= 1) {
+    const float oc = __shfl_xor(bc, o, 8);
+    const int32_t oe = __shfl_xor(be, o, 8);
+    const int ol = __shfl_xor(bl, o, 8);
+    if (beats(oc, oe, bc, be)) {
+      bc = oc;
+      be = oe;
+      bl = ol;
+    }
+  }
+  float sc = (q == bl) ? -1.0f : c;  // runner-up: best of the others
+  for (int o = 4; o > 0; o >>= 1) sc = fmaxf(sc, __shfl_xor(sc, o, 8));
+  const double bdr = __shfl(dr, (lane & ~7) + bl);
+  const double bdi = __shfl(di, (lane & ~7) + bl);
+  const double bn2 = __shfl(n2, (lane & ~7) + bl);
+  if (v < a.n_vox && q == 0) {
+    a.idx[v] = be == 0x7fffffff ? -1 : a.entry_base + be;
+    if (a.cc) a.cc[v] = fmaxf(bc, 0.0f);
+    if (a.margin) a.margin[v] = sc < 0.0f ? INFINITY : bc - sc;
+    if (a.pd_re) a.pd_re[v] = bn2 > 0.0 ? (float)(bdr / bn2) : 0.0f;
+    if (a.pd_im) a.pd_im[v] = bn2 > 0.0 ? (float)(bdi / bn2) : 0.0f;
+  }
+  if (v < a.n_vox && q < a.top_k) {
+    const float s = a.best_s[(int64_t)v * a.kk + q];
+    if (a.topk_idx) a.topk_idx[(int64_t)v * a.top_k + q] = e == 0x7fffffff ? -1 : a.entry_base + e;
+    if (a.topk_cc) a.topk_cc[(int64_t)v * a.top_k + q] = sqrtf(fmaxf(s, 0.0f));
+  }
+}
+
+// ---------------------------------------------------------------------------
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct PlanB {
+  int32_t nblk, nblk_pad, m_pad, n_vox_pad, n_row_tiles, n_col_tiles, n_chunks, kk;
+  size_t off_A, off_vn, off_ps, off_pi, off_bs, off_bi, total;
+};
+
+static PlanB plan_bf16(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu) {
+  PlanB p;
+  p.kk = std::max(top_k, 2);
+  p.nblk = d->n_tr / 4;
+  p.nblk_pad = (p.nblk + BKB - 1) / BKB * BKB;
+  p.m_pad = std::max((2 * n_vox + BBM - 1) / BBM * BBM, BBM);
+  p.n_vox_pad = p.m_pad / 2;
+  p.n_row_tiles = p.m_pad / BBM;
+  p.n_col_tiles = (int32_t)((d->n_entries + BBN - 1) / BBN);
+  int want = (2 * n_cu + p.n_row_tiles - 1) / p.n_row_tiles;
+  want = std::min(want, std::max(p.n_col_tiles, 1));
+  p.n_chunks = std::max(8, (want + 7) / 8 * 8);
+  size_t o = 0;
+  p.off_A = o;
+  o = al(o + sizeof(uint4) * (size_t)p.nblk_pad * p.m_pad);
+  p.off_vn = o;
+  o = al(o + sizeof(double) * (size_t)p.n_vox_pad);
+  const size_t np = (size_t)p.n_chunks * 2 * p.n_vox_pad * p.kk;
+  p.off_ps = o;
+  o = al(o + sizeof(float) * np);
+  p.off_pi = o;
+  o = al(o + sizeof(int32_t) * np);
+  p.off_bs = o;
+  o = al(o + sizeof(float) * (size_t)p.n_vox_pad * p.kk);
+  p.off_bi = o;
+  o = al(o + sizeof(int32_t) * (size_t)p.n_vox_pad * p.kk);
+  p.total = o;
+  return p;
+}
+
+size_t bf16_workspace_bytes(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu) {
+  return plan_bf16(d, n_vox, top_k, n_cu).total;
+}
+
+int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_t n_vox,
+               int64_t ld_vox, int32_t top_k, const mrf_sequence* seq, const mrf_grid* grid,
+               mrf_result_view out, int64_t* topk_idx, float* topk_cc, void* workspace,
+               size_t ws_bytes, hipStream_t st) {
+  MRF_CHECK_ARG(seq != nullptr && grid != nullptr,
+                "a BF16 dictionary needs seq and grid (candidates are re-simulated in FP32)");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  MRF_CHECK_ARG(top_k >= 2 && top_k <= BKK_MAX, "BF16 matching needs top_k in [2, %d]", BKK_MAX);
+  MRF_CHECK_ARG(d->n_tr <= seq->n, "dictionary n_tr exceeds the sequence length");
+  MRF_CHECK_ARG(d->entry_base + d->n_entries <= grid_size_checked(grid),
+                "dictionary entries exceed the grid");
+  const PlanB p = plan_bf16(d, n_vox, top_k, ctx->n_cu);
+  MRF_CHECK_ARG(ws_bytes >= p.total, "workspace too small (%zu < %zu bytes)", ws_bytes, p.total);
+  const Tables* t = nullptr;
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, d->n_tr, st, &t);
+  if (rc) return rc;
+  char* ws = (char*)workspace;
+  uint4* A = (uint4*)(ws + p.off_A);
+  double* vn = (double*)(ws + p.off_vn);
+  float* ps = (float*)(ws + p.off_ps);
+  int32_t* pi = (int32_t*)(ws + p.off_pi);
+  float* bs = (float*)(ws + p.off_bs);
+  int32_t* bi = (int32_t*)(ws + p.off_bi);
+  {
+    ProfScope prof(ctx, "k_pack_bf16", st);
+    hipLaunchKernelGGL(k_pack_bf16, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox,
+                       ld_vox, n_vox, d->n_tr, p.nblk_pad, p.m_pad, A, vn);
+  }
+  MRF_HIP(hipGetLastError());
+  MatchB16Args a;
+  a.A = A;
+  a.B = (const uint4*)d->re;
+  a.norm = d->norm;
+  a.nblk = p.nblk;
+  a.nblk_pad = p.nblk_pad;
+  a.m_pad = p.m_pad;
+  a.n_vox_pad = p.n_vox_pad;
+  a.ld = d->ld;
+  a.n_entries = d->n_entries;
+  a.n_row_tiles = p.n_row_tiles;
+  a.n_chunks = p.n_chunks;
+  a.n_col_tiles = p.n_col_tiles;
+  a.kk = p.kk;
+  a.part_s = ps;
+  a.part_i = pi;
+  const size_t lds = sizeof(uint4) * 2 * BKB * (BBM + BBN) +
+                     (sizeof(float) + sizeof(int32_t)) * 4 * 64 * BKK_MAX;
+  static bool attr = false;
+  if (!attr) {
+    MRF_HIP(hipFuncSetAttribute((const void*)k_match_bf16,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  {
+    ProfScope prof(ctx, "k_match_bf16", st);
+    hipLaunchKernelGGL(k_match_bf16, dim3(p.n_row_tiles * p.n_chunks), dim3(256), lds, st, a);
+  }
+  MRF_HIP(hipGetLastError());
+  MergeArgs m;
+  m.part_s = ps;
+  m.part_i = pi;
+  m.n_lists = p.n_chunks * 2;
+  m.n_vox = n_vox;
+  m.n_vox_pad = p.n_vox_pad;
+  m.kk = p.kk;
+  m.top_k = top_k;
+  m.entry_base = d->entry_base;
+  m.best_s = bs;
+  m.best_i = bi;
+  m.idx = nullptr;  // final outputs come from the re-scoring
+  m.cc = nullptr;
+  m.margin = nullptr;
+  m.topk_idx = nullptr;
+  m.topk_cc = nullptr;
+  rc = launch_merge(ctx, m, st);
+  if (rc) return rc;
+  RescoreArgs r;
+  r.t1T = t->t1T;
+  r.t1ti = t->t1ti;
+  r.t2T = t->t2T;
+  r.dfT = t->dfT;
+  r.rf = t->rf;
+  r.n_tr = d->n_tr;
+  r.inversion = t->inversion;
+  r.n2 = t->n2;
+  r.n3 = t->n3;
+  r.n4 = t->n4;
+  r.vox = (const float2*)vox;
+  r.ld_vox = ld_vox;
+  r.n_vox = n_vox;
+  r.kk = p.kk;
+  r.top_k = top_k;
+  r.vnorm = vn;
+  r.best_s = bs;
+  r.best_i = bi;
+  r.entry_base = d->entry_base;
+  r.idx = out.idx;
+  r.cc = out.cc;
+  r.margin = out.margin;
+  r.pd_re = out.pd_re;
+  r.pd_im = out.pd_im;
+  r.topk_idx = topk_idx;
+  r.topk_cc = topk_cc;
+  {
+    ProfScope prof(ctx, "k_rescore", st);
+    hipLaunchKernelGGL(k_rescore, dim3((n_vox + 7) / 8), dim3(64), 0, st, r);
+  }
+  MRF_HIP(hipGetLastError());
+  return MRF_OK;
+}
+
 }  // namespace mrf

@@ -11,4 +11,21 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
                int64_t ld_vox, int32_t top_k, const mrf_sequence* seq, const mrf_grid* grid,
                mrf_result_view out, int64_t* topk_idx, float* topk_cc, void* workspace,
                size_t ws_bytes, hipStream_t stream);
+
+// Merge of per-chunk candidate lists [n_lists][n_vox_pad][kk] into the final
+// per-voxel list (best_s/best_i [n_vox][kk]) and the FP32 outputs.
+struct MergeArgs {
+  const float* part_s;
+  const int32_t* part_i;
+  int32_t n_lists, n_vox, n_vox_pad, kk, top_k;
+  int64_t entry_base;
+  float* best_s;
+  int32_t* best_i;
+  int64_t* idx;
+  float* cc;
+  float* margin;
+  int64_t* topk_idx;
+  float* topk_cc;
+};
+int launch_merge(mrf_context* ctx, const MergeArgs& m, hipStream_t st);
 }  // namespace mrf

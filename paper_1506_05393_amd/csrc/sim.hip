@@ -58,12 +58,16 @@ __device__ __forceinline__ void unravel(int64_t k, int32_t n2, int32_t n3, int32
   i1 = (int32_t)(k / n2);
 }
 
-// mode 0: accumulate the norm only; mode 1: FP32 planar stores; mode 2: BF16 blocks.
+// mode 0: accumulate the norm only; mode 1: FP32 planar stores; mode 2: BF16
+// blocks. Returns the squared norm of the simulated signal; in mode 2 *stored
+// receives the squared norm of the stored (scaled, rounded) BF16 values, the
+// normaliser that keeps CCs computed from the stored dictionary consistent.
 template <int MODE>
 __device__ __forceinline__ double run_entry(const SimArgs& a, int32_t i1, int32_t i2, int32_t i3,
-                                            const float* R, int64_t e, float scale) {
+                                            const float* R, int64_t e, float scale,
+                                            double* stored = nullptr) {
   Spin m = initial_spin(a.inversion, a.t1ti[i1]);
-  double n2 = 0.0;
+  double n2 = 0.0, nb = 0.0;
   const float2* t1 = a.t1 + i1;
   const float2* t2 = a.t2 + i2;
   const float4* df = a.df + i3;
@@ -81,10 +85,15 @@ __device__ __forceinline__ double run_entry(const SimArgs& a, int32_t i1, int32_
         n2 = fma((double)m.x, (double)m.x, n2);
         n2 = fma((double)m.y, (double)m.y, n2);
         w[q] = pack_bf16x2(m.x * scale, m.y * scale);
+        const double bx = (double)__uint_as_float(w[q] << 16);
+        const double by = (double)__uint_as_float(w[q] & 0xFFFF0000u);
+        nb = fma(bx, bx, nb);
+        nb = fma(by, by, nb);
         free_evolve(m, pc.z, pc.w, r2.y, r1.y);
       }
       a.packed[(int64_t)(j >> 2) * a.ld + e] = make_uint4(w[0], w[1], w[2], w[3]);
     }
+    if (stored) *stored = nb;
   } else {
 #pragma unroll 2
     for (int32_t j = 0; j < a.n_tr; ++j) {
@@ -119,8 +128,10 @@ __global__ __launch_bounds__(256) void k_sim_dict(SimArgs a) {
     n2 = run_entry<0>(a, i1, i2, i3, R, e, 1.0f);
     scale = n2 > 0.0 ? (float)(1.0 / sqrt(n2)) : 0.0f;
   }
-  double n2b = run_entry<MODE>(a, i1, i2, i3, R, e, scale);
+  double stored = 0.0;
+  double n2b = run_entry<MODE>(a, i1, i2, i3, R, e, scale, &stored);
   if (!a.unit_norm) n2 = n2b;
+  if (MODE == 2) n2 = stored;  // BF16: the norm of the values actually stored
   if (a.norm) a.norm[e] = sqrt(n2);
 }
 
