@@ -101,9 +101,11 @@ def main():
     vox = make_inputs(api, ctx, sq, w, torch)
     n_vox, N, E = vox.shape[0], w.n_tr, w.grid.size
     d32 = api.alloc_dictionary(N, E, "f32")
+    d16 = api.alloc_dictionary(N, E, "bf16")
     ws = api.Workspace(ctx.device)
     wsz = api.Workspace(ctx.device)
     out32 = api._result_tensors(n_vox, ctx.device)
+    out16 = api._result_tensors(n_vox, ctx.device)
     outz = api._result_tensors(n_vox, ctx.device, with_nsim=True)
     ga = api.GridArg(w.grid)
     sched = api.schedule_paper(ctx, sq, ga)
@@ -121,6 +123,12 @@ def main():
         api.match_bruteforce(ctx, d32, vox, top_k=2, workspace=ws, out=out32)
         marks.append(("match_f32", ev()))
         marks[-1][1].record()
+        api.simulate_dictionary(ctx, sq, ga, dtype="bf16", out=d16)
+        marks.append(("dict_bf16", ev()))
+        marks[-1][1].record()
+        api.match_bruteforce(ctx, d16, vox, top_k=8, seq=sq, grid=ga, workspace=ws, out=out16)
+        marks.append(("match_bf16_rescore", ev()))
+        marks[-1][1].record()
         api.zoom_search(ctx, sq, ga, vox, sched=sched, workspace=wsz, out=outz)
         marks.append(("zoom", ev()))
         marks[-1][1].record()
@@ -132,7 +140,7 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
     ctx.profile(True)
-    for k in ("k_match_f32", "k_sim_dict"):
+    for k in ("k_match_f32", "k_sim_dict", "k_match_bf16", "k_rescore"):
         ctx.profile_read(k, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,7 +172,13 @@ def main():
     gemm_ms, gemm_n = ctx.profile_read("k_match_f32")
     sim_ms, sim_n = ctx.profile_read("k_sim_dict")
     gemm_avg = gemm_ms / max(gemm_n, 1)
-    sim_avg = sim_ms / max(sim_n, 1)
+    sim_avg = float(np.median(per_row["dict_f32"]))  # k_sim_dict runs for FP32 and BF16
+    b16_ms, b16_n = ctx.profile_read("k_match_bf16")
+    rs_ms, rs_n = ctx.profile_read("k_rescore")
+    b16_avg = b16_ms / max(b16_n, 1)
+    idx32 = out32["idx"].cpu().numpy()
+    idx16 = out16["idx"].cpu().numpy()
+    idxz = outz["idx"].cpu().numpy()
     flops = 8.0 * n_vox * N * E
     achieved = flops / (gemm_avg * 1e-3) / 1e12
     dict_bytes = E * N * 8 + E * 8
@@ -183,7 +197,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "voxels": n_vox, "n_tr": N, "entries": E,
-                   "step": "dictionary generation FP32 + brute-force matching FP32 + MRF-ZOOM"},
+                   "step": "dictionary generation FP32 + brute-force FP32 + dictionary generation "
+                           "BF16 + brute-force BF16 with top-8 FP32 re-scoring + MRF-ZOOM"},
         "roofline": {"bound": "mfma", "kernel": "k_match_f32", "achieved": achieved,
                      "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp32_mfma_tflops"], "traffic": None,
@@ -191,9 +206,25 @@ def main():
                      "algorithmic_flops_per_launch": flops},
         "rows_ms": {k: float(np.median(v)) for k, v in per_row.items()},
         "brute_f32_voxels_per_s": n_vox / (float(np.median(per_row["match_f32"])) * 1e-3),
-        "dict_gen": {"kernel": "k_sim_dict", "avg_ms": sim_avg,
-                     "GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
-                     "frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"]},
+        "brute_bf16_rescore_voxels_per_s":
+            n_vox / (float(np.median(per_row["match_bf16_rescore"])) * 1e-3),
+        "bf16": {"kernel": "k_match_bf16", "avg_ms": b16_avg,
+                 "TFLOP_per_s": flops / (b16_avg * 1e-3) / 1e12,
+                 "frac_bf16_peak": flops / (b16_avg * 1e-3) / 1e12 / PEAK["bf16_mfma_tflops"],
+                 "rescore_ms": rs_ms / max(rs_n, 1),
+                 "index_agreement_vs_f32": float(np.mean(idx16 == idx32)),
+                 "speedup_vs_f32": float(np.median(per_row["match_f32"]) /
+                                         np.median(per_row["match_bf16_rescore"]))},
+        "zoom_vs_brute": {"index_agreement_vs_f32": float(np.mean(idxz == idx32)),
+                          "speedup_vs_f32": float(np.median(per_row["match_f32"]) / np.median(zl)),
+                          "speedup_vs_bf16": float(np.median(per_row["match_bf16_rescore"]) /
+                                                   np.median(zl))},
+        "dict_gen": {"kernel": "k_sim_dict", "f32_ms": sim_avg,
+                     "f32_GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
+                     "f32_frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"],
+                     "bf16_ms": float(np.median(per_row["dict_bf16"])),
+                     "bf16_GB_per_s": (E * N * 4 + E * 8) /
+                                      (float(np.median(per_row["dict_bf16"])) * 1e-3) / 1e9},
         "zoom_voxels_per_s": n_vox / (float(np.median(zl)) * 1e-3),
         "zoom": {"schedule": "paper (Methods, Experiment 2 steps 1-5)",
                  "n_sim_mean": float(nsim.mean()), "n_sim_max": int(nsim.max()),
