@@ -27,7 +27,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // (lanes 0-31: block 2s, lanes 32-63: block 2s + 1).
 constexpr int BBM = 256;
 constexpr int BBN = 256;
-constexpr int BKB = 4;        // 4-readout blocks per LDS chunk (16 readouts)
+constexpr int BKB = 4;        // 4-readout blocks per pipeline stage (16 readouts, K = 32)
+constexpr int NSTAGE = 4;     // LDS ring of stages; loads run NSTAGE-1 stages ahead
 constexpr int BKK_MAX = 8;    // candidate list length in the epilogue
 
 struct MatchB16Args {
@@ -41,6 +42,34 @@ struct MatchB16Args {
   int32_t* part_i;
 };
 
+typedef __attribute__((address_space(3))) void* lds_ptr;
+typedef const __attribute__((address_space(1))) void* glb_ptr;
+
+// One wavefront moves 64 x 16 B from global memory straight into LDS: lane l
+// reads `src` (its own address) and the data lands at dst + 16 l.
+__device__ __forceinline__ void load_to_lds(const uint4* src, uint4* dst) {
+  __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)dst, 16, 0, 0);
+}
+
+// Issue the loads of one stage (BKB blocks of A rows and B columns) for this wave.
+__device__ __forceinline__ void issue_stage(const MatchB16Args& a, uint4* As, uint4* Bs, int st,
+                                            int c, int row0, int64_t col0, int wave, int lane) {
+#pragma unroll
+  for (int i = 0; i < BKB; ++i) {
+    const int blk = c * BKB + i;
+    // A is zero-padded to nblk_pad blocks: every row of the tile exists
+    load_to_lds(a.A + (int64_t)blk * a.m_pad + row0 + wave * 64 + lane,
+                As + (st * BKB + i) * BBM + wave * 64);
+    // B: blocks past the last readout are clamped to a real block (their
+    // products meet zero A rows); columns past ld are clamped too (those
+    // columns are masked in the epilogue)
+    const int bb = blk < a.nblk ? blk : a.nblk - 1;
+    int64_t col = col0 + wave * 64 + lane;
+    col = col < a.ld ? col : a.ld - 1;
+    load_to_lds(a.B + (int64_t)bb * a.ld + col, Bs + (st * BKB + i) * BBN + wave * 64);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   const int w = blockIdx.x;
   const int xcd = w & 7;
@@ -50,9 +79,9 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   if (chunk >= a.n_chunks) return;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  uint4* As = (uint4*)smem;              // [2 buf][BKB][BBM]
-  uint4* Bs = As + 2 * BKB * BBM;        // [2 buf][BKB][BBN]
-  float* Ls = (float*)(Bs + 2 * BKB * BBN);  // [4 waves][64 voxels][BKK_MAX]
+  uint4* As = (uint4*)smem;                  // [NSTAGE][BKB][BBM]
+  uint4* Bs = As + NSTAGE * BKB * BBM;       // [NSTAGE][BKB][BBN]
+  float* Ls = (float*)(Bs + NSTAGE * BKB * BBN);  // [4 waves][64 voxels][BKK_MAX]
   int32_t* Li = (int32_t*)(Ls + 4 * 64 * BKK_MAX);
 
   const int tid = threadIdx.x;
@@ -71,7 +100,6 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   const int ct_begin = (int)((int64_t)chunk * a.n_col_tiles / a.n_chunks);
   const int ct_end = (int)((int64_t)(chunk + 1) * a.n_col_tiles / a.n_chunks);
   const int n_kc = a.nblk_pad / BKB;
-  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 
   for (int ct = ct_begin; ct < ct_end; ++ct) {
     const int64_t col0 = (int64_t)ct * BBN;
@@ -83,34 +111,30 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    uint4 ra[BKB], rb[BKB];
-    auto gload = [&](int c) {
-#pragma unroll
-      for (int i = 0; i < BKB; ++i) {
-        const int blk = c * BKB + i;
-        ra[i] = a.A[(int64_t)blk * a.m_pad + row0 + tid];
-        const int64_t col = col0 + tid;
-        uint4 b = zero;
-        if (blk < a.nblk && col < a.ld) b = a.B[(int64_t)blk * a.ld + col];
-        rb[i] = b;
-      }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-      for (int i = 0; i < BKB; ++i) {
-        As[(buf * BKB + i) * BBM + tid] = ra[i];
-        Bs[(buf * BKB + i) * BBN + tid] = rb[i];
-      }
-    };
-
-    gload(0);
-    sstore(0);
+    // every wave is past the previous tile's last reads of the ring
     __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NSTAGE - 1; ++p)
+      if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, col0, wave, lane);
+
     for (int c = 0; c < n_kc; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < n_kc) gload(c + 1);
-      const bf16x8* as = (const bf16x8*)(As + (buf * BKB + (lane >> 5)) * BBM + wr * 128 + (lane & 31));
-      const bf16x8* bs = (const bf16x8*)(Bs + (buf * BKB + (lane >> 5)) * BBN + wc * 128 + (lane & 31));
+      // wait for this wave's loads of stage c (2 loads per block and stage),
+      // then for everyone's
+      const int ahead = min(n_kc - 1 - c, NSTAGE - 2);
+      if (ahead >= 2)
+        asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+      else if (ahead == 1)
+        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+      else
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // plain barrier: __syncthreads() would also wait for the later stages'
+      // loads (its fence drains every outstanding memory operation)
+      __builtin_amdgcn_s_barrier();
+      if (c + NSTAGE - 1 < n_kc)
+        issue_stage(a, As, Bs, (c + NSTAGE - 1) % NSTAGE, c + NSTAGE - 1, row0, col0, wave, lane);
+      const int st = c % NSTAGE;
+      const bf16x8* as = (const bf16x8*)(As + (st * BKB + (lane >> 5)) * BBM + wr * 128 + (lane & 31));
+      const bf16x8* bs = (const bf16x8*)(Bs + (st * BKB + (lane >> 5)) * BBN + wc * 128 + (lane & 31));
 #pragma unroll
       for (int s = 0; s < BKB / 2; ++s) {
         bf16x8 fa[4], fb[4];
@@ -125,8 +149,6 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
           for (int j = 0; j < 4; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
-      if (c + 1 < n_kc) sstore(buf ^ 1);
-      __syncthreads();
     }
 
     // ---- epilogue (as in the FP32 kernel) ----
@@ -143,25 +165,40 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
         inv[bn] = -1.0f;
       }
     }
-#pragma unroll
+    // one row block (4 x 32 x 32 accumulators) at a time: a rolled loop with a
+    // switch keeps only 64 accumulator values live in VGPRs
+#pragma unroll 1
     for (int bm = 0; bm < 4; ++bm) {
+      floatx16 blk[4];
+      switch (bm) {
+        case 0: blk[0] = acc[0][0]; blk[1] = acc[0][1]; blk[2] = acc[0][2]; blk[3] = acc[0][3]; break;
+        case 1: blk[0] = acc[1][0]; blk[1] = acc[1][1]; blk[2] = acc[1][2]; blk[3] = acc[1][3]; break;
+        case 2: blk[0] = acc[2][0]; blk[1] = acc[2][1]; blk[2] = acc[2][2]; blk[3] = acc[2][3]; break;
+        default: blk[0] = acc[3][0]; blk[1] = acc[3][1]; blk[2] = acc[3][2]; blk[3] = acc[3][3]; break;
+      }
 #pragma unroll
-      for (int bn = 0; bn < 4; ++bn) {
+      for (int q = 0; q < 8; ++q) {
+        const int r = 4 * (q >> 1) + 2 * (q & 1);
+        float sc[4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int r = 4 * (q >> 1) + 2 * (q & 1);
-          const float re = acc[bm][bn][r], im = acc[bm][bn][r + 1];
-          const float sc = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
-          // threshold: the current k-th best of this lane's voxel (list tail in LDS)
-          const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
-          uint64_t m = __ballot(sc > myLs[vme * BKK_MAX + kk - 1]);
+        for (int bn = 0; bn < 4; ++bn) {
+          const float re = blk[bn][r], im = blk[bn][r + 1];
+          sc[bn] = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
+        }
+        // threshold: the current k-th best of this lane's voxel (list tail in LDS)
+        const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
+        const float mx = fmaxf(fmaxf(sc[0], sc[1]), fmaxf(sc[2], sc[3]));
+        if (__ballot(mx > myLs[vme * BKK_MAX + kk - 1]) == 0) continue;  // common case
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn) {
+          uint64_t m = __ballot(sc[bn] > myLs[vme * BKK_MAX + kk - 1]);
           while (m) {
             const int src = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
-            const float s = __shfl(sc, src);
+            const float sv = __shfl(sc[bn], src);
             const int32_t e = __shfl(ecol[bn], src);
             const int vl = bm * 16 + 4 * (q >> 1) + 2 * (src >> 5) + (q & 1);
-            list_insert(myLs + vl * BKK_MAX, myLi + vl * BKK_MAX, kk, lane, s, e);
+            list_insert(myLs + vl * BKK_MAX, myLi + vl * BKK_MAX, kk, lane, sv, e);
           }
         }
       }
@@ -406,7 +443,7 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   a.kk = p.kk;
   a.part_s = ps;
   a.part_i = pi;
-  const size_t lds = sizeof(uint4) * 2 * BKB * (BBM + BBN) +
+  const size_t lds = sizeof(uint4) * NSTAGE * BKB * (BBM + BBN) +
                      (sizeof(float) + sizeof(int32_t)) * 4 * 64 * BKK_MAX;
   static bool attr = false;
   if (!attr) {
