@@ -44,6 +44,42 @@ struct MatchArgs {
   int32_t* part_i;
 };
 
+// One LDS chunk of KC readouts: A [2 planes][KC][BM] and B [2][KC][BN]
+// floats; thread t moves 8 float4 of each.
+__device__ __forceinline__ void load_chunk(const MatchArgs& a, int c, int row0, int64_t col0,
+                                           int tid, float4 (&ra)[8], float4 (&rb)[8]) {
+  const int s0 = c * KC;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = i * 256 + tid;  // [g][s][c4] with 32 float4 per row
+    const int g = idx >> 10;        // / (KC * 32)
+    const int s = (idx >> 5) & (KC - 1);
+    const int c4 = idx & 31;
+    ra[i] = *(const float4*)(a.A + ((int64_t)g * a.n_tr_pad + s0 + s) * a.m_pad + row0 + 4 * c4);
+    // unconditional loads (a branch here would make every load wait for
+    // the previous ones): readouts past n_tr are clamped to a stored row
+    // (they meet zero A rows), columns past ld to the last float4 (those
+    // columns are masked in the epilogue)
+    int64_t col = col0 + 4 * c4;
+    col = col + 4 <= a.ld ? col : a.ld - 4;
+    const int row = s0 + s < a.n_tr ? s0 + s : a.n_tr - 1;
+    const float* bp = g ? a.Bim : a.Bre;
+    rb[i] = *(const float4*)(bp + (int64_t)row * a.ld + col);
+  }
+}
+
+__device__ __forceinline__ void store_chunk(float* As, float* Bs, int buf, int tid,
+                                            const float4 (&ra)[8], const float4 (&rb)[8]) {
+  float* as = As + buf * 2 * KC * BM;
+  float* bs = Bs + buf * 2 * KC * BN;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = i * 256 + tid;
+    *(float4*)(as + 4 * idx) = ra[i];
+    *(float4*)(bs + 4 * idx) = rb[i];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
   // (round robin over 8), so the row tiles of one column chunk are grouped on
@@ -93,40 +129,14 @@ __global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
     float4 ra[8], rb[8];
-    auto gload = [&](int c) {
-      const int s0 = c * KC;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int idx = i * 256 + tid;  // [g][s][c4] with 32 float4 per row
-        const int g = idx >> 10;        // / (KC * 32)
-        const int s = (idx >> 5) & (KC - 1);
-        const int c4 = idx & 31;
-        ra[i] = *(const float4*)(a.A + ((int64_t)g * a.n_tr_pad + s0 + s) * a.m_pad + row0 + 4 * c4);
-        const int64_t col = col0 + 4 * c4;
-        const float* bp = g ? a.Bim : a.Bre;
-        if (s0 + s < a.n_tr && col + 4 <= a.ld)
-          rb[i] = *(const float4*)(bp + (int64_t)(s0 + s) * a.ld + col);
-        else
-          rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    };
-    auto sstore = [&](int buf) {
-      float* as = As + buf * 2 * KC * BM;
-      float* bs = Bs + buf * 2 * KC * BN;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int idx = i * 256 + tid;
-        *(float4*)(as + 4 * idx) = ra[i];
-        *(float4*)(bs + 4 * idx) = rb[i];
-      }
-    };
-
-    gload(0);
-    sstore(0);
+    load_chunk(a, 0, row0, col0, tid, ra, rb);
+    store_chunk(As, Bs, 0, tid, ra, rb);
     __syncthreads();
     for (int c = 0; c < n_kc; ++c) {
       const int buf = c & 1;
-      if (c + 1 < n_kc) gload(c + 1);
+      // always load (the last iteration reloads its own chunk): no branch
+      // around the loads, so they stay in flight during the MFMAs
+      load_chunk(a, c + 1 < n_kc ? c + 1 : c, row0, col0, tid, ra, rb);
       const float* as = As + buf * 2 * KC * BM + (lane >> 5) * KC * BM + wr * 64 + (lane & 31);
       const float* bs = Bs + buf * 2 * KC * BN + (lane >> 5) * KC * BN + wc * 64 + (lane & 31);
 #pragma unroll 8
@@ -138,7 +148,7 @@ __global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
         acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
       }
-      if (c + 1 < n_kc) sstore(buf ^ 1);
+      store_chunk(As, Bs, buf ^ 1, tid, ra, rb);
       __syncthreads();
     }
 
