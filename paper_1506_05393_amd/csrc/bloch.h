@@ -56,9 +56,9 @@ __device__ __forceinline__ void precession(double t, double df, float* cm1, floa
 // Rz(phi) Rx(-alpha) Rz(-phi), row-major, alpha = b1 * fa.
 __device__ __forceinline__ void pulse_matrix(double fa_deg, double ph_deg, double b1, float* R) {
   const double al = b1 * fa_deg * (M_PI / 180.0);
-  const double p = ph_deg * (M_PI / 180.0);
   double s, c, sa, ca;
-  sincos(p, &s, &c);
+  // phase in half-turns: multiples of 180 degrees give exact 0 and +-1
+  sincospi(ph_deg / 180.0, &s, &c);
   sincos(al, &sa, &ca);
   R[0] = (float)(c * c + s * s * ca);
   R[1] = (float)(c * s - s * c * ca);

@@ -39,6 +39,10 @@ struct Tables {
   uint64_t key = 0;
   int32_t n_tr = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;  // n4 >= 1
   int32_t inversion = 1;
+  // every RF phase of the first n_tr readouts is a multiple of 180 degrees, so
+  // each pulse is a rotation about the x axis (pulse_matrix then gives exact
+  // zeros off that axis and R00 = 1)
+  int32_t x_axis_pulses = 0;
   float2* t1 = nullptr;   // [n_tr][n1]  (1-E1 over TE, 1-E1 over TR-TE)
   float* t1ti = nullptr;  // [n1]        (1-E1 over TI)
   float2* t2 = nullptr;   // [n_tr][n2]  (1-E2 over TE, 1-E2 over TR-TE)

@@ -194,6 +194,9 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   t.n3 = g->df_hz.n;
   t.n4 = g->b1.n > 0 ? g->b1.n : 1;
   t.inversion = seq->inversion;
+  t.x_axis_pulses = 1;
+  for (int32_t j = 0; j < n_tr; ++j)
+    if (std::fmod(seq->ph[j], 180.0) != 0.0) t.x_axis_pulses = 0;
   const size_t nt = (size_t)(n_tr > 0 ? n_tr : 1);
   size_t o_t1 = 0;
   size_t o_ti = align256(o_t1 + sizeof(float2) * nt * t.n1);

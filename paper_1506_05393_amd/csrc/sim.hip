@@ -1,10 +1,20 @@
 // K1: dictionary simulation (Appendix Eq. A2 per entry) and on-the-fly
 // simulation of fingerprints at arbitrary parameter values.
 //
-// One thread per entry runs the readout recursion in registers (FP32 state,
-// FP64 norm). Consecutive threads take consecutive entries, so every store of
-// a wavefront is one contiguous 256 B (FP32 plane row) or 1 KB (BF16 4-readout
-// block) segment.
+// One thread runs the readout recursion of two entries in registers (FP32
+// state, FP32 partial sums of |m|^2 over four readouts added into FP64). A
+// block of 256 threads owns 512 consecutive entries: thread t takes entries
+// t and t + 256, so every store instruction of a wavefront writes one
+// contiguous 256 B (FP32 plane row) or 1 KB (BF16 four-readout block) run.
+//
+// The kernel is bound by its HBM writes. Three things keep it there:
+//  - stores are non-temporal buffer stores: the write stream does not evict
+//    the step tables from L2, and a per-row buffer range drops the ragged tail
+//    without branches;
+//  - the df table (the widest, 16 B per entry and readout) is staged through
+//    LDS eight readouts at a time, prefetched into registers one chunk ahead;
+//  - table rows, pulse matrices and store rows are addressed from scalar
+//    registers, so the per-readout vector work is the Bloch update itself.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -15,39 +25,63 @@
 
 namespace mrf {
 
-struct SimArgs {
-  const float2* t1;
-  const float* t1ti;
-  const float2* t2;
-  const float4* df;
-  const float* rf;
-  int32_t n_tr, n1, n2, n3, n4, inversion;
-  int64_t k0, count, ld;
-  float* re;        // F32 planar
-  float* im;
-  uint4* packed;    // BF16 blocks
-  double* norm;
-  int32_t unit_norm;
-};
+namespace {
 
-__device__ __forceinline__ const float* wave_uniform(const float* p) {
-  const uint64_t v = (uint64_t)p;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (const float*)(((uint64_t)hi << 32) | lo);
+constexpr int kThreads = 256;
+constexpr int kQ = 2;                              // entries per thread
+constexpr int kBlockEntries = kThreads * kQ;
+constexpr int kChunk = 8;                          // readouts per staged df chunk
+constexpr int kLdsMaxN3 = 128;                     // longest df axis staged through LDS
+constexpr int kPrefetch = kChunk * kLdsMaxN3 / kThreads;  // float4 per thread per chunk
+constexpr int kRsrcWord3 = 0x00020000;             // raw 32-bit buffer format
+
+// pulse kinds: general 3x3 or x-axis rotation, one matrix per wavefront
+// (no B1 axis: read through the scalar cache) or one per lane (B1 axis)
+enum PulseKind { kGeneralUniform = 0, kXAxisUniform = 1, kGeneralLane = 2, kXAxisLane = 3 };
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, int32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, kRsrcWord3);
 }
 
-__device__ __forceinline__ uint32_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
+__device__ __forceinline__ float2 load2(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
+__device__ __forceinline__ float4 load4(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+constexpr int kNonTemporal = 2;  // buffer cache-policy bit: streaming store
+
+__device__ __forceinline__ void store1(float v, rsrc_t r, uint32_t voff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, 0, kNonTemporal);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store4(const uint32_t w[4], rsrc_t r, uint32_t voff) {
+  const u32x4 v = {w[0], w[1], w[2], w[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, 0, kNonTemporal);
+}
+
+// LDS writes visible to the block; s_barrier without the full fence of
+// __syncthreads, which would also wait for every outstanding HBM store.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Round-to-nearest-even to BF16, two values per instruction (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-  return bf16_rne(lo) | (bf16_rne(hi) << 16);
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
-// Entry k -> per-axis indices.
+// Entry k -> per-axis indices (B1 fastest, then df, T2, T1).
 __device__ __forceinline__ void unravel(int64_t k, int32_t n2, int32_t n3, int32_t n4, int32_t& i1,
                                         int32_t& i2, int32_t& i3, int32_t& i4) {
   i4 = (int32_t)(k % n4);
@@ -58,81 +92,219 @@ __device__ __forceinline__ void unravel(int64_t k, int32_t n2, int32_t n3, int32
   i1 = (int32_t)(k / n2);
 }
 
-// mode 0: accumulate the norm only; mode 1: FP32 planar stores; mode 2: BF16
-// blocks. Returns the squared norm of the simulated signal; in mode 2 *stored
-// receives the squared norm of the stored (scaled, rounded) BF16 values, the
-// normaliser that keeps CCs computed from the stored dictionary consistent.
-template <int MODE>
-__device__ __forceinline__ double run_entry(const SimArgs& a, int32_t i1, int32_t i2, int32_t i3,
-                                            const float* R, int64_t e, float scale,
-                                            double* stored = nullptr) {
-  Spin m = initial_spin(a.inversion, a.t1ti[i1]);
-  double n2 = 0.0, nb = 0.0;
-  const float2* t1 = a.t1 + i1;
-  const float2* t2 = a.t2 + i2;
-  const float4* df = a.df + i3;
-  if (MODE == 2) {
-    for (int32_t j = 0; j < a.n_tr; j += 4) {
-      uint32_t w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int32_t jj = j + q;
-        const float2 r1 = t1[(int64_t)jj * a.n1];
-        const float2 r2 = t2[(int64_t)jj * a.n2];
-        const float4 pc = df[(int64_t)jj * a.n3];
-        rf_pulse(m, R + 9 * jj);
-        free_evolve(m, pc.x, pc.y, r2.x, r1.x);
-        n2 = fma((double)m.x, (double)m.x, n2);
-        n2 = fma((double)m.y, (double)m.y, n2);
-        w[q] = pack_bf16x2(m.x * scale, m.y * scale);
-        const double bx = (double)__uint_as_float(w[q] << 16);
-        const double by = (double)__uint_as_float(w[q] & 0xFFFF0000u);
-        nb = fma(bx, bx, nb);
-        nb = fma(by, by, nb);
-        free_evolve(m, pc.z, pc.w, r2.y, r1.y);
-      }
-      a.packed[(int64_t)(j >> 2) * a.ld + e] = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-    if (stored) *stored = nb;
+// x-axis pulse: with R00 = 1 and R01 = R02 = R10 = R20 = 0 exactly, the
+// general product rounds to the same values (the zero terms add exact zeros).
+template <int PK>
+__device__ __forceinline__ void pulse(Spin& m, const float* __restrict__ R) {
+  if (PK == kXAxisUniform || PK == kXAxisLane) {
+    const float y = m.y, z = m.z;
+    m.y = fmaf(R[5], z, R[4] * y);
+    m.z = fmaf(R[8], z, R[7] * y);
   } else {
-#pragma unroll 2
-    for (int32_t j = 0; j < a.n_tr; ++j) {
-      const float2 r1 = t1[(int64_t)j * a.n1];
-      const float2 r2 = t2[(int64_t)j * a.n2];
-      const float4 pc = df[(int64_t)j * a.n3];
-      rf_pulse(m, R + 9 * j);
-      free_evolve(m, pc.x, pc.y, r2.x, r1.x);
-      n2 = fma((double)m.x, (double)m.x, n2);
-      n2 = fma((double)m.y, (double)m.y, n2);
-      if (MODE == 1) {
-        a.re[(int64_t)j * a.ld + e] = m.x * scale;
-        a.im[(int64_t)j * a.ld + e] = m.y * scale;
+    rf_pulse(m, R);
+  }
+}
+
+}  // namespace
+
+struct SimArgs {
+  int32_t n_tr, n1, n2, n3, n4, inversion, unit_norm;
+  int32_t t1_bytes, t2_bytes, df_bytes;  // table extents (buffer ranges)
+  int64_t k0, count, ld;
+  float* re;        // F32 planar
+  float* im;
+  uint4* packed;    // BF16 blocks
+  double* norm;
+};
+
+struct EntryState {
+  uint32_t o1[kQ], o2[kQ], i3[kQ];  // byte offsets into the t1/t2 rows, df column
+  const float* rq[kQ];              // per-lane pulse matrices (B1 axis)
+  float r1ti[kQ];
+};
+
+// One pass over all readouts for the thread's kQ entries. MODE 0 accumulates
+// the norm only, MODE 1 stores FP32 planes, MODE 2 stores BF16 blocks and
+// also accumulates the norm of the stored (scaled, rounded) values into nb.
+template <int MODE, int PK, bool DF_LDS, bool SCALED>
+__device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
+                                         const float* __restrict__ rftab, rsrc_t r1s, rsrc_t r2s,
+                                         rsrc_t rds, float4* sdf, int64_t blk0, int32_t nrec,
+                                         const float (&scale)[kQ], double (&n2)[kQ],
+                                         double (&nb)[kQ]) {
+  const uint32_t tid = threadIdx.x;
+  const int32_t n_tr = a.n_tr, n3 = a.n3;
+  const int32_t per = kChunk * n3;  // staged float4 per chunk
+  Spin m[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    m[q] = initial_spin(a.inversion, st.r1ti[q]);
+    n2[q] = 0.0;
+    nb[q] = 0.0;
+  }
+  float4 pf[kPrefetch];
+  if (DF_LDS) {
+#pragma unroll
+    for (int p = 0; p < kPrefetch; ++p) pf[p] = load4(rds, 16u * (tid + kThreads * p), 0);
+#pragma unroll
+    for (int p = 0; p < kPrefetch; ++p)
+      if ((int32_t)(tid + kThreads * p) < per) sdf[tid + kThreads * p] = pf[p];
+    lds_barrier();
+  }
+  const int32_t nch = (n_tr + kChunk - 1) / kChunk;
+  for (int32_t c = 0; c < nch; ++c) {
+    const int32_t j0 = c * kChunk;
+    const float4* sd = sdf + (c & 1) * per;
+    if (DF_LDS && c + 1 < nch) {
+      // rows j0+8.. of the step-major table are contiguous. The whole offset
+      // goes in the vector operand, which the buffer range check covers:
+      // reads past the table end return zero and are never used.
+      const uint32_t row = (uint32_t)(j0 + kChunk) * (uint32_t)n3 * 16u;
+#pragma unroll
+      for (int p = 0; p < kPrefetch; ++p)
+        pf[p] = load4(rds, row + 16u * (tid + kThreads * p), 0);
+    }
+    float part[kQ], partb[kQ];
+    uint32_t w[kQ][4];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) part[q] = partb[q] = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < kChunk; ++jj) {
+      const int32_t j = j0 + jj;
+      if (j < n_tr) {
+        const rsrc_t wr = make_rsrc(MODE == 2 ? (const void*)(a.packed + (int64_t)(j >> 2) * a.ld + blk0)
+                                              : (const void*)(a.re + (int64_t)j * a.ld + blk0),
+                                    nrec);
+        const rsrc_t wi = make_rsrc(a.im + (int64_t)j * a.ld + blk0, nrec);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const float2 r1 = load2(r1s, st.o1[q], (uint32_t)j * a.n1 * 8u);
+          const float2 r2 = load2(r2s, st.o2[q], (uint32_t)j * a.n2 * 8u);
+          const float4 pc = DF_LDS ? sd[jj * n3 + st.i3[q]]
+                                   : load4(rds, 16u * st.i3[q], (uint32_t)j * n3 * 16u);
+          if (PK == kGeneralUniform || PK == kXAxisUniform)
+            pulse<PK>(m[q], rftab + 9 * j);
+          else
+            pulse<PK>(m[q], st.rq[q] + 9 * j);
+          free_evolve(m[q], pc.x, pc.y, r2.x, r1.x);
+          part[q] = fmaf(m[q].x, m[q].x, part[q]);
+          part[q] = fmaf(m[q].y, m[q].y, part[q]);
+          const float ox = SCALED ? m[q].x * scale[q] : m[q].x;
+          const float oy = SCALED ? m[q].y * scale[q] : m[q].y;
+          if (MODE == 1) {
+            store1(ox, wr, 4u * (tid + kThreads * q));
+            store1(oy, wi, 4u * (tid + kThreads * q));
+          } else if (MODE == 2) {
+            const uint32_t v = pack_bf16x2(ox, oy);
+            w[q][jj & 3] = v;
+            // |stored value|^2: BF16 products are exact in FP32 (v_dot2_f32_bf16)
+            const bf16x2_t b = __builtin_bit_cast(bf16x2_t, v);
+            partb[q] = __builtin_amdgcn_fdot2_f32_bf16(b, b, partb[q], false);
+            if ((jj & 3) == 3) store4(w[q], wr, 16u * (tid + kThreads * q));
+          }
+          free_evolve(m[q], pc.z, pc.w, r2.y, r1.y);
+        }
       }
-      free_evolve(m, pc.z, pc.w, r2.y, r1.y);
+      if ((jj & 3) == 3) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          n2[q] += (double)part[q];
+          nb[q] += (double)partb[q];
+          part[q] = partb[q] = 0.f;
+        }
+      }
+    }
+    if (DF_LDS) {
+      if (c + 1 < nch) {
+        float4* nx = sdf + ((c + 1) & 1) * per;
+#pragma unroll
+        for (int p = 0; p < kPrefetch; ++p)
+          if ((int32_t)(tid + kThreads * p) < per) nx[tid + kThreads * p] = pf[p];
+      }
+      lds_barrier();
     }
   }
-  return n2;
+}
+
+template <int MODE, int PK, bool DF_LDS>
+__global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* __restrict__ t1tab,
+                                                       const float2* __restrict__ t2tab,
+                                                       const float4* __restrict__ dftab,
+                                                       const float* __restrict__ rftab,
+                                                       const float* __restrict__ t1ti) {
+  extern __shared__ float4 sdf[];
+  const uint32_t tid = threadIdx.x;
+  const int64_t blk0 = (int64_t)blockIdx.x * kBlockEntries;
+  const int64_t rem = a.count - blk0;
+  const int32_t nb_entries = (int32_t)(rem < kBlockEntries ? rem : kBlockEntries);
+  const int32_t nrec = nb_entries * (MODE == 2 ? 16 : 4);
+  EntryState st;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    int64_t e = blk0 + tid + kThreads * q;
+    if (e >= a.count) e = a.count - 1;  // tail lanes recompute the last entry, never store it
+    int32_t i1, i2, i3, i4;
+    unravel(a.k0 + e, a.n2, a.n3, a.n4, i1, i2, i3, i4);
+    st.o1[q] = 8u * (uint32_t)i1;
+    st.o2[q] = 8u * (uint32_t)i2;
+    st.i3[q] = (uint32_t)i3;
+    st.rq[q] = rftab + (int64_t)i4 * a.n_tr * 9;
+    st.r1ti[q] = t1ti[i1];
+  }
+  const rsrc_t r1s = make_rsrc(t1tab, a.t1_bytes);
+  const rsrc_t r2s = make_rsrc(t2tab, a.t2_bytes);
+  const rsrc_t rds = make_rsrc(dftab, a.df_bytes);
+  float scale[kQ];
+  double n2[kQ], nb[kQ];
+  if (a.unit_norm) {
+    // two passes: the norm first, then the entries divided by it
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) scale[q] = 1.0f;
+    sim_pass<0, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) scale[q] = n2[q] > 0.0 ? (float)(1.0 / sqrt(n2[q])) : 0.0f;
+    double n2b[kQ];
+    sim_pass<MODE, PK, DF_LDS, true>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2b, nb);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) scale[q] = 1.0f;
+    sim_pass<MODE, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb);
+  }
+  if (a.norm) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int64_t e = blk0 + tid + kThreads * q;
+      // BF16: the norm of the values actually stored
+      if (e < a.count) a.norm[e] = sqrt(MODE == 2 ? nb[q] : n2[q]);
+    }
+  }
+}
+
+template <int MODE, int PK>
+static void launch_sim_variant(const SimArgs& a, const Tables& t, bool df_lds, int64_t blocks,
+                               hipStream_t stream) {
+  const dim3 g((unsigned)blocks), b(kThreads);
+  const size_t lds = df_lds ? 2 * sizeof(float4) * kChunk * (size_t)a.n3 : 0;
+  if (df_lds)
+    hipLaunchKernelGGL((k_sim_dict<MODE, PK, true>), g, b, lds, stream, a, t.t1, t.t2, t.df, t.rf,
+                       t.t1ti);
+  else
+    hipLaunchKernelGGL((k_sim_dict<MODE, PK, false>), g, b, 0, stream, a, t.t1, t.t2, t.df, t.rf,
+                       t.t1ti);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_sim_dict(SimArgs a) {
-  const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (e >= a.count) return;
-  int32_t i1, i2, i3, i4;
-  unravel(a.k0 + e, a.n2, a.n3, a.n4, i1, i2, i3, i4);
-  const float* R = a.rf + (int64_t)i4 * a.n_tr * 9;
-  if (a.n4 == 1) R = wave_uniform(R);
-  float scale = 1.0f;
-  double n2 = 0.0;
-  if (a.unit_norm) {
-    n2 = run_entry<0>(a, i1, i2, i3, R, e, 1.0f);
-    scale = n2 > 0.0 ? (float)(1.0 / sqrt(n2)) : 0.0f;
-  }
-  double stored = 0.0;
-  double n2b = run_entry<MODE>(a, i1, i2, i3, R, e, scale, &stored);
-  if (!a.unit_norm) n2 = n2b;
-  if (MODE == 2) n2 = stored;  // BF16: the norm of the values actually stored
-  if (a.norm) a.norm[e] = sqrt(n2);
+static void launch_sim_mode(const SimArgs& a, const Tables& t, int64_t blocks, hipStream_t stream) {
+  const bool df_lds = a.n3 <= kLdsMaxN3;
+  const bool lane = a.n4 > 1;
+  if (!lane && t.x_axis_pulses)
+    launch_sim_variant<MODE, kXAxisUniform>(a, t, df_lds, blocks, stream);
+  else if (!lane)
+    launch_sim_variant<MODE, kGeneralUniform>(a, t, df_lds, blocks, stream);
+  else if (t.x_axis_pulses)
+    launch_sim_variant<MODE, kXAxisLane>(a, t, df_lds, blocks, stream);
+  else
+    launch_sim_variant<MODE, kGeneralLane>(a, t, df_lds, blocks, stream);
 }
 
 // Fingerprints at arbitrary parameters: the factors are computed per readout
@@ -174,18 +346,24 @@ int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count
                     mrf_dtype dtype, void* re, void* im, int64_t ld, double* norm, int unit_norm,
                     hipStream_t stream) {
   if (count == 0) return MRF_OK;
+  // the step tables are addressed through 32-bit buffer ranges
+  const int64_t nt = t.n_tr;
+  const int64_t b1 = 8 * nt * t.n1, b2 = 8 * nt * t.n2, b3 = 16 * nt * t.n3;
+  if (b1 > INT32_MAX || b2 > INT32_MAX || b3 > INT32_MAX) {
+    set_error("grid axis too long: a step table of n_tr x axis length exceeds 2 GiB");
+    return MRF_ERR_INVALID;
+  }
   SimArgs a;
-  a.t1 = t.t1;
-  a.t1ti = t.t1ti;
-  a.t2 = t.t2;
-  a.df = t.df;
-  a.rf = t.rf;
   a.n_tr = t.n_tr;
   a.n1 = t.n1;
   a.n2 = t.n2;
   a.n3 = t.n3;
   a.n4 = t.n4;
   a.inversion = t.inversion;
+  a.unit_norm = unit_norm;
+  a.t1_bytes = (int32_t)b1;
+  a.t2_bytes = (int32_t)b2;
+  a.df_bytes = (int32_t)b3;
   a.k0 = k0;
   a.count = count;
   a.ld = ld;
@@ -193,17 +371,16 @@ int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count
   a.im = (float*)im;
   a.packed = (uint4*)re;
   a.norm = norm;
-  a.unit_norm = unit_norm;
-  const int64_t blocks = (count + 255) / 256;
+  const int64_t blocks = (count + kBlockEntries - 1) / kBlockEntries;
   if (blocks > INT32_MAX) {
     set_error("too many entries in one call");
     return MRF_ERR_INVALID;
   }
   ProfScope prof(ctx, "k_sim_dict", stream);
   if (dtype == MRF_F32)
-    hipLaunchKernelGGL(k_sim_dict<1>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    launch_sim_mode<1>(a, t, blocks, stream);
   else
-    hipLaunchKernelGGL(k_sim_dict<2>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    launch_sim_mode<2>(a, t, blocks, stream);
   MRF_HIP(hipGetLastError());
   return MRF_OK;
 }

@@ -124,6 +124,46 @@ def test_signals_at_grid_points_equal_entries_and_oracle(ctx, orc):
         assert np.linalg.norm(_unit(sig[i]) - _unit(ref)) < UNIT_L2_TOL
 
 
+def _general_phase_seq(n, seed):
+    """Sequence with arbitrary RF phases (pulses not about the x axis)."""
+    base = I.make_sequence(n, seed)
+    ph = np.random.default_rng(seed + 1000).uniform(0.0, 360.0, n)
+    return I.Sequence(base.fa_deg, ph, base.tr_ms, base.te_ms, 1, 0.0)
+
+
+@pytest.mark.parametrize("n3,b1", [(150, None), (150, [0.9, 1.1]), (21, None), (21, [0.8, 1.0, 1.2])])
+def test_dictionary_general_phases_both_df_paths(ctx, orc, n3, b1):
+    """General pulse matrices (uniform and per-lane), df axis staged through LDS
+    (21 values) and read directly (150), a readout count that is not a multiple
+    of the staging chunk; FP32, BF16 and unit-norm outputs; signals at grid
+    points equal the entries bit for bit."""
+    from paper_1506_05393_amd import api
+    seq = _general_phase_seq(62, 7)
+    axes = [[300.0, 700.0, 1500.0, 2500.0], [30.0, 80.0, 250.0], I.grid_linspace(-60, 60, n3)]
+    grid = I.make_grid(*axes, b1) if b1 else I.make_grid(*axes)
+    sq = api.Sequence(ctx, seq)
+    d = api.simulate_dictionary(ctx, sq, grid, dtype="f32")
+    u = api.simulate_dictionary(ctx, sq, grid, dtype="f32", unit_norm=True)
+    d16 = api.simulate_dictionary(ctx, sq, grid, n_tr=60, dtype="bf16")
+    torch.cuda.synchronize()
+    gpu = _gpu_entries(d, grid.size)
+    ref, nref = orc.simulate_grid(seq, grid, threads=8)
+    assert np.linalg.norm(_unit(gpu) - _unit(ref), axis=1).max() < UNIT_L2_TOL
+    assert np.max(np.abs(d.norm.cpu().numpy() - nref) / nref) < 5e-6
+    gu = _gpu_entries(u, grid.size)
+    assert np.linalg.norm(gu - _unit(ref), axis=1).max() < UNIT_L2_TOL
+    g16 = _gpu_entries(d16, grid.size)
+    r60 = ref[:, :60]
+    assert np.all(np.abs(g16.real - r60.real) <= np.abs(r60.real) * 2.0 ** -8 + 1e-6)
+    assert np.all(np.abs(g16.imag - r60.imag) <= np.abs(r60.imag) * 2.0 ** -8 + 1e-6)
+    # the BF16 norm is the norm of the stored values
+    assert np.allclose(d16.norm.cpu().numpy(), np.linalg.norm(g16, axis=1), rtol=1e-6)
+    ks = np.array([0, 1, grid.size // 2, grid.size - 1])
+    params = np.stack([np.array(grid.values(k), dtype=np.float64) for k in ks])
+    sig = api.simulate_signals(ctx, sq, to_dev(params)).cpu().numpy()
+    assert np.array_equal(sig, gpu[ks].astype(np.complex64))
+
+
 def test_closed_forms_on_gpu(ctx):
     """Flip angle zero gives no signal; first sample closed form; bSSFP steady state."""
     from paper_1506_05393_amd import api
