@@ -101,7 +101,8 @@ int64_t mrf_grid_size(const mrf_grid* grid);
  * Simulates entries [entry_begin, entry_begin + entry_count) of `grid` over
  * the first n_tr readouts (n_tr <= sequence n). FP32 state; the relaxation
  * and precession factors are computed once per grid value in FP64 and
- * rounded to FP32; the norm is accumulated in FP64.
+ * rounded to FP32; the norm accumulates FP32 partial sums of four readouts
+ * in FP64.
  *
  * Layouts (entry e = k - entry_begin, 0 <= e < entry_count <= ld):
  *   MRF_F32  : planar, time-major. re[j*ld + e] = Re d_j, im[j*ld + e] = Im d_j,
@@ -255,6 +256,105 @@ int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* g
                     const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
                     int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                     mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over resident dictionaries (not part of the paper,
+ * whose searches are one slice at a time; it serves the same two searches,
+ * brute force (Theory Eq. 1 over the whole grid) and MRF-ZOOM (Theory: MRF
+ * ZOOM; Methods: Experiment 2), to many slices that arrive over time).
+ *
+ * The server owns one scheduler thread and n_streams device streams.
+ *   - mrf_server_register builds a slot: the sequence's dictionary over a
+ *     grid, simulated once at the longest registered readout count and kept
+ *     in HBM, plus the per-entry norms of every registered shorter prefix
+ *     (computed from the stored values, identical to the norms a dictionary
+ *     of that length gets from mrf_simulate_dictionary).
+ *   - mrf_serve_submit is non-blocking. A request whose buffers could never
+ *     fit in the budget beside the resident dictionaries is rejected at once
+ *     (MRF_ERR_REJECTED, no ticket).
+ *   - Admission is first-in first-out by HBM footprint: the head request is
+ *     admitted when the footprints of all admitted requests plus its own fit
+ *     in hbm_budget_bytes minus the resident bytes and fewer than max_inflight
+ *     requests are admitted; later requests never overtake it.
+ *   - Continuous batching: whenever a stream is idle, the admitted requests
+ *     that share the oldest one's (slot, mode, n_tr) form one batch (up to
+ *     max_batch_vox voxels): their voxels are gathered into one matrix, one
+ *     search runs over it, and the results are scattered to each request's
+ *     outputs. Requests that arrive while others run join the next batch on
+ *     the next free stream, so brute-force and ZOOM batches overlap on the
+ *     device.
+ *   - Brute force: FP32 slots search with top_k = 2 (the margin needs the
+ *     runner-up); BF16 slots search with top_k = 8 and FP32 re-scoring.
+ *     ZOOM: the slot's grid with mrf_zoom_schedule_paper, no prior.
+ * Each voxel's result depends only on that voxel and the slot: a request's
+ * outputs are the same alone and in any mix.
+ *
+ * Ownership: vox and the out arrays are caller device memory and must stay
+ * valid until mrf_serve_poll reports DONE, FAILED or CANCELLED. Requests are
+ * remembered for the server's lifetime (a few hundred bytes each).
+ * ---------------------------------------------------------------------- */
+typedef struct mrf_server mrf_server;
+
+typedef enum { MRF_SERVE_BRUTE = 0, MRF_SERVE_ZOOM = 1 } mrf_serve_mode;
+typedef enum {
+  MRF_REQ_QUEUED = 0,    /* submitted, waiting for admission or a stream */
+  MRF_REQ_RUNNING = 1,   /* its batch is on the device */
+  MRF_REQ_DONE = 2,
+  MRF_REQ_FAILED = 3,    /* the batch failed; mrf_serve_poll sets mrf_last_error */
+  MRF_REQ_CANCELLED = 4
+} mrf_request_state;
+
+typedef struct {
+  size_t hbm_budget_bytes;   /* resident dictionaries + buffers of admitted requests */
+  int32_t max_inflight;      /* admitted requests (waiting for a stream or running), >= 1 */
+  int32_t n_streams;         /* device streams, one batch in flight on each, >= 1 */
+  int32_t max_batch_vox;     /* voxels per batch; 0 = 65536 */
+  /* Host-simulated device for testing the scheduler without a GPU: no device
+   * work at all and the outputs are never written; registration allocates
+   * nothing; a batch takes fake_ns_per_byte x its buffer bytes of wall time;
+   * the batch holding ticket fake_fail_ticket (0 = none) fails. ctx and the
+   * sequence may be NULL. */
+  int32_t fake_device;
+  double fake_ns_per_byte;
+  uint64_t fake_fail_ticket;
+} mrf_server_config;
+
+typedef struct {
+  int32_t mode;        /* mrf_serve_mode */
+  int32_t slot;
+  int32_t n_tr;        /* readouts used; brute force: one of the slot's lengths;
+                          ZOOM: any value up to the longest */
+  int32_t n_vox;       /* >= 0; 0 completes at submission */
+  const void* vox;     /* complex64 [n_vox][ld_vox] device */
+  int64_t ld_vox;      /* >= n_tr */
+  mrf_result_view out; /* idx required; n_sim filled by ZOOM requests */
+} mrf_request;
+
+typedef struct {
+  size_t budget_bytes, resident_bytes, reserved_bytes, peak_reserved_bytes, arena_peak_bytes;
+  int64_t submitted, rejected, done, failed, cancelled, batches, max_batch_requests;
+  int32_t peak_inflight;
+} mrf_server_stats;
+
+int mrf_server_create(mrf_context* ctx, const mrf_server_config* cfg, mrf_server** out);
+/* n_tr: n_lengths readout counts (each <= the sequence length; multiples of
+ * 4 for BF16). Blocks until the dictionary is built. MRF_ERR_REJECTED if the
+ * dictionary does not fit in the budget. */
+int mrf_server_register(mrf_server* srv, const mrf_sequence* seq, const mrf_grid* grid,
+                        mrf_dtype dtype, const int32_t* n_tr, int32_t n_lengths, int32_t* slot);
+int mrf_serve_submit(mrf_server* srv, const mrf_request* req, uint64_t* ticket);
+/* Non-blocking. Times in ms since the server was created (host clock);
+ * t_start is when the request's batch was launched, t_done when its
+ * completion was observed (-1 while unknown). Unknown ticket: MRF_ERR_INVALID. */
+int mrf_serve_poll(mrf_server* srv, uint64_t ticket, int32_t* state, double* t_submit_ms,
+                   double* t_start_ms, double* t_done_ms);
+/* Cancels a QUEUED request (its state becomes CANCELLED and its admission
+ * reservation is released). A RUNNING request cannot be cancelled
+ * (MRF_ERR_NOT_READY); on a finished one this is a no-op (MRF_OK). */
+int mrf_serve_cancel(mrf_server* srv, uint64_t ticket);
+int mrf_server_stats_read(mrf_server* srv, mrf_server_stats* out);
+/* Drains: waits for every submitted request to finish, then frees the slots. */
+int mrf_server_destroy(mrf_server* srv);
 
 /* ------------------------------------------------------------------------
  * Kernel timing. When enabled, every launch of a named kernel

@@ -133,3 +133,44 @@ _SIGS += [
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
       C.c_void_p]),
 ]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int32),
+                ("n_streams", C.c_int32), ("max_batch_vox", C.c_int32),
+                ("fake_device", C.c_int32), ("fake_ns_per_byte", C.c_double),
+                ("fake_fail_ticket", C.c_uint64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("slot", C.c_int32), ("n_tr", C.c_int32),
+                ("n_vox", C.c_int32), ("vox", C.c_void_p), ("ld_vox", C.c_int64),
+                ("out", ResultView)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("budget_bytes", C.c_size_t), ("resident_bytes", C.c_size_t),
+                ("reserved_bytes", C.c_size_t), ("peak_reserved_bytes", C.c_size_t),
+                ("arena_peak_bytes", C.c_size_t), ("submitted", C.c_int64),
+                ("rejected", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
+                ("cancelled", C.c_int64), ("batches", C.c_int64),
+                ("max_batch_requests", C.c_int64), ("peak_inflight", C.c_int32)]
+
+
+SERVE_BRUTE, SERVE_ZOOM = 0, 1
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
+_SIGS += [
+    ("mrf_server_create", C.c_int,
+     [C.c_void_p, C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    ("mrf_server_register", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int, C.POINTER(C.c_int32), C.c_int32,
+      C.POINTER(C.c_int32)]),
+    ("mrf_serve_submit", C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    ("mrf_serve_poll", C.c_int,
+     [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("mrf_serve_cancel", C.c_int, [C.c_void_p, C.c_uint64]),
+    ("mrf_server_stats_read", C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    ("mrf_server_destroy", C.c_int, [C.c_void_p]),
+]

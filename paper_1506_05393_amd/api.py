@@ -328,3 +328,108 @@ def zoom_search(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, sched: Opt
         init.data_ptr() if init is not None else None, _result_view(r), buf.data_ptr(),
         buf.numel(), _stream_ptr(stream)))
     return r
+
+
+# ------------------------------------------------------------- serving -----
+
+class Server:
+    """Request loop over resident dictionaries (libmrf mrf_server_*).
+
+    fake=True runs the scheduler against a host-simulated device (no GPU, no
+    outputs written): requests then need only n_vox, not tensors."""
+
+    def __init__(self, ctx: Optional[Context], budget_bytes: int, max_inflight: int = 64,
+                 n_streams: int = 2, max_batch_vox: int = 0, fake: bool = False,
+                 fake_ns_per_byte: float = 0.0, fake_fail_ticket: int = 0):
+        self._lib = L.load()
+        self.ctx = ctx
+        cfg = L.ServerConfig(int(budget_bytes), int(max_inflight), int(n_streams),
+                             int(max_batch_vox), int(bool(fake)), float(fake_ns_per_byte),
+                             int(fake_fail_ticket))
+        h = C.c_void_p()
+        L.check(self._lib.mrf_server_create(ctx.handle if ctx is not None else None,
+                                            C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self.fake = bool(fake)
+        self._keep = {}    # ticket -> tensors that must outlive the request
+        self._grids = []
+
+    def register(self, seq: Optional[Sequence], grid, dtype: str = "bf16", lengths=(1000,)) -> int:
+        g = grid if isinstance(grid, GridArg) else GridArg(grid)
+        self._grids.append(g)
+        n = (C.c_int32 * len(lengths))(*[int(x) for x in lengths])
+        slot = C.c_int32()
+        L.check(self._lib.mrf_server_register(
+            self.handle, seq.handle if seq is not None else None, g.ptr,
+            L.MRF_F32 if dtype == "f32" else L.MRF_BF16, n, len(lengths), C.byref(slot)))
+        return int(slot.value)
+
+    def submit(self, mode: str, slot: int, n_tr: int, vox: Optional[torch.Tensor] = None,
+               out: Optional[dict] = None, n_vox: Optional[int] = None) -> int:
+        """mode 'brute' or 'zoom'. vox: complex64 cuda [n_vox, >= n_tr]; out: result
+        tensors (see _result_tensors; created if None). Returns the ticket."""
+        m = L.SERVE_BRUTE if mode == "brute" else L.SERVE_ZOOM
+        if vox is not None:
+            if vox.dtype != torch.complex64 or not vox.is_cuda or vox.stride(1) != 1:
+                raise ValueError("vox must be a complex64 CUDA tensor with contiguous rows")
+            nv = vox.shape[0]
+            r = out if out is not None else _result_tensors(nv, vox.device, with_nsim=m == 1)
+            req = L.Request(m, slot, n_tr, nv, vox.data_ptr(), vox.stride(0), _result_view(r))
+        else:
+            if not self.fake:
+                raise ValueError("vox is required on a real device")
+            nv, r = int(n_vox), None
+            dummy = 1 << 12  # never dereferenced by the fake device
+            req = L.Request(m, slot, n_tr, nv, dummy, n_tr, L.ResultView(dummy))
+        t = C.c_uint64()
+        L.check(self._lib.mrf_serve_submit(self.handle, C.byref(req), C.byref(t)))
+        self._keep[int(t.value)] = (vox, r)
+        return int(t.value)
+
+    def result(self, ticket: int) -> Optional[dict]:
+        return self._keep[ticket][1]
+
+    def poll(self, ticket: int):
+        """(state, t_submit_ms, t_start_ms, t_done_ms); raises MRFError for a failed request."""
+        st, a, b, c = C.c_int32(), C.c_double(), C.c_double(), C.c_double()
+        L.check(self._lib.mrf_serve_poll(self.handle, int(ticket), C.byref(st), C.byref(a),
+                                         C.byref(b), C.byref(c)))
+        state = L.REQ_STATES[st.value]
+        return state, a.value, b.value, c.value
+
+    def failure(self, ticket: int) -> str:
+        self.poll(ticket)
+        return self._lib.mrf_last_error().decode(errors="replace")
+
+    def cancel(self, ticket: int):
+        L.check(self._lib.mrf_serve_cancel(self.handle, int(ticket)))
+
+    def stats(self) -> dict:
+        s = L.ServerStats()
+        L.check(self._lib.mrf_server_stats_read(self.handle, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in L.ServerStats._fields_}
+
+    def wait(self, tickets, timeout_s: float = 60.0, sleep_s: float = 0.0005):
+        import time
+        t_end = time.monotonic() + timeout_s
+        pending = set(tickets)
+        while pending:
+            for t in list(pending):
+                if self.poll(t)[0] in ("done", "failed", "cancelled"):
+                    pending.discard(t)
+            if pending:
+                if time.monotonic() > t_end:
+                    raise TimeoutError(f"{len(pending)} requests still pending")
+                time.sleep(sleep_s)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.mrf_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,133 @@
+"""Serving on the GPU: every request's outputs are the same alone and in a mix
+of concurrent brute-force (BF16 with FP32 re-scoring, FP32) and MRF-ZOOM
+batches, and equal the direct entry points on a dictionary simulated at the
+request's readout count (prefix norms identical to a dictionary of that
+length). Stated tolerance: same index, |dCC| <= 1e-6; bitwise is the target
+and is reported."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1506_05393_amd import inputs as I
+from tests.gpu_common import need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+GB = 1 << 30
+
+
+@pytest.fixture(scope="module")
+def env():
+    need_gpu()
+    from paper_1506_05393_amd import api
+    ctx = api.Context(0)
+    seqs = [I.make_sequence(200, 2), I.make_sequence(200, 3)]
+    grid = I.make_grid(I.grid_linspace(100, 2000, 40), I.grid_geomspace(20, 400, 30),
+                       I.grid_arange(-20, 20, 4))
+    sqs = [api.Sequence(ctx, s) for s in seqs]
+    return api, ctx, sqs, grid
+
+
+def _voxels(api, ctx, sq, grid, n, seed):
+    rng = np.random.default_rng(seed)
+    p = np.stack([rng.uniform(150, 1900, n), rng.uniform(25, 380, n), rng.uniform(-19, 19, n),
+                  np.ones(n)], axis=1)
+    s = api.simulate_signals(ctx, sq, torch.tensor(p, device="cuda"))
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    noise = torch.randn(s.shape, dtype=torch.complex64, device="cuda", generator=g)
+    sigma = s.abs().pow(2).mean(dim=1, keepdim=True).sqrt() / 20
+    return (s + sigma * noise).contiguous()
+
+
+def _requests(api, ctx, sqs, grid):
+    """(mode, slot, n_tr, vox): both modes, both slots, ragged voxel counts."""
+    spec = [("brute", 0, 200, 256), ("zoom", 1, 200, 300), ("brute", 1, 200, 64),
+            ("brute", 0, 100, 513), ("zoom", 0, 100, 128), ("brute", 0, 200, 1024),
+            ("zoom", 0, 200, 77), ("brute", 1, 200, 700), ("zoom", 1, 150, 256),
+            ("brute", 0, 100, 33), ("zoom", 0, 200, 1000), ("brute", 0, 200, 5)]
+    return [(m, s, n, _voxels(api, ctx, sqs[s], grid, nv, 100 + i))
+            for i, (m, s, n, nv) in enumerate(spec)]
+
+
+def _run(srv, reqs, gap_s=0.0):
+    tickets = []
+    for m, slot, n_tr, vox in reqs:
+        tickets.append(srv.submit(m, slot, n_tr, vox))
+        if gap_s:
+            time.sleep(gap_s)
+    srv.wait(tickets, timeout_s=90)
+    for t in tickets:
+        assert srv.poll(t)[0] == "done", srv.failure(t)
+    torch.cuda.synchronize()
+    return tickets, [{k: v.cpu().numpy() for k, v in srv.result(t).items()} for t in tickets]
+
+
+def _same(a, b, name):
+    assert np.array_equal(a["idx"], b["idx"]), name
+    for k in ("cc", "margin", "pd_re", "pd_im"):
+        assert np.max(np.abs(a[k] - b[k]), initial=0) <= 1e-6, (name, k)
+    if "n_sim" in a and "n_sim" in b:
+        assert np.array_equal(a["n_sim"], b["n_sim"]), name
+    return all(np.array_equal(a[k], b[k]) for k in ("cc", "margin", "pd_re", "pd_im"))
+
+
+def test_alone_equals_mix_equals_direct(env):
+    api, ctx, sqs, grid = env
+    srv = api.Server(ctx, 4 * GB, max_inflight=32, n_streams=2, max_batch_vox=4096)
+    try:
+        slots = [srv.register(sqs[0], grid, "bf16", lengths=(100, 200)),
+                 srv.register(sqs[1], grid, "f32", lengths=(200,))]
+        assert slots == [0, 1]
+        reqs = _requests(api, ctx, sqs, grid)
+        alone = []
+        for q in reqs:  # one at a time: nothing else on the device
+            alone += _run(srv, [q])[1]
+        tickets, mix = _run(srv, reqs)  # all at once: batched and overlapped
+        st = srv.stats()
+        times = [srv.poll(t) for t in tickets]
+    finally:
+        srv.close()
+    bitwise = sum(_same(a, b, f"request {i}") for i, (a, b) in enumerate(zip(alone, mix)))
+    print(f"mix vs alone: {bitwise}/{len(reqs)} requests bitwise equal; "
+          f"{st['batches']} batches, max {st['max_batch_requests']} requests per batch")
+    assert st["max_batch_requests"] > 1 and st["failed"] == 0
+    assert st["peak_reserved_bytes"] <= st["budget_bytes"] - st["resident_bytes"]
+    # brute-force and ZOOM batches overlapped on the two streams
+    modes = [q[0] for q in reqs]
+    iv = [(t[2], t[3]) for t in times]
+    assert any(iv[i][0] < iv[j][1] and iv[j][0] < iv[i][1]
+               for i in range(len(reqs)) for j in range(len(reqs)) if modes[i] != modes[j])
+
+    # direct entry points, dictionary simulated at the request's own length
+    dicts = {}
+    for i, (m, slot, n_tr, vox) in enumerate(reqs):
+        sq, dt = sqs[slot], ("bf16", "f32")[slot]
+        if m == "brute":
+            if (slot, n_tr) not in dicts:
+                dicts[(slot, n_tr)] = api.simulate_dictionary(ctx, sq, grid, n_tr=n_tr, dtype=dt)
+            d = dicts[(slot, n_tr)]
+            r = (api.match_bruteforce(ctx, d, vox, top_k=8, seq=sq, grid=grid) if dt == "bf16"
+                 else api.match_bruteforce(ctx, d, vox, top_k=2))
+        else:
+            r = api.zoom_search(ctx, sq, grid, vox, n_tr=n_tr)
+        torch.cuda.synchronize()
+        ref = {k: v.cpu().numpy() for k, v in r.items() if not k.startswith("_")}
+        _same(ref, alone[i], f"direct vs served request {i}")
+
+
+def test_server_keeps_serving_after_an_invalid_request(env):
+    """A request for a readout count the slot was not registered with is
+    refused at submission; the next request is served."""
+    api, ctx, sqs, grid = env
+    srv = api.Server(ctx, 1 * GB, n_streams=1)
+    try:
+        slot = srv.register(sqs[0], grid, "f32", lengths=(200,))
+        vox = _voxels(api, ctx, sqs[0], grid, 40, 7)
+        with pytest.raises(Exception):
+            srv.submit("brute", slot, 150, vox)  # length not registered
+        t = srv.submit("zoom", slot, 200, vox)
+        srv.wait([t])
+        assert srv.poll(t)[0] == "done"
+    finally:
+        srv.close()
