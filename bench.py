@@ -31,6 +31,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="target CPU time of the oracle sample")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    p.add_argument("--copy-probe-gb", type=float, default=0.0,
+                   help="only run a plain device copy of this size (3 times), the reference "
+                        "for scaling HBM byte counters, and exit")
+    p.add_argument("--serve-requests", type=int, default=60)
+    p.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     return p.parse_args()
 
 
@@ -53,6 +59,104 @@ def make_inputs(api, ctx, sq, w, torch):
     rms = clean.abs().pow(2).mean(dim=1).sqrt()
     sigma = torch.from_numpy(ph.mag.astype(np.float32)).cuda() * rms / ph.snr
     return (scale[:, None] * clean + sigma[:, None] * noise).contiguous()
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters__slice64x64_N1000_E12636729.md")
+
+
+def counted_traffic(kernel: str, source: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when the kernel's source has
+    changed since the counters were taken (or no summary exists)."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    now = hashlib.sha256(open(os.path.join(ROOT, "paper_1506_05393_amd", "csrc", source),
+                              "rb").read()).hexdigest()
+    if f"csrc/{source}: {now}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == kernel:
+            return float(cells[6])
+    return None
+
+
+def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
+    """Request stream through the server: Poisson arrivals at `rate`/s, slices of
+    32^2, 64^2, 96^2 or 128^2 voxels, N in {500, 1000}, three sequences
+    (seeds 2-4) with resident BF16 dictionaries over a 1.6M-entry grid, half
+    brute force (BF16 + FP32 re-scoring), half MRF-ZOOM (simulated on the fly).
+    Latency = completion observed by the server - submission."""
+    from paper_1506_05393_amd import inputs as I
+    from paper_1506_05393_amd import workloads as W
+    grid = W.serving_grid()
+    seqs = [api.Sequence(ctx, I.make_sequence(1000, s)) for s in (2, 3, 4)]
+    sizes = [32, 64, 96, 128]
+    rng = np.random.default_rng(seed)
+    # voxel pools: in-grid parameters, GPU-simulated signals, SNR 30 noise
+    pools = {}
+    for si, sq in enumerate(seqs):
+        for n in sizes:
+            nv = n * n
+            p = np.stack([rng.uniform(120, 3900, nv), rng.uniform(12, 1900, nv),
+                          rng.uniform(-39, 39, nv), np.ones(nv)], axis=1)
+            sig = api.simulate_signals(ctx, sq, torch.tensor(p, device="cuda"))
+            g = torch.Generator(device="cuda").manual_seed(seed * 1000 + si * 10 + n)
+            noise = torch.randn(sig.shape, dtype=torch.complex64, device="cuda", generator=g)
+            sigma = sig.abs().pow(2).mean(dim=1, keepdim=True).sqrt() / 30
+            pools[(si, n)] = (sig + sigma * noise).contiguous()
+    resident = 3 * ((grid.size + 255) // 256 * 256 * 250 * 16 + 2 * grid.size * 8)
+    budget = resident + 24 * (1 << 30)
+    srv = api.Server(ctx, budget, max_inflight=64, n_streams=2)
+    try:
+        slots = [srv.register(sq, grid, "bf16", lengths=(500, 1000)) for sq in seqs]
+        warm = [srv.submit(m, s, n, pools[(s, 32)]) for m in ("brute", "zoom") for s in slots
+                for n in (500, 1000)]
+        srv.wait(warm, timeout_s=120)
+        st0 = srv.stats()
+        trace = []
+        t = 0.0
+        for _ in range(n_req):
+            t += rng.exponential(1.0 / rate)
+            trace.append((t, ("brute", "zoom")[rng.integers(2)], int(rng.integers(3)),
+                          int(rng.choice([500, 1000])), int(rng.choice(sizes))))
+        tickets, meta = [], []
+        t0 = time.perf_counter()
+        for at, mode, s, n_tr, n in trace:
+            d = at - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets.append(srv.submit(mode, slots[s], n_tr, pools[(s, n)]))
+            meta.append((mode, n * n))
+        srv.wait(tickets, timeout_s=600)
+        polls = [srv.poll(tk) for tk in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array([p[3] - p[1] for p in polls])
+    span_s = (max(p[3] for p in polls) - min(p[1] for p in polls)) * 1e-3
+    vox = sum(m[1] for m in meta)
+    by_mode = {m: np.array([lat[i] for i in range(n_req) if meta[i][0] == m]) for m in ("brute", "zoom")}
+    return {
+        "workload": f"Poisson {rate:g} req/s, {n_req} requests, sizes 32^2..128^2, N in {{500,1000}}, "
+                    f"3 sequences, grid {grid.size} entries, BF16 resident, half brute / half ZOOM",
+        "failed": int(sum(p[0] != "done" for p in polls)),
+        "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_ms_p50_by_mode": {m: float(np.percentile(v, 50)) for m, v in by_mode.items() if len(v)},
+        "latency_ms_p99_by_mode": {m: float(np.percentile(v, 99)) for m, v in by_mode.items() if len(v)},
+        "voxels_per_s": vox / span_s,
+        "requests_per_s": n_req / span_s,
+        "offered_requests_per_s": rate,
+        "batches": int(st["batches"] - st0["batches"]),
+        "max_batch_requests": int(st["max_batch_requests"]),
+        "resident_GB": st["resident_bytes"] / 1e9,
+        "peak_reserved_GB": st["peak_reserved_bytes"] / 1e9,
+        "budget_GB": st["budget_bytes"] / 1e9,
+    }
 
 
 def cpu_baseline(w, target_s: float):
@@ -85,8 +189,24 @@ def cpu_baseline(w, target_s: float):
                       f"in {dt:.1f} s, extrapolated to {w.grid.size} entries"}
 
 
+def copy_probe(gb: float):
+    """y = x * 1 over `gb` GB of float32: an elementwise kernel that reads and
+    writes exactly gb GB, to scale FETCH_SIZE / WRITE_SIZE counter readings."""
+    import torch
+    n = int(gb * 1e9) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}))
+
+
 def main():
     args = parse()
+    if args.copy_probe_gb > 0:
+        copy_probe(args.copy_probe_gb)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -201,7 +321,8 @@ def main():
                            "BF16 + brute-force BF16 with top-8 FP32 re-scoring + MRF-ZOOM"},
         "roofline": {"bound": "mfma", "kernel": "k_match_f32", "achieved": achieved,
                      "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp32_mfma_tflops"], "traffic": None,
+                     "frac": achieved / PEAK["fp32_mfma_tflops"],
+                     "traffic": counted_traffic("mrf::k_match_f32", "match.hip"),
                      "avg_ms": gemm_avg, "launches": gemm_n,
                      "algorithmic_flops_per_launch": flops},
         "rows_ms": {k: float(np.median(v)) for k, v in per_row.items()},
@@ -222,6 +343,7 @@ def main():
         "dict_gen": {"kernel": "k_sim_dict", "f32_ms": sim_avg,
                      "f32_GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
                      "f32_frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"],
+                     "f32_traffic": counted_traffic("mrf::k_sim_dict<1, 1, true>", "sim.hip"),
                      "bf16_ms": float(np.median(per_row["dict_bf16"])),
                      "bf16_GB_per_s": (E * N * 4 + E * 8) /
                                       (float(np.median(per_row["dict_bf16"])) * 1e-3) / 1e9},
@@ -235,6 +357,11 @@ def main():
         "paper_context": "paper: 116.72 s per 1731-voxel 64x64 slice (ZOOM, df dictionary) on a "
                          "2.0 GHz dual-core laptop, C++",
     }
+    if not args.no_serve:
+        log("serving ...")
+        res["serving"] = serve_bench(api, ctx, torch, args.serve_requests, args.serve_rate)
+        log(f"serving done: p50 {res['serving']['latency_ms_p50']:.1f} ms, "
+            f"p99 {res['serving']['latency_ms_p99']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
