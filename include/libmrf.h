@@ -171,7 +171,9 @@ int mrf_match_workspace(mrf_context* ctx, const mrf_dict_view* dict, int32_t n_v
 /* top_k in [1, 64]: the kept candidate list per voxel (at least 2 internally
  * for the margin). With a BF16 dictionary top_k must be >= 2 and seq/grid
  * are required: the top_k BF16 candidates of each voxel are re-simulated in
- * FP32 and re-scored exactly, and the best of them is returned. topk_idx /
+ * FP32 (the values an FP32 dictionary stores) and re-scored with an FP32 dot
+ * product under compensated summation (error ~1 FP32 ulp of the sum), and the
+ * best of them is returned. topk_idx /
  * topk_cc (device [n_vox][top_k], optional) receive the candidate list
  * (FP32: exact scores; BF16: the BF16 GEMM's CC estimates). */
 int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* dict, const void* vox,
@@ -244,6 +246,14 @@ typedef struct {
 int mrf_zoom_schedule_paper(const mrf_grid* grid, const mrf_sequence* seq,
                             mrf_zoom_schedule* out);
 
+/* Local refinement (not a schedule of the paper: its finest-resolution
+ * steps, Methods Experiment 2 step 5, used alone): unit-step 2-D zoom on
+ * (T1, T2), unit-step 1-D zoom on df (and on B1 with a B1 axis), repeated
+ * while the centre moves, up to outer_max rounds. Run with init_idx = a
+ * brute-force result it climbs to the local CC maximum next to it; without
+ * init it starts at the grid centre. */
+int mrf_zoom_schedule_local(const mrf_grid* grid, int32_t outer_max, mrf_zoom_schedule* out);
+
 int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_t n_vox, int32_t n_tr,
                        size_t* bytes);
 
@@ -256,6 +266,15 @@ int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* g
                     const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
                     int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                     mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
+
+/* As mrf_zoom_search, with each voxel's prior centre given as a flat grid
+ * index (device int64 [n_vox], e.g. the idx output of mrf_match_bruteforce;
+ * a negative index starts at the grid origin). With mrf_zoom_schedule_local
+ * this refines a brute-force result to the local CC maximum next to it. */
+int mrf_zoom_search_from(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                         const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                         int64_t ld_vox, int32_t n_tr, const int64_t* start_idx,
+                         mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop over resident dictionaries (not part of the paper,

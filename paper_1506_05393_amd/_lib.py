@@ -126,9 +126,15 @@ class ZoomSchedule(C.Structure):
 _SIGS += [
     ("mrf_zoom_schedule_paper", C.c_int,
      [C.POINTER(GridDesc), C.c_void_p, C.POINTER(ZoomSchedule)]),
+    ("mrf_zoom_schedule_local", C.c_int,
+     [C.POINTER(GridDesc), C.c_int32, C.POINTER(ZoomSchedule)]),
     ("mrf_zoom_workspace", C.c_int,
      [C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     ("mrf_zoom_search", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
+      C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
+    ("mrf_zoom_search_from", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
       C.c_void_p]),

@@ -301,13 +301,38 @@ def schedule_paper(ctx: Context, seq: Sequence, grid) -> dict:
     return schedule_to_dict(s)
 
 
+def schedule_local(grid, outer_max: int = 8) -> dict:
+    """Unit-step local refinement schedule (see mrf_zoom_schedule_local)."""
+    lib = L.load()
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    s = L.ZoomSchedule()
+    L.check(lib.mrf_zoom_schedule_local(g.ptr, int(outer_max), C.byref(s)))
+    return schedule_to_dict(s)
+
+
+def grid_indices(grid, idx) -> np.ndarray:
+    """Flat grid indices -> int32 [n, 4] per-axis indices (the init_idx layout)."""
+    gr = grid.grid if isinstance(grid, GridArg) else grid
+    k = np.asarray(idx, dtype=np.int64)
+    n4 = max(len(gr.b1), 1)
+    n3, n2 = len(gr.df_hz), len(gr.t2_ms)
+    i4 = k % n4
+    k = k // n4
+    i3 = k % n3
+    k = k // n3
+    i2 = k % n2
+    i1 = k // n2
+    return np.stack([i1, i2, i3, i4], axis=1).astype(np.int32)
+
+
 def zoom_search(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, sched: Optional[dict] = None,
                 n_tr: Optional[int] = None, init: Optional[torch.Tensor] = None,
                 workspace: Optional[Workspace] = None, out: Optional[dict] = None,
-                stream=None) -> dict:
+                stream=None, start: Optional[torch.Tensor] = None) -> dict:
     """MRF-ZOOM per voxel. vox: complex64 cuda [n_vox, >= n_tr]; init: int32 cuda
-    [n_vox, 4] prior centres. Returns idx, cc, margin (min decision margin),
-    pd_re, pd_im, n_sim."""
+    [n_vox, 4] prior centres, or start: int64 cuda [n_vox] prior centres as flat
+    grid indices. Returns idx, cc, margin (min decision margin), pd_re, pd_im,
+    n_sim."""
     if vox.dtype != torch.complex64 or not vox.is_cuda or vox.stride(1) != 1:
         raise ValueError("vox must be a complex64 CUDA tensor with contiguous rows")
     n_tr = seq.n if n_tr is None else int(n_tr)
@@ -320,6 +345,15 @@ def zoom_search(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, sched: Opt
     ws = workspace if workspace is not None else Workspace(ctx.device)
     buf = ws.get(int(nb.value))
     r = out if out is not None else _result_tensors(n_vox, ctx.device, with_nsim=True)
+    if start is not None:
+        # prior centres as flat grid indices (e.g. a brute-force idx output)
+        start = start.to(device=ctx.device, dtype=torch.int64).contiguous()
+        r["_start"] = start
+        L.check(ctx._lib.mrf_zoom_search_from(
+            ctx.handle, seq.handle, g.ptr, C.byref(s), vox.data_ptr(), n_vox, vox.stride(0),
+            n_tr, start.data_ptr(), _result_view(r), buf.data_ptr(), buf.numel(),
+            _stream_ptr(stream)))
+        return r
     if init is not None:
         init = init.to(device=ctx.device, dtype=torch.int32).contiguous()
         r["_init"] = init

@@ -277,6 +277,14 @@ struct RescoreArgs {
   float* topk_cc;
 };
 
+// s + c += x, with the rounding error of the addition kept in c (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
+  const float t = s + x;
+  const float z = t - s;
+  c += (s - (t - z)) + (x - z);
+  s = t;
+}
+
 __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
   const int lane = threadIdx.x;
   const int v = blockIdx.x * 8 + (lane >> 3);
@@ -284,7 +292,11 @@ __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
   const bool active = v < a.n_vox && q < a.kk;
   int32_t e = 0x7fffffff;
   if (active) e = a.best_i[(int64_t)v * a.kk + q];
-  double dr = 0.0, di = 0.0, n2 = 0.0;
+  // <v, d> in FP32 with compensated (TwoSum) accumulation: the sum carries
+  // about one FP32 ulp of error instead of growing with sqrt(n_tr); the entry
+  // norm accumulates in FP64.
+  float sr = 0.f, cr = 0.f, si = 0.f, ci = 0.f;
+  double n2 = 0.0;
   const bool sim = active && e != 0x7fffffff;
   if (sim) {
     const int64_t k = a.entry_base + e;
@@ -310,13 +322,14 @@ __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
       free_evolve(m, pc.x, pc.y, r2.x, r1.x);
       const float2 s = x[j];
       // v conj(d)
-      dr = fma((double)s.x, (double)m.x, fma((double)s.y, (double)m.y, dr));
-      di = fma((double)s.y, (double)m.x, fma(-(double)s.x, (double)m.y, di));
+      two_sum_acc(sr, cr, fmaf(s.x, m.x, s.y * m.y));
+      two_sum_acc(si, ci, fmaf(s.y, m.x, -(s.x * m.y)));
       n2 = fma((double)m.x, (double)m.x, n2);
       n2 = fma((double)m.y, (double)m.y, n2);
       free_evolve(m, pc.z, pc.w, r2.y, r1.y);
     }
   }
+  const double dr = (double)sr + (double)cr, di = (double)si + (double)ci;
   float c = -1.0f;
   if (sim) {
     const double nv = a.vnorm[v];

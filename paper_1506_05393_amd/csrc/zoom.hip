@@ -30,7 +30,8 @@ struct ZoomArgs {
   const float2* vox;
   int64_t ld_vox;
   int32_t n_vox;
-  const int32_t* init;
+  const int32_t* init;       // per-axis prior centres [n_vox][4], or
+  const int64_t* init_flat;  // flat grid indices [n_vox] (either may be NULL)
   int64_t* idx;
   float* cc;
   float* margin;
@@ -554,7 +555,19 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.n_sim = 0;
     e.overflow = false;
     e.mm = INFINITY;
-    const int32_t* init = a.init ? a.init + 4 * (int64_t)v : nullptr;
+    const bool has_init = a.init || a.init_flat;
+    int32_t ini[4] = {0, 0, 0, 0};
+    if (a.init) {
+      for (int q = 0; q < 4; ++q) ini[q] = a.init[4 * (int64_t)v + q];
+    } else if (a.init_flat) {
+      int64_t k = a.init_flat[v];
+      if (k < 0) k = 0;  // a search that returned no entry: start at the grid origin
+      for (int q = 3; q >= 0; --q) {
+        ini[q] = (int32_t)(k % a.dims[q]);
+        k /= a.dims[q];
+      }
+    }
+    const int32_t* init = has_init ? ini : nullptr;
     for (int q = 0; q < 4; ++q) {
       e.lo[q] = 0;
       e.hi[q] = a.dims[q] - 1;
@@ -721,6 +734,31 @@ extern "C" int mrf_zoom_schedule_paper(const mrf_grid* g, const mrf_sequence* se
   return MRF_OK;
 }
 
+extern "C" int mrf_zoom_schedule_local(const mrf_grid* g, int32_t outer_max,
+                                       mrf_zoom_schedule* o) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  MRF_CHECK_ARG(o, "NULL argument");
+  MRF_CHECK_ARG(outer_max >= 0 && outer_max <= 64, "outer_max must be in [0, 64]");
+  *o = mrf_zoom_schedule();
+  int k = 0;
+  o->stages[k++] = stage(MRF_ZOOM2, 0, 1, 1, 1, 0, 0.0);
+  o->stages[k++] = stage(MRF_ZOOM1, 2, 0, 1, 0, 0, 0.0);
+  if (g->b1.n > 1) o->stages[k++] = stage(MRF_ZOOM1, 3, 0, 1, 0, 0, 0.0);
+  o->n_stages = k;
+  for (int i = 0; i < k; ++i) o->outer[i] = o->stages[i];
+  o->n_outer = k;
+  o->outer_max = outer_max;
+  o->n_starts = 1;
+  o->starts[0][0] = g->t1_ms.n / 2;
+  o->starts[0][1] = g->t2_ms.n / 2;
+  o->starts[0][2] = g->df_hz.n / 2;
+  o->starts[0][3] = g->b1.n > 1 ? g->b1.n / 2 : 0;
+  o->pruned = 0;
+  for (int a = 0; a < 4; ++a) o->prior_half[a] = -1;
+  return MRF_OK;
+}
+
 static int check_schedule(const mrf_zoom_schedule* s, const int32_t* dims) {
   MRF_CHECK_ARG(s != nullptr, "schedule is NULL");
   MRF_CHECK_ARG(s->n_stages >= 0 && s->n_stages <= MRF_ZOOM_MAX_STAGES, "bad n_stages");
@@ -757,11 +795,11 @@ extern "C" int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_
   return MRF_OK;
 }
 
-extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
-                               const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
-                               int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
-                               mrf_result_view out, void* workspace, size_t ws_bytes,
-                               void* stream) {
+static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                       const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                       int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
+                       const int64_t* init_flat, mrf_result_view out, void* workspace,
+                       size_t ws_bytes, void* stream) {
   MRF_CHECK_ARG(ctx && seq, "context and sequence must not be NULL");
   int rc = check_grid(grid);
   if (rc) return rc;
@@ -796,6 +834,7 @@ extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const 
   a.ld_vox = ld_vox;
   a.n_vox = n_vox;
   a.init = init_idx;
+  a.init_flat = init_flat;
   a.idx = out.idx;
   a.cc = out.cc;
   a.margin = out.margin;
@@ -825,4 +864,23 @@ extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const 
   }
   MRF_HIP(hipGetLastError());
   return MRF_OK;
+}
+
+extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                               const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                               int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
+                               mrf_result_view out, void* workspace, size_t ws_bytes,
+                               void* stream) {
+  return zoom_search(ctx, seq, grid, sched, vox, n_vox, ld_vox, n_tr, init_idx, nullptr, out,
+                     workspace, ws_bytes, stream);
+}
+
+extern "C" int mrf_zoom_search_from(mrf_context* ctx, const mrf_sequence* seq,
+                                    const mrf_grid* grid, const mrf_zoom_schedule* sched,
+                                    const void* vox, int32_t n_vox, int64_t ld_vox, int32_t n_tr,
+                                    const int64_t* start_idx, mrf_result_view out,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  MRF_CHECK_ARG(start_idx != nullptr || n_vox == 0, "start_idx must not be NULL");
+  return zoom_search(ctx, seq, grid, sched, vox, n_vox, ld_vox, n_tr, nullptr, start_idx, out,
+                     workspace, ws_bytes, stream);
 }

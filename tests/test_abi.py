@@ -54,3 +54,18 @@ def test_host_only_calls_without_gpu():
     assert b"strictly increasing" in lib.mrf_last_error()
     neg = inputs.Grid(np.array([-1.0]), np.array([10.0]), np.array([0.0]))
     assert lib.mrf_grid_size(api.GridArg(neg).ptr) == -1
+
+
+def test_local_refine_schedule_builder():
+    """mrf_zoom_schedule_local (host only): unit 2-D (T1, T2) zoom, unit df zoom
+    (and unit B1 zoom with a B1 axis), the same list repeated as the outer loop."""
+    from paper_1506_05393_amd import api
+    from paper_1506_05393_amd import inputs as I
+    g = I.make_grid([300.0, 700.0, 1200.0], [30.0, 60.0], [-4.0, 0.0, 4.0])
+    s = api.schedule_local(g, outer_max=5)
+    kinds = [(x["kind"], x["axis0"], x["step0"]) for x in s["stages"]]
+    assert kinds == [(4, 0, 1), (3, 2, 1)] and s["stages"][0]["axis1"] == 1
+    assert s["outer"] == s["stages"] and s["outer_max"] == 5
+    g4 = I.make_grid([300.0, 700.0], [30.0, 60.0], [0.0], [0.9, 1.0, 1.1])
+    s4 = api.schedule_local(g4)
+    assert [(x["kind"], x["axis0"]) for x in s4["stages"]] == [(4, 0), (3, 2), (3, 3)]

@@ -160,3 +160,35 @@ def test_zoom_four_parameters_sampled(ctx, orc):
     dcc = np.abs(cc - ref["cc"])
     print(f"volume: median |dCC| {np.median(dcc):.2e}, max {dcc.max():.2e}")
     assert np.median(dcc) < 1e-4
+
+
+def test_local_refine_from_brute_force(ctx, orc):
+    """Unit-step local refinement started at the FP32 brute-force result: same
+    path as the oracle's engine on pinned voxels, and the oracle's refined
+    entry is a local CC maximum among its unit neighbours."""
+    from paper_1506_05393_amd import api
+    w = _cfg1()
+    V = oracle_fingerprints(orc, w.seq, w.phantom)
+    sq = api.Sequence(ctx, w.seq)
+    d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+    r = api.match_bruteforce(ctx, d, to_dev(V), top_k=2)
+    init = api.grid_indices(w.grid, r["idx"].cpu().numpy())
+    sched = api.schedule_local(w.grid)
+    ref = orc.zoom(w.seq, w.grid, sched, V, init=init, threads=8)
+    res = api.zoom_search(ctx, sq, w.grid, to_dev(V), sched=sched, start=r["idx"])
+    res4 = api.zoom_search(ctx, sq, w.grid, to_dev(V), sched=sched, init=to_dev(init))
+    torch.cuda.synchronize()
+    _check(res, ref, "local refine", min_pinned_frac=0.5, orc=orc, seq=w.seq, grid=w.grid, V=V)
+    for k in ("idx", "cc", "n_sim"):  # flat and per-axis prior centres are the same search
+        assert torch.equal(res[k], res4[k])
+    dims = [len(w.grid.t1_ms), len(w.grid.t2_ms), len(w.grid.df_hz)]
+    for v in range(0, V.shape[0], 16):
+        c = np.array(w.grid.unravel(int(ref["idx"][v]))[:3])
+        best = orc.cc(V[v], orc.simulate(w.seq, *w.grid.values(int(ref["idx"][v]))))
+        for dlt in ([1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [1, 1, 0], [1, -1, 0],
+                    [-1, 1, 0], [-1, -1, 0], [0, 0, 1], [0, 0, -1]):
+            n = c + np.array(dlt)
+            if np.any(n < 0) or np.any(n >= dims):
+                continue
+            k = int((n[0] * dims[1] + n[1]) * dims[2] + n[2])
+            assert orc.cc(V[v], orc.simulate(w.seq, *w.grid.values(k))) <= best

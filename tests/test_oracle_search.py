@@ -293,3 +293,50 @@ def test_neighbour_prior_restricts_range(orc):
     r = orc.zoom_generic(sched, (30, 30, 1, 1), _bowl((25, 25, 0, 0)), init=(10, 10, 0, 0))
     assert r["idx"] == (13, 12, 0, 0)
     assert all(7 <= c[0] <= 13 and 8 <= c[1] <= 12 for c in r["calls"])
+
+
+def _local_schedule(orc, b1=False):
+    st = [dict(kind=orc.ZOOM2, axis0=0, axis1=1, step0=1, step1=1),
+          dict(kind=orc.ZOOM1, axis0=2, step0=1)]
+    if b1:
+        st.append(dict(kind=orc.ZOOM1, axis0=3, step0=1))
+    return dict(stages=st, outer=list(st), outer_max=8, starts=[[0, 0, 0, 0]])
+
+
+def test_local_refine_keeps_the_global_maximum(orc):
+    """The global CC maximum is a local one: unit-step refinement started at
+    the brute-force argmax never moves, and its value is brute force's."""
+    seq, grid = _tiny()
+    rng = np.random.default_rng(21)
+    D, _ = orc.simulate_grid(seq, grid)
+    V = D[rng.integers(0, grid.size, 20)] * np.exp(1j * rng.uniform(0, 6.3, (20, 1)))
+    V = V + 0.03 * (rng.normal(size=V.shape) + 1j * rng.normal(size=V.shape))
+    brute = orc.bruteforce(seq, grid, V)
+    init = np.stack(grid.unravel(brute["idx"]), axis=1).astype(np.int32)
+    z = orc.zoom(seq, grid, _local_schedule(orc), V, init=init)
+    assert np.array_equal(z["idx"], brute["idx"])
+    assert np.allclose(z["cc"], brute["cc"], rtol=0, atol=1e-15)
+
+
+def test_local_refine_climbs_to_a_local_maximum(orc):
+    """From an arbitrary start the refinement ends where no unit neighbour
+    (the 8 of the (T1, T2) stencil, df +-1) has a higher CC."""
+    seq, grid = _tiny()
+    rng = np.random.default_rng(22)
+    D, _ = orc.simulate_grid(seq, grid)
+    V = D[rng.integers(0, grid.size, 12)]
+    V = V + 0.05 * (rng.normal(size=V.shape) + 1j * rng.normal(size=V.shape))
+    dims = np.array([len(grid.t1_ms), len(grid.t2_ms), len(grid.df_hz)])
+    init = np.zeros((12, 4), np.int32)
+    init[:, :3] = rng.integers(0, dims, (12, 3))
+    z = orc.zoom(seq, grid, _local_schedule(orc), V, init=init)
+    for v in range(12):
+        c = np.array(grid.unravel(int(z["idx"][v]))[:3])
+        best = orc.cc(V[v], D[int(z["idx"][v])])
+        assert abs(best - z["cc"][v]) < 1e-12
+        for dl in ([1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [1, 1, 0], [1, -1, 0],
+                   [-1, 1, 0], [-1, -1, 0], [0, 0, 1], [0, 0, -1]):
+            n = c + np.array(dl)
+            if np.any(n < 0) or np.any(n >= dims):
+                continue
+            assert orc.cc(V[v], D[int((n[0] * dims[1] + n[1]) * dims[2] + n[2])]) <= best
