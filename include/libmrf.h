@@ -276,6 +276,21 @@ int mrf_zoom_search_from(mrf_context* ctx, const mrf_sequence* seq, const mrf_gr
                          int64_t ld_vox, int32_t n_tr, const int64_t* start_idx,
                          mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
 
+/* Neighbour prior (Methods, Experiment 3: each voxel starts from a
+ * neighbour's result with narrowed ranges), as a two-pass lattice over a
+ * volume of n_slices slices of width x height voxels stored slice-major in
+ * raster order (voxel v = (s*height + y)*width + x): pass 1 searches the
+ * voxels with x % stride == 0 and y % stride == 0 without a prior; pass 2
+ * starts every other voxel at the result of the nearest pass-1 voxel of its
+ * slice (Chebyshev distance, ties to the lower raster index), with each axis
+ * restricted to that centre +- sched->prior_half (entries < 0: whole axis).
+ * Workspace as mrf_zoom_workspace for width*height*n_slices voxels. */
+int mrf_zoom_search_lattice(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                            const mrf_zoom_schedule* sched, const void* vox, int32_t width,
+                            int32_t height, int32_t n_slices, int64_t ld_vox, int32_t n_tr,
+                            int32_t stride, mrf_result_view out, void* workspace,
+                            size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Serving: a request loop over resident dictionaries (not part of the paper,
  * whose searches are one slice at a time; it serves the same two searches,

@@ -134,6 +134,10 @@ _SIGS += [
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("mrf_zoom_search_lattice", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
+      C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32, ResultView, C.c_void_p,
+      C.c_size_t, C.c_void_p]),
     ("mrf_zoom_search_from", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,

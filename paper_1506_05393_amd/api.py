@@ -467,3 +467,49 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def prior_half_widths(grid, t1_ms=3000.0, t2_ms=800.0, df_hz=150.0, b1=0.3) -> list:
+    """Neighbour-prior half-widths in index steps for physical ranges (the
+    Methods' Experiment 3 ranges by default; B1 +-0.3 for a B1 axis): per axis
+    max(1, round(r / ((max - min)/(n - 1)))), -1 for an axis of one value."""
+    gr = grid.grid if isinstance(grid, GridArg) else grid
+    out = []
+    for ax, r in ((gr.t1_ms, t1_ms), (gr.t2_ms, t2_ms), (gr.df_hz, df_hz), (gr.b1, b1)):
+        n = len(ax)
+        if n <= 1:
+            out.append(-1)
+            continue
+        step = (float(ax[-1]) - float(ax[0])) / (n - 1)
+        out.append(max(1, int(np.floor(r / step + 0.5))))
+    return out
+
+
+def zoom_search_lattice(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, width: int,
+                        height: int, n_slices: int, sched: Optional[dict] = None,
+                        stride: int = 4, n_tr: Optional[int] = None,
+                        workspace: Optional[Workspace] = None, out: Optional[dict] = None,
+                        stream=None) -> dict:
+    """MRF-ZOOM over a volume with the two-pass lattice neighbour prior
+    (mrf_zoom_search_lattice). vox: complex64 cuda [n_slices*height*width,
+    >= n_tr], slice-major raster order. sched['prior_half'] sets the pass-2
+    ranges (see prior_half_widths)."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda or vox.stride(1) != 1:
+        raise ValueError("vox must be a complex64 CUDA tensor with contiguous rows")
+    n_tr = seq.n if n_tr is None else int(n_tr)
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    sd = schedule_paper(ctx, seq, g) if sched is None else sched
+    s = schedule_from_dict(sd)
+    n_vox = vox.shape[0]
+    if n_vox != width * height * n_slices:
+        raise ValueError("vox rows must equal width * height * n_slices")
+    nb = C.c_size_t()
+    L.check(ctx._lib.mrf_zoom_workspace(ctx.handle, g.ptr, n_vox, n_tr, C.byref(nb)))
+    ws = workspace if workspace is not None else Workspace(ctx.device)
+    buf = ws.get(int(nb.value))
+    r = out if out is not None else _result_tensors(n_vox, ctx.device, with_nsim=True)
+    L.check(ctx._lib.mrf_zoom_search_lattice(
+        ctx.handle, seq.handle, g.ptr, C.byref(s), vox.data_ptr(), int(width), int(height),
+        int(n_slices), vox.stride(0), n_tr, int(stride), _result_view(r), buf.data_ptr(),
+        buf.numel(), _stream_ptr(stream)))
+    return r

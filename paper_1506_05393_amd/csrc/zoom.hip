@@ -32,6 +32,10 @@ struct ZoomArgs {
   int32_t n_vox;
   const int32_t* init;       // per-axis prior centres [n_vox][4], or
   const int64_t* init_flat;  // flat grid indices [n_vox] (either may be NULL)
+  // queue: n_items positions. Neighbour-prior lattice passes (lat_pass 1:
+  // the voxels on every lat_stride-th row and column of each lat_w x lat_h
+  // slice; 2: the others, each started at its nearest lattice voxel's result)
+  int32_t n_items, lat_pass, lat_w, lat_h, lat_stride;
   int64_t* idx;
   float* cc;
   float* margin;
@@ -510,11 +514,34 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   __syncthreads();
   int64_t serial = 0;
 
+  const int32_t W = a.lat_w, H = a.lat_h, L = a.lat_stride;
+  const int32_t lw = a.lat_pass ? (W + L - 1) / L : 0, lh = a.lat_pass ? (H + L - 1) / L : 0;
   for (;;) {
-    int v = 0;
-    if (lane == 0) v = atomicAdd(a.counter, 1);
-    v = __shfl(v, 0);
-    if (v >= a.n_vox) break;
+    int p = 0;
+    if (lane == 0) p = atomicAdd(a.counter, 1);
+    p = __shfl(p, 0);
+    if (p >= a.n_items) break;
+    // queue position -> voxel (slice-major raster order for the lattice passes)
+    int v = p;
+    int32_t prior_v = -1;
+    if (a.lat_pass == 1) {
+      const int32_t s = p / (lw * lh), r = p % (lw * lh);
+      v = (s * H + (r / lw) * L) * W + (r % lw) * L;
+    } else if (a.lat_pass == 2) {
+      const int32_t x = v % W, y = (v / W) % H, s = v / (W * H);
+      if (x % L == 0 && y % L == 0) continue;  // a lattice voxel: done in the first pass
+      // nearest lattice voxel in Chebyshev distance, ties to the lower raster
+      // index: D = the larger of the per-axis distances to the nearest lattice
+      // line; every lattice voxel within D on both axes is a nearest one, and
+      // the lowest raster index among them takes the lowest row, then column
+      const int32_t qx = x / L, qy = y / L;
+      const int32_t dx = min(x - qx * L, (qx + 1) * L < W ? (qx + 1) * L - x : L);
+      const int32_t dy = min(y - qy * L, (qy + 1) * L < H ? (qy + 1) * L - y : L);
+      const int32_t D = max(dx, dy);
+      const int32_t px = (max(x - D, 0) + L - 1) / L * L;
+      const int32_t py = (max(y - D, 0) + L - 1) / L * L;
+      prior_v = (s * H + py) * W + px;
+    }
 
     // unit-norm voxel (norm in FP64) into LDS
     const float2* src = a.vox + (int64_t)v * a.ld_vox;
@@ -555,12 +582,13 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.n_sim = 0;
     e.overflow = false;
     e.mm = INFINITY;
-    const bool has_init = a.init || a.init_flat;
+    const bool has_init = a.init || a.init_flat || prior_v >= 0;
     int32_t ini[4] = {0, 0, 0, 0};
     if (a.init) {
       for (int q = 0; q < 4; ++q) ini[q] = a.init[4 * (int64_t)v + q];
-    } else if (a.init_flat) {
-      int64_t k = a.init_flat[v];
+    } else if (a.init_flat || prior_v >= 0) {
+      // the first pass wrote the lattice voxel's result before this launch
+      int64_t k = prior_v >= 0 ? a.idx[prior_v] : a.init_flat[v];
       if (k < 0) k = 0;  // a search that returned no entry: start at the grid origin
       for (int q = 3; q >= 0; --q) {
         ini[q] = (int32_t)(k % a.dims[q]);
@@ -799,7 +827,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
                        const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
                        int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                        const int64_t* init_flat, mrf_result_view out, void* workspace,
-                       size_t ws_bytes, void* stream) {
+                       size_t ws_bytes, void* stream, const int32_t* lattice = nullptr) {
   MRF_CHECK_ARG(ctx && seq, "context and sequence must not be NULL");
   int rc = check_grid(grid);
   if (rc) return rc;
@@ -835,6 +863,11 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.n_vox = n_vox;
   a.init = init_idx;
   a.init_flat = init_flat;
+  a.n_items = n_vox;
+  a.lat_pass = 0;
+  a.lat_w = lattice ? lattice[0] : 1;
+  a.lat_h = lattice ? lattice[1] : 1;
+  a.lat_stride = lattice ? lattice[3] : 1;
   a.idx = out.idx;
   a.cc = out.cc;
   a.margin = out.margin;
@@ -858,9 +891,28 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
                                 64 * 1024));
     attr = true;
   }
-  {
+  if (!lattice) {
     ProfScope prof(ctx, "k_zoom", st);
     hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
+  } else {
+    // pass 1: the lattice voxels, no prior
+    const int32_t L = lattice[3];
+    a.lat_pass = 1;
+    a.n_items = lattice[2] * ((lattice[0] + L - 1) / L) * ((lattice[1] + L - 1) / L);
+    {
+      ProfScope prof(ctx, "k_zoom", st);
+      hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
+    }
+    MRF_HIP(hipGetLastError());
+    // pass 2: every other voxel from its nearest lattice voxel's result
+    hipLaunchKernelGGL(k_zoom_init, dim3(1), dim3(64), 0, st, a.counter, *sched, dsch);
+    MRF_HIP(hipGetLastError());
+    a.lat_pass = 2;
+    a.n_items = n_vox;
+    {
+      ProfScope prof(ctx, "k_zoom", st);
+      hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
+    }
   }
   MRF_HIP(hipGetLastError());
   return MRF_OK;
@@ -883,4 +935,19 @@ extern "C" int mrf_zoom_search_from(mrf_context* ctx, const mrf_sequence* seq,
   MRF_CHECK_ARG(start_idx != nullptr || n_vox == 0, "start_idx must not be NULL");
   return zoom_search(ctx, seq, grid, sched, vox, n_vox, ld_vox, n_tr, nullptr, start_idx, out,
                      workspace, ws_bytes, stream);
+}
+
+extern "C" int mrf_zoom_search_lattice(mrf_context* ctx, const mrf_sequence* seq,
+                                       const mrf_grid* grid, const mrf_zoom_schedule* sched,
+                                       const void* vox, int32_t width, int32_t height,
+                                       int32_t n_slices, int64_t ld_vox, int32_t n_tr,
+                                       int32_t stride, mrf_result_view out, void* workspace,
+                                       size_t ws_bytes, void* stream) {
+  MRF_CHECK_ARG(width >= 1 && height >= 1 && n_slices >= 1, "volume sizes must be >= 1");
+  MRF_CHECK_ARG(stride >= 1 && stride <= 64, "stride must be in [1, 64]");
+  const int64_t n = (int64_t)width * height * n_slices;
+  MRF_CHECK_ARG(n <= INT32_MAX, "too many voxels in one call");
+  const int32_t lat[4] = {width, height, n_slices, stride};
+  return zoom_search(ctx, seq, grid, sched, vox, (int32_t)n, ld_vox, n_tr, nullptr, nullptr, out,
+                     workspace, ws_bytes, stream, lat);
 }

@@ -192,3 +192,39 @@ def test_local_refine_from_brute_force(ctx, orc):
                 continue
             k = int((n[0] * dims[1] + n[1]) * dims[2] + n[2])
             assert orc.cc(V[v], orc.simulate(w.seq, *w.grid.values(k))) <= best
+
+
+def test_zoom_lattice_neighbour_prior(ctx, orc):
+    """Two-pass lattice neighbour prior over a 2-slice 16x16 volume vs the
+    oracle's driver: lattice voxels as plain ZOOM; every other voxel, where its
+    lattice voxel agrees with the oracle's, takes the oracle's path (pinned
+    voxels) inside the narrowed ranges."""
+    from paper_1506_05393_amd import api
+    w = _cfg1()
+    V1 = oracle_fingerprints(orc, w.seq, w.phantom)
+    V = np.ascontiguousarray(np.concatenate([V1, V1[::-1]]))
+    sched = orc.schedule_paper(w.seq, w.grid)
+    half = [10, 8, 5]
+    sched["prior_half"] = half + [-1]
+    ref = orc.zoom_lattice(w.seq, w.grid, sched, V, 16, 16, 2, stride=4, threads=8)
+    sq = api.Sequence(ctx, w.seq)
+    res = api.zoom_search_lattice(ctx, sq, w.grid, to_dev(V), 16, 16, 2, sched=sched)
+    torch.cuda.synchronize()
+    idx = res["idx"].cpu().numpy()
+    ns = res["n_sim"].cpu().numpy()
+    cc = res["cc"].cpu().numpy().astype(np.float64)
+    near, lat = ref["prior_voxel"], ref["lattice"]
+    assert lat.sum() == 2 * 16 and np.all(ns > 0)
+    comparable = lat | (idx[near] == ref["idx"][near])
+    pinned = comparable & (ref["min_margin"] > MARGIN)
+    agree = idx == ref["idx"]
+    print(f"lattice prior: comparable {comparable.sum()}/512, pinned {pinned.sum()}, "
+          f"agreement all {agree.mean():.4f}, n_sim mean {ns.mean():.1f} "
+          f"(lattice {ns[lat].mean():.1f}, others {ns[~lat].mean():.1f})")
+    assert pinned.sum() >= 128
+    assert np.all(agree[pinned]), np.flatnonzero(pinned & ~agree)[:10]
+    assert np.all(ns[pinned] == ref["n_sim"][pinned])
+    assert np.abs(cc - ref["cc"])[agree].max() < CC_TOL
+    gi, pi = w.grid.unravel(idx), w.grid.unravel(idx[near])
+    for ax, h in enumerate(half):
+        assert np.all(np.abs(gi[ax][~lat] - pi[ax][~lat]) <= h)

@@ -340,3 +340,37 @@ def test_local_refine_climbs_to_a_local_maximum(orc):
             if np.any(n < 0) or np.any(n >= dims):
                 continue
             assert orc.cc(V[v], D[int((n[0] * dims[1] + n[1]) * dims[2] + n[2])]) <= best
+
+
+def test_nearest_lattice_voxel_by_hand(orc):
+    """Two-pass neighbour prior: the nearest lattice voxel (Chebyshev, ties
+    to the lower raster index) on a 6 x 5 slice with stride 4, by hand."""
+    near = orc.nearest_lattice(6, 5, 2, 4)
+    xy = lambda v: (v % 6, (v // 6) % 5)
+    expect = {(0, 0): (0, 0), (1, 0): (0, 0), (2, 0): (0, 0), (3, 0): (4, 0), (5, 0): (4, 0),
+              (2, 2): (0, 0), (3, 2): (4, 0), (2, 3): (0, 4), (5, 4): (4, 4), (1, 3): (0, 4),
+              (4, 2): (4, 0)}
+    for (x, y), (px, py) in expect.items():
+        assert xy(near[y * 6 + x]) == (px, py), (x, y)
+        assert near[30 + y * 6 + x] == 30 + py * 6 + px  # second slice: its own lattice
+
+
+def test_lattice_prior_pass_structure(orc):
+    """Lattice voxels get exactly the plain search; with whole-axis prior
+    ranges every other voxel gets the plain search started at its prior
+    centre."""
+    seq, grid = _tiny()
+    rng = np.random.default_rng(23)
+    D, _ = orc.simulate_grid(seq, grid)
+    V = D[rng.integers(0, grid.size, 30)]
+    V = V + 0.05 * (rng.normal(size=V.shape) + 1j * rng.normal(size=V.shape))
+    sched = orc.schedule_paper(seq, grid)
+    res = orc.zoom_lattice(seq, grid, sched, V, 6, 5, 1, stride=4)
+    lat = res["lattice"]
+    plain = orc.zoom(seq, grid, sched, V[lat])
+    assert np.array_equal(res["idx"][lat], plain["idx"])
+    rest = np.flatnonzero(~lat)
+    init = np.stack(grid.unravel(res["idx"][res["prior_voxel"][rest]]), axis=1).astype(np.int32)
+    again = orc.zoom(seq, grid, sched, V[rest], init=init)
+    assert np.array_equal(res["idx"][rest], again["idx"])
+    assert np.array_equal(res["n_sim"][rest], again["n_sim"])
