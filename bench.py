@@ -32,6 +32,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="target CPU time of the oracle sample")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    p.add_argument("--no-volume", action="store_true",
+                   help="skip the 8 x 256 x 256 four-parameter ZOOM volume")
     p.add_argument("--copy-probe-gb", type=float, default=0.0,
                    help="only run a plain device copy of this size (3 times), the reference "
                         "for scaling HBM byte counters, and exit")
@@ -82,6 +84,73 @@ def counted_traffic(kernel: str, source: str):
         if len(cells) == 7 and cells[0] == kernel:
             return float(cells[6])
     return None
+
+
+def volume_bench(api, ctx, torch, n_slices: int = 8, side: int = 256):
+    """MRF-ZOOM over 8 slices of 256 x 256 voxels, N = 1000, on the virtual
+    3901 x 1991 x 241 x 121 (T1, T2, df, B1) grid: the paper schedule with B1
+    stages, without and with the two-pass lattice neighbour prior (Experiment
+    3 ranges: +-3000 ms, +-800 ms, +-150 Hz, +-0.3). Fingerprints: GPU-simulated
+    phantom truths, random global phase and magnitude, SNR 25 noise."""
+    from paper_1506_05393_amd import workloads as W
+    w = W.volume(n_slices, side)
+    sq = api.Sequence(ctx, w.seq)
+    ga = api.GridArg(w.grid)
+    ph = w.phantom
+    clean = api.simulate_signals(ctx, sq, torch.from_numpy(W.phantom_params(ph)).cuda())
+    g = torch.Generator(device="cuda").manual_seed(ph.noise_key)
+    noise = torch.randn(clean.shape, dtype=torch.complex64, device="cuda", generator=g)
+    scale = torch.from_numpy((ph.mag * np.exp(1j * ph.phase)).astype(np.complex64)).cuda()
+    sigma = (clean.abs().pow(2).mean(dim=1).sqrt() * torch.from_numpy(ph.mag.astype(np.float32))
+             .cuda() / ph.snr)
+    vox = (scale[:, None] * clean + sigma[:, None] * noise).contiguous()
+    del clean, noise
+    sched = api.schedule_paper(ctx, sq, ga)
+    sched_p = dict(sched)
+    sched_p["prior_half"] = api.prior_half_widths(ga)
+    ws = api.Workspace(ctx.device)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn in (("plain", lambda: api.zoom_search(ctx, sq, ga, vox, sched=sched, workspace=ws)),
+                     ("lattice", lambda: api.zoom_search_lattice(ctx, sq, ga, vox, side, side,
+                                                                 n_slices, sched=sched_p,
+                                                                 workspace=ws))):
+        a, b = ev(), ev()
+        a.record()
+        r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = (a.elapsed_time(b), r)
+        log(f"volume {name}: {out[name][0]:.0f} ms")
+    per_slice = []
+    nv = side * side
+    for s in range(n_slices):
+        a, b = ev(), ev()
+        a.record()
+        api.zoom_search_lattice(ctx, sq, ga, vox[s * nv:(s + 1) * nv], side, side, 1,
+                                sched=sched_p, workspace=ws)
+        b.record()
+        per_slice.append((a, b))
+    torch.cuda.synchronize()
+    per_slice = [a.elapsed_time(b) for a, b in per_slice]
+    n = vox.shape[0]
+    res = {"workload": f"{w.name}: {n} voxels, grid {len(w.grid.t1_ms)} x {len(w.grid.t2_ms)} x "
+                       f"{len(w.grid.df_hz)} x {len(w.grid.b1)} (never stored)",
+           "prior_half_idx": sched_p["prior_half"]}
+    for name, (ms, r) in out.items():
+        ns = r["n_sim"].cpu().numpy()
+        res[name] = {"ms": ms, "voxels_per_s": n / (ms * 1e-3), "n_sim_mean": float(ns.mean()),
+                     "n_sim_p50": float(np.percentile(ns, 50)),
+                     "n_sim_p99": float(np.percentile(ns, 99)), "n_sim_max": int(ns.max()),
+                     "n_sim_hist": np.histogram(ns, bins=[0, 100, 200, 300, 400, 600, 800,
+                                                          1200, 1 << 30])[0].tolist()}
+    res["lattice_speedup"] = out["plain"][0] / out["lattice"][0]
+    res["index_agreement_lattice_vs_plain"] = float(
+        (out["plain"][1]["idx"] == out["lattice"][1]["idx"]).double().mean().item())
+    res["cc_mean"] = {k: float(v[1]["cc"].double().mean().item()) for k, v in out.items()}
+    res["slice_ms_lattice"] = {"p50": float(np.percentile(per_slice, 50)),
+                               "p99": float(np.percentile(per_slice, 99))}
+    return res
 
 
 def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
@@ -381,6 +450,11 @@ def main():
         "paper_context": "paper: 116.72 s per 1731-voxel 64x64 slice (ZOOM, df dictionary) on a "
                          "2.0 GHz dual-core laptop, C++",
     }
+    if not args.no_volume:
+        log("volume ...")
+        del d32, d16
+        torch.cuda.empty_cache()
+        res["volume"] = volume_bench(api, ctx, torch)
     if not args.no_serve:
         log("serving ...")
         res["serving"] = serve_bench(api, ctx, torch, args.serve_requests, args.serve_rate)
