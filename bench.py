@@ -240,7 +240,10 @@ def cpu_baseline(w, target_s: float):
     clean = np.stack([oracle.simulate(w.seq, ph.t1[v], ph.t2[v], ph.df[v], ph.b1[v])
                       for v in vox])
     V = I.compose_fingerprints(clean, ph, vox).astype(np.complex64)
-    threads = os.cpu_count() or 1
+    # the host threads this process may use (affinity), capped by OMP_NUM_THREADS
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     # calibrate on 2 T1 rows, then size the sample to about target_s
     rows = 2
     sub = I.make_grid(w.grid.t1_ms[:rows], w.grid.t2_ms, w.grid.df_hz)
