@@ -29,7 +29,8 @@ namespace mrf {
 // ---------------------------------------------------------------------------
 constexpr int BM = 128;     // rows (64 voxels)
 constexpr int BN = 128;     // entries
-constexpr int KC = 32;      // readouts per LDS chunk
+constexpr int KC = 16;      // readouts per LDS chunk (80 KB of LDS: two workgroups per CU)
+constexpr int NLD = KC / 4;  // float4 of A (and of B) each thread moves per chunk
 constexpr int KK_MAX = 16;  // longest candidate list kept in the epilogue
 
 struct MatchArgs {
@@ -45,15 +46,15 @@ struct MatchArgs {
 };
 
 // One LDS chunk of KC readouts: A [2 planes][KC][BM] and B [2][KC][BN]
-// floats; thread t moves 8 float4 of each.
+// floats; thread t moves NLD float4 of each.
 __device__ __forceinline__ void load_chunk(const MatchArgs& a, int c, int row0, int64_t col0,
-                                           int tid, float4 (&ra)[8], float4 (&rb)[8]) {
+                                           int tid, float4 (&ra)[NLD], float4 (&rb)[NLD]) {
   const int s0 = c * KC;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < NLD; ++i) {
     const int idx = i * 256 + tid;  // [g][s][c4] with 32 float4 per row
-    const int g = idx >> 10;        // / (KC * 32)
-    const int s = (idx >> 5) & (KC - 1);
+    const int g = idx / (KC * 32);
+    const int s = (idx / 32) % KC;
     const int c4 = idx & 31;
     ra[i] = *(const float4*)(a.A + ((int64_t)g * a.n_tr_pad + s0 + s) * a.m_pad + row0 + 4 * c4);
     // unconditional loads (a branch here would make every load wait for
@@ -69,18 +70,22 @@ __device__ __forceinline__ void load_chunk(const MatchArgs& a, int c, int row0, 
 }
 
 __device__ __forceinline__ void store_chunk(float* As, float* Bs, int buf, int tid,
-                                            const float4 (&ra)[8], const float4 (&rb)[8]) {
+                                            const float4 (&ra)[NLD], const float4 (&rb)[NLD]) {
   float* as = As + buf * 2 * KC * BM;
   float* bs = Bs + buf * 2 * KC * BN;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < NLD; ++i) {
     const int idx = i * 256 + tid;
     *(float4*)(as + 4 * idx) = ra[i];
     *(float4*)(bs + 4 * idx) = rb[i];
   }
 }
 
-__global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
+// Two workgroups per CU (one wave per SIMD each): the registers of a wave
+// stay within half of the file, so each SIMD holds two waves whose MFMAs fill
+// each other's LDS waits.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_match_f32(
+    MatchArgs a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
   // (round robin over 8), so the row tiles of one column chunk are grouped on
   // one XCD and share its L2 for the dictionary tiles.
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(256) void k_match_f32(MatchArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    float4 ra[8], rb[8];
+    float4 ra[NLD], rb[NLD];
     load_chunk(a, 0, row0, col0, tid, ra, rb);
     store_chunk(As, Bs, 0, tid, ra, rb);
     __syncthreads();
