@@ -29,9 +29,10 @@ namespace mrf {
 // ---------------------------------------------------------------------------
 constexpr int BM = 128;     // rows (64 voxels)
 constexpr int BN = 128;     // entries
-constexpr int KC = 16;      // readouts per LDS chunk (80 KB of LDS: two workgroups per CU)
+constexpr int KC = 8;       // readouts per LDS chunk (48 KB of LDS: three workgroups per CU)
 constexpr int NLD = KC / 4;  // float4 of A (and of B) each thread moves per chunk
 constexpr int KK_MAX = 16;  // longest candidate list kept in the epilogue
+constexpr int kWgPerCu = 3;  // resident workgroups per CU (LDS and registers allow three)
 
 struct MatchArgs {
   const float* A;       // [2][n_tr_pad][m_pad]
@@ -81,10 +82,10 @@ __device__ __forceinline__ void store_chunk(float* As, float* Bs, int buf, int t
   }
 }
 
-// Two workgroups per CU (one wave per SIMD each): the registers of a wave
-// stay within half of the file, so each SIMD holds two waves whose MFMAs fill
-// each other's LDS waits.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_match_f32(
+// Three workgroups per CU (one wave per SIMD each): the registers of a wave
+// stay within a third of the file, so each SIMD holds three waves whose MFMAs
+// fill each other's LDS waits.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_match_f32(
     MatchArgs a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
   // (round robin over 8), so the row tiles of one column chunk are grouped on
@@ -354,8 +355,9 @@ static Plan make_plan(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int 
   p.n_vox_pad = p.m_pad / 2;
   p.n_row_tiles = p.m_pad / BM;
   p.n_col_tiles = (int32_t)((d->n_entries + BN - 1) / BN);
-  // enough chunks to give every CU several workgroups, a multiple of 8 (XCDs)
-  int want = (4 * n_cu + p.n_row_tiles - 1) / p.n_row_tiles;
+  // enough chunks for two rounds of the three resident workgroups per CU, a
+  // multiple of 8 (XCDs)
+  int want = (2 * kWgPerCu * n_cu + p.n_row_tiles - 1) / p.n_row_tiles;
   want = std::min(want, std::max(p.n_col_tiles, 1));
   p.n_chunks = std::max(8, (want + 7) / 8 * 8);
   size_t o = 0;
