@@ -70,6 +70,40 @@ __device__ __forceinline__ void issue_stage(const MatchB16Args& a, uint4* As, ui
   }
 }
 
+// The entry norms of this lane's 4 tile columns (1 when the dictionary has
+// unit-norm entries; columns past the last entry read entry 0, masked later).
+__device__ __forceinline__ void load_norms(const MatchB16Args& a, int64_t col0, int wc, int lane,
+                                           double (&nrm)[4]) {
+#pragma unroll
+  for (int bn = 0; bn < 4; ++bn) {
+    const int64_t e = col0 + wc * 128 + bn * 32 + (lane & 31);
+    nrm[bn] = a.norm ? a.norm[e < a.n_entries ? e : 0] : 1.0;
+  }
+}
+
+// The A and B fragments of MFMA group s (0 or 1) of ring slot st for this lane.
+__device__ __forceinline__ void read_frags(const uint4* As, const uint4* Bs, int st, int s, int wr,
+                                           int wc, int lane, bf16x8 (&fa)[4], bf16x8 (&fb)[4]) {
+  const bf16x8* as =
+      (const bf16x8*)(As + (st * BKB + 2 * s + (lane >> 5)) * BBM + wr * 128 + (lane & 31));
+  const bf16x8* bs =
+      (const bf16x8*)(Bs + (st * BKB + 2 * s + (lane >> 5)) * BBN + wc * 128 + (lane & 31));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    fa[i] = as[32 * i];
+    fb[i] = bs[32 * i];
+  }
+}
+
+__device__ __forceinline__ void mfma_group(floatx16 (&acc)[4][4], const bf16x8 (&fa)[4],
+                                           const bf16x8 (&fb)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+}
+
 __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   const int w = blockIdx.x;
   const int xcd = w & 7;
@@ -101,6 +135,16 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   const int ct_end = (int)((int64_t)(chunk + 1) * a.n_col_tiles / a.n_chunks);
   const int n_kc = a.nblk_pad / BKB;
 
+  // Tile pipeline: the entry norms and the first NSTAGE stages of a tile are
+  // requested before the previous tile's epilogue runs, so their latency is
+  // hidden behind it. Loads complete in issue order, so the norm loads (issued
+  // first) have landed whenever a stage wait below is satisfied.
+  double nrm[4];
+  if (ct_begin < ct_end) {
+    load_norms(a, (int64_t)ct_begin * BBN, wc, lane, nrm);
+    for (int p = 0; p < NSTAGE; ++p)
+      if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, (int64_t)ct_begin * BBN, wave, lane);
+  }
   for (int ct = ct_begin; ct < ct_end; ++ct) {
     const int64_t col0 = (int64_t)ct * BBN;
     floatx16 acc[4][4];
@@ -111,60 +155,73 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    // every wave is past the previous tile's last reads of the ring
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < NSTAGE - 1; ++p)
-      if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, col0, wave, lane);
+    // stage 0 landed for this wave (stages 1-3 may still be in flight), then
+    // for everyone (wait and barrier in one asm statement: no LDS read can be
+    // moved above it)
+    if (n_kc >= 4)
+      asm volatile("s_waitcnt vmcnt(24)\n\ts_barrier" ::: "memory");
+    else if (n_kc == 3)
+      asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
+    else if (n_kc == 2)
+      asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
 
+    // Each stage is two MFMA groups (K = 16 each). The fragments of the next
+    // group are read from LDS while the current group's 16 MFMAs run. Between
+    // the groups every wave has finished reading the stage's ring slot and
+    // stage c + 1 has landed (one barrier); after the second group the slot
+    // is refilled with stage c + NSTAGE. In the last stage the next-group
+    // reads fetch a slot that is never used.
+    bf16x8 fa0[4], fb0[4], fa1[4], fb1[4];
+    read_frags(As, Bs, 0, 0, wr, wc, lane, fa0, fb0);
     for (int c = 0; c < n_kc; ++c) {
-      // wait for this wave's loads of stage c (2 loads per block and stage),
-      // then for everyone's
-      const int ahead = min(n_kc - 1 - c, NSTAGE - 2);
-      if (ahead >= 2)
-        asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
-      else if (ahead == 1)
-        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-      else
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      // plain barrier: __syncthreads() would also wait for the later stages'
-      // loads (its fence drains every outstanding memory operation)
-      __builtin_amdgcn_s_barrier();
-      if (c + NSTAGE - 1 < n_kc)
-        issue_stage(a, As, Bs, (c + NSTAGE - 1) % NSTAGE, c + NSTAGE - 1, row0, col0, wave, lane);
       const int st = c % NSTAGE;
-      const bf16x8* as = (const bf16x8*)(As + (st * BKB + (lane >> 5)) * BBM + wr * 128 + (lane & 31));
-      const bf16x8* bs = (const bf16x8*)(Bs + (st * BKB + (lane >> 5)) * BBN + wc * 128 + (lane & 31));
+      read_frags(As, Bs, st, 1, wr, wc, lane, fa1, fb1);
+      mfma_group(acc, fa0, fb0);
 #pragma unroll
-      for (int s = 0; s < BKB / 2; ++s) {
-        bf16x8 fa[4], fb[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          fa[i] = as[2 * s * BBM + 32 * i];
-          fb[i] = bs[2 * s * BBN + 32 * i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      for (int g = 0; g < 8; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
       }
+      // this wave's reads of slot st are done and stage c + 1 landed, then
+      // everyone's
+      const int ahead = min(n_kc - 2 - c, NSTAGE - 2);
+      if (ahead >= 2)
+        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(16)\n\ts_barrier" ::: "memory");
+      else if (ahead == 1)
+        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(8)\n\ts_barrier" ::: "memory");
+      else
+        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(0)\n\ts_barrier" ::: "memory");
+      read_frags(As, Bs, (c + 1) % NSTAGE, 0, wr, wc, lane, fa0, fb0);
+      mfma_group(acc, fa1, fb1);
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      if (c + NSTAGE < n_kc) issue_stage(a, As, Bs, st, c + NSTAGE, row0, col0, wave, lane);
     }
 
-    // ---- epilogue (as in the FP32 kernel) ----
+    // every wave is past its last reads of the ring: the next tile's norms and
+    // first stages go out now and land during this epilogue
     float inv[4];
     int32_t ecol[4];
 #pragma unroll
     for (int bn = 0; bn < 4; ++bn) {
       const int64_t e = col0 + wc * 128 + bn * 32 + (lane & 31);
       ecol[bn] = (int32_t)e;
-      if (e < a.n_entries) {
-        const double n = a.norm ? a.norm[e] : 1.0;
-        inv[bn] = n > 0.0 ? (float)(1.0 / (n * n)) : 0.0f;
-      } else {
-        inv[bn] = -1.0f;
-      }
+      inv[bn] = e < a.n_entries ? (nrm[bn] > 0.0 ? (float)(1.0 / (nrm[bn] * nrm[bn])) : 0.0f)
+                                : -1.0f;
     }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (ct + 1 < ct_end) {
+      load_norms(a, col0 + BBN, wc, lane, nrm);
+      for (int p = 0; p < NSTAGE; ++p)
+        if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, col0 + BBN, wave, lane);
+    }
+
+    // ---- epilogue (as in the FP32 kernel) ----
     // one row block (4 x 32 x 32 accumulators) at a time: a rolled loop with a
     // switch keeps only 64 accumulator values live in VGPRs
 #pragma unroll 1
@@ -176,6 +233,16 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
         case 2: blk[0] = acc[2][0]; blk[1] = acc[2][1]; blk[2] = acc[2][2]; blk[3] = acc[2][3]; break;
         default: blk[0] = acc[3][0]; blk[1] = acc[3][1]; blk[2] = acc[3][2]; blk[3] = acc[3][3]; break;
       }
+      // thresholds (the current k-th best of each voxel of this block), read
+      // once; an insertion below can only raise a threshold, so a value read
+      // here lets through a superset of the candidates, which list_insert
+      // filters exactly
+      float thr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
+        thr[q] = myLs[vme * BKK_MAX + kk - 1];
+      }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int r = 4 * (q >> 1) + 2 * (q & 1);
@@ -185,10 +252,9 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
           const float re = blk[bn][r], im = blk[bn][r + 1];
           sc[bn] = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
         }
-        // threshold: the current k-th best of this lane's voxel (list tail in LDS)
-        const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
         const float mx = fmaxf(fmaxf(sc[0], sc[1]), fmaxf(sc[2], sc[3]));
-        if (__ballot(mx > myLs[vme * BKK_MAX + kk - 1]) == 0) continue;  // common case
+        if (__ballot(mx > thr[q]) == 0) continue;  // common case
+        const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
 #pragma unroll
         for (int bn = 0; bn < 4; ++bn) {
           uint64_t m = __ballot(sc[bn] > myLs[vme * BKK_MAX + kk - 1]);
