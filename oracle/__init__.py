@@ -81,6 +81,8 @@ def lib():
         L.orc_bruteforce.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
                                      C.c_int32, C.c_int32, lp, dp, dp, dp, dp, lp, dp,
                                      C.c_int32]
+        L.orc_cc_map.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
+                                 C.c_int32, C.c_int64, C.c_int64, dp, C.c_int32]
         L.orc_schedule_paper.argtypes = [C.POINTER(GridS), C.POINTER(Seq),
                                          C.POINTER(Schedule)]
         L.orc_zoom_generic.argtypes = [C.POINTER(Schedule), ip, ip, OBJECTIVE, C.c_void_p,
@@ -197,6 +199,26 @@ def bruteforce(seq, grid, vox, top_k=1, n_tr=None, threads=0) -> dict:
     if rc:
         raise ValueError(f"orc_bruteforce failed ({rc})")
     return dict(idx=idx, cc=ccv, margin=mg, pd=pr + 1j * pi, topk_idx=tki, topk_cc=tkc)
+
+
+def cc_map(seq, grid, vox, k0=0, count=None, n_tr=None, threads=0) -> np.ndarray:
+    """CC (Eq. 1) of each fingerprint against every entry of [k0, k0 + count)
+    of the grid (Experiment 1's CC mapping): float64 [n_vox][count]."""
+    vox = np.atleast_2d(np.asarray(vox, np.complex128))
+    n_vox = vox.shape[0]
+    n_tr = vox.shape[1] if n_tr is None else n_tr
+    vox = vox[:, :n_tr]
+    s, ks = make_seq(seq)
+    g, kg = make_grid(grid)
+    count = grid.size - k0 if count is None else count
+    vr = np.ascontiguousarray(vox.real)
+    vi = np.ascontiguousarray(vox.imag)
+    out = np.zeros((n_vox, count))
+    rc = lib().orc_cc_map(C.byref(s), C.byref(g), n_tr, _dp(vr), _dp(vi), n_vox, int(k0),
+                          int(count), _dp(out), _threads(threads))
+    if rc:
+        raise ValueError(f"orc_cc_map failed ({rc})")
+    return out
 
 
 def schedule_to_dict(s: Schedule) -> dict:

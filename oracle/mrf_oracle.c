@@ -403,6 +403,60 @@ int orc_bruteforce(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
 }
 
 /* ------------------------------------------------------------------------ */
+/* CC map (Methods and Results, Experiment 1): the CC of Eq. 1 between each   */
+/* fingerprint and every entry of [k0, k0 + count), written out in full.      */
+/* ------------------------------------------------------------------------ */
+
+int orc_cc_map(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
+               const double* vr, const double* vi, int32_t n_vox, int64_t k0,
+               int64_t count, double* out, int32_t n_threads) {
+  if (!grid || n_vox < 0 || count < 0 || k0 < 0 ||
+      (n_vox > 0 && count > 0 && (!vr || !vi || !out)))
+    return 1;
+  tables t;
+  int rc = tables_build(seq, grid, n_tr, &t);
+  if (rc) return rc;
+  if (k0 + count > grid_size(grid)) {
+    tables_free(&t);
+    return 1;
+  }
+  double* vnorm = (double*)malloc(sizeof(double) * (size_t)(n_vox + 1));
+  for (int32_t v = 0; v < n_vox; ++v)
+    vnorm[v] = sqrt(norm2(n_tr, vr + (size_t)v * n_tr, vi + (size_t)v * n_tr));
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+  {
+    double* re = (double*)malloc(sizeof(double) * (size_t)(n_tr + 1));
+    double* im = (double*)malloc(sizeof(double) * (size_t)(n_tr + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < count; ++i) {
+      entry_factors f;
+      tables_view(&t, k0 + i, &f);
+      run_entry(n_tr, t.inversion, &f, re, im, NULL);
+      double nd = sqrt(norm2(n_tr, re, im));
+      for (int32_t v = 0; v < n_vox; ++v) {
+        double c = 0.0;
+        if (nd != 0.0 && vnorm[v] != 0.0) {
+          double sr, si;
+          cdot(n_tr, vr + (size_t)v * n_tr, vi + (size_t)v * n_tr, re, im, &sr, &si);
+          c = sqrt(sr * sr + si * si) / (vnorm[v] * nd);
+        }
+        out[(size_t)v * count + i] = c;
+      }
+    }
+    free(re);
+    free(im);
+  }
+  free(vnorm);
+  tables_free(&t);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ZOOM (Theory: MRF ZOOM; Methods: Experiment 2 procedure).                 */
 /* ------------------------------------------------------------------------ */
 

@@ -96,6 +96,11 @@ int orc_bruteforce(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
                    double* pd_re, double* pd_im, int64_t* topk_idx,
                    double* topk_cc, int32_t n_threads);
 
+/* ---- CC map (Experiment 1): out[v][i] = CC(v, entry k0 + i), Eq. 1 ---- */
+int orc_cc_map(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
+               const double* vr, const double* vi, int32_t n_vox, int64_t k0,
+               int64_t count, double* out, int32_t n_threads);
+
 /* ---- ZOOM ---- */
 int orc_schedule_paper(const orc_grid* grid, const orc_seq* seq,
                        orc_schedule* out);
