@@ -37,6 +37,10 @@ def parse():
     p.add_argument("--copy-probe-gb", type=float, default=0.0,
                    help="only run a plain device copy of this size (3 times), the reference "
                         "for scaling HBM byte counters, and exit")
+    p.add_argument("--no-ccmap", action="store_true",
+                   help="skip the CC map of Experiment 1 and its Property I-III checks")
+    p.add_argument("--no-peaks", action="store_true",
+                   help="skip the measured device peaks (MFMA-only loops, write and copy streams)")
     p.add_argument("--serve-requests", type=int, default=60)
     p.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     return p.parse_args()
@@ -228,6 +232,17 @@ def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
     }
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target_s: float):
     """The FP64 oracle's brute force on a bounded sample: a few voxels against
     a leading slab of T1 rows of the grid, extrapolated to the whole grid."""
@@ -256,9 +271,116 @@ def cpu_baseline(w, target_s: float):
     oracle.bruteforce(w.seq, sub, V, threads=threads)
     dt = time.perf_counter() - t
     full_s = dt * w.grid.size / sub.size
+    # the same oracle on one core, on one T1 row
+    sub1 = I.make_grid(w.grid.t1_ms[:1], w.grid.t2_ms, w.grid.df_hz)
+    t = time.perf_counter()
+    oracle.bruteforce(w.seq, sub1, V, threads=1)
+    dt1 = time.perf_counter() - t
     return {"value": nv / full_s, "unit": "voxels/s", "cores": threads, "kind": "oracle",
             "sample": f"{nv} voxels x {sub.size} entries ({rows} of {len(w.grid.t1_ms)} T1 rows) "
-                      f"in {dt:.1f} s, extrapolated to {w.grid.size} entries"}
+                      f"in {dt:.1f} s, extrapolated to {w.grid.size} entries",
+            "one_core": {"value": nv / (dt1 * w.grid.size / sub1.size), "unit": "voxels/s",
+                         "sample": f"{nv} voxels x {sub1.size} entries (1 T1 row) in {dt1:.1f} s"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+# FP32 flops per entry and readout of the CC-map recursion with general RF
+# pulses: 3x3 rotation (15), two precession + relaxation intervals (2 x 10),
+# |d|^2 (4), v conj(d) (8), |v|^2 shared by two entries (2), counted from the
+# kernel's 28 FMA-class instructions per entry and readout.
+CC_MAP_FLOPS_PER_STEP = 56.0
+# FP32 VALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz (the published 157.3 TFLOP/s counts packed FP32 pairs)
+FP32_VALU_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def cc_map_bench(api, ctx, torch, repeats: int = 5):
+    """CC mapping after Experiment 1 (37,260,000 entries, N = 500): the map of
+    one fingerprint, simulated on the fly, and the Property I-III checks."""
+    from paper_1506_05393_amd import properties, workloads as W
+    name, seq, grid, truth, ti = W.exp1_ccmap()
+    sq = api.Sequence(ctx, seq)
+    params = torch.tensor([[truth[0], truth[1], truth[2], 1.0]], dtype=torch.float64,
+                          device=ctx.device)
+    v = api.simulate_signals(ctx, sq, params)
+    out = torch.empty((1, grid.size), dtype=torch.float32, device=ctx.device)
+    api.cc_map(ctx, sq, grid, v, out=out)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read("k_cc_map", reset=True)
+    for _ in range(repeats):
+        api.cc_map(ctx, sq, grid, v, out=out)
+    torch.cuda.synchronize()
+    ms, n = ctx.profile_read("k_cc_map")
+    ctx.profile(False)
+    ms /= max(n, 1)
+    m = out[0].cpu().numpy()
+    E, N = grid.size, seq.n
+    kt = (ti[0] * len(grid.t2_ms) + ti[1]) * len(grid.df_hz) + ti[2]
+    props = properties.check(m, (len(grid.t1_ms), len(grid.t2_ms), len(grid.df_hz)), grid.df_hz,
+                             grid.t1_ms, grid.t2_ms, seq.tr_ms, truth=ti)
+    tflops = E * N * CC_MAP_FLOPS_PER_STEP / (ms * 1e-3) / 1e12
+    return {"workload": name, "entries": E, "n_tr": N, "truth_T1_T2_df": list(truth),
+            "kernel": "k_cc_map", "ms": ms, "launches": n,
+            "entries_per_s": E / (ms * 1e-3), "readout_steps_per_s": E * N / (ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": tflops,
+                         "peak": FP32_VALU_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / FP32_VALU_UNPACKED_TFLOPS,
+                         "flops_per_entry_readout": CC_MAP_FLOPS_PER_STEP},
+            "argmax_is_truth": bool(int(np.argmax(m)) == kt), "max_cc": float(m.max()),
+            "properties": props,
+            "paper_context": "Experiment 1: 4 h 35 min to generate the dictionary and the CC "
+                             "maps (C++, 2.0 GHz dual-core laptop)"}
+
+
+def device_peaks(api, ctx, torch, write_gb: float = 16.0):
+    """Measured device peaks: MFMA-only loops per dtype and a non-temporal
+    write stream (libmrf probe kernels, timed by HIP events on their launch
+    stream), and a plain copy (torch, timed by events on the same stream)."""
+    n_cu = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    out = torch.empty(n_cu * 2 * 256, dtype=torch.float32, device=ctx.device)
+    res = {"what": "MFMA-only loops (4 independent 32x32 accumulators per wave, 2 waves per "
+                   "SIMD); write = one 16 B store per thread, 4 KB per workgroup; copy = torch copy_"}
+    ctx.profile(True)
+    for dt, iters, per_lane in (("f32", 120000, 16), ("bf16", 240000, 128)):
+        name = "k_probe_mfma_" + dt
+        api.probe_mfma(ctx, dt, 1000, out)
+        torch.cuda.synchronize()
+        ctx.profile_read(name, reset=True)
+        fl = 0.0
+        for _ in range(3):
+            fl = api.probe_mfma(ctx, dt, iters, out)
+        torch.cuda.synchronize()
+        ms, n = ctx.profile_read(name)
+        res[f"mfma_{dt}_tflops"] = fl / (ms / n * 1e-3) / 1e12
+        res[f"mfma_{dt}_output_exact"] = bool((out == float(per_lane * iters)).all().item())
+    nb = int(write_gb * 1e9) // 32 * 32
+    buf = torch.empty(nb, dtype=torch.uint8, device=ctx.device)
+    api.probe_write(ctx, buf)
+    torch.cuda.synchronize()
+    ctx.profile_read("k_probe_write", reset=True)
+    for _ in range(3):
+        api.probe_write(ctx, buf, pattern=0x1234567)
+    torch.cuda.synchronize()
+    ms, n = ctx.profile_read("k_probe_write")
+    ctx.profile(False)
+    res["write_GB_per_s"] = nb / (ms / n * 1e-3) / 1e9
+    w4 = buf.view(torch.int32).view(-1, 4)
+    res["write_output_exact"] = bool(int(w4[0, 0]) == 0x1234567 and int(w4[-1, 0]) == 0x1234567
+                                     and int(w4[-1, 1]) == (w4.shape[0] - 1) % (1 << 32))
+    half = nb // 2
+    x, y = buf[:half], buf[half:]
+    a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    y.copy_(x)
+    a_.record()
+    for _ in range(3):
+        y.copy_(x)
+    b_.record()
+    torch.cuda.synchronize()
+    res["copy_GB_per_s"] = 2 * half / (a_.elapsed_time(b_) / 3 * 1e-3) / 1e9
+    del buf, x, y, w4
+    torch.cuda.empty_cache()
+    return res
 
 
 def copy_probe(gb: float):
@@ -367,6 +489,14 @@ def main():
     torch.cuda.synchronize()
     zl = [a_.elapsed_time(b_) for a_, b_ in zl]
     nsim = outz["n_sim"].cpu().numpy()
+    ccm = None
+    if not args.no_ccmap:
+        log("cc map (Experiment 1) ...")
+        ccm = cc_map_bench(api, ctx, torch)
+    peaks = None
+    if not args.no_peaks:
+        log("device peaks ...")
+        peaks = device_peaks(api, ctx, torch)
 
     per_row = {}
     step_ms = []
@@ -411,7 +541,9 @@ def main():
                      "frac": achieved / PEAK["fp32_mfma_tflops"],
                      "traffic": counted_traffic("mrf::k_match_f32", "match.hip"),
                      "avg_ms": gemm_avg, "launches": gemm_n,
-                     "algorithmic_flops_per_launch": flops},
+                     "algorithmic_flops_per_launch": flops,
+                     "peak_measured": peaks["mfma_f32_tflops"] if peaks else None,
+                     "frac_measured": achieved / peaks["mfma_f32_tflops"] if peaks else None},
         "rows_ms": {k: float(np.median(v)) for k, v in per_row.items()},
         "brute_f32_voxels_per_s": n_vox / (float(np.median(per_row["match_f32"])) * 1e-3),
         "brute_bf16_rescore_voxels_per_s":
@@ -419,6 +551,8 @@ def main():
         "bf16": {"kernel": "k_match_bf16", "avg_ms": b16_avg,
                  "TFLOP_per_s": flops / (b16_avg * 1e-3) / 1e12,
                  "frac_bf16_peak": flops / (b16_avg * 1e-3) / 1e12 / PEAK["bf16_mfma_tflops"],
+                 "frac_bf16_measured": (flops / (b16_avg * 1e-3) / 1e12 / peaks["mfma_bf16_tflops"]
+                                        if peaks else None),
                  "rescore_ms": rs_ms / max(rs_n, 1),
                  "index_agreement_vs_f32": float(np.mean(idx16 == idx32)),
                  "speedup_vs_f32": float(np.median(per_row["match_f32"]) /
@@ -439,6 +573,8 @@ def main():
         "dict_gen": {"kernel": "k_sim_dict", "f32_ms": sim_avg,
                      "f32_GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
                      "f32_frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"],
+                     "f32_frac_write_measured": (dict_bytes / (sim_avg * 1e-3) / 1e9 /
+                                                 peaks["write_GB_per_s"] if peaks else None),
                      "f32_traffic": counted_traffic("mrf::k_sim_dict<1, 1, true>", "sim.hip"),
                      "bf16_ms": float(np.median(per_row["dict_bf16"])),
                      "bf16_GB_per_s": (E * N * 4 + E * 8) /
@@ -450,6 +586,8 @@ def main():
                  "slice_ms_p99": float(np.percentile(zl, 99)), "repeats": len(zl)},
         "slice_latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                              "p99": float(np.percentile(step_ms, 99))},
+        "device_peaks": peaks,
+        "cc_map": ccm,
         "paper_context": "paper: 116.72 s per 1731-voxel 64x64 slice (ZOOM, df dictionary) on a "
                          "2.0 GHz dual-core laptop, C++",
     }

@@ -123,6 +123,26 @@ int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq, const mrf
                             mrf_dtype dtype, void* re, void* im, int64_t ld,
                             double* norm, int32_t unit_norm, void* stream);
 
+/* CC map (Methods and Results, Experiment 1): the CC of Eq. 1 between each
+ * fingerprint and every entry of [entry_begin, entry_begin + entry_count) of
+ * `grid`, written out in full:
+ *   cc[v * ld_cc + i] = |<v, d_e>| / (||v|| ||d_e||),  e = entry_begin + i,
+ * 0 where either norm is 0. The entries are simulated exactly as by
+ * mrf_simulate_dictionary (FP32 recursion, the same step tables) and the CC
+ * is accumulated on the fly (FP32 partial sums of four readouts added into
+ * FP64), so no dictionary is stored and any grid size fits.
+ *   vox: device complex64 [n_vox][ld_vox] (ld_vox >= n_tr; the first n_tr
+ *        readouts are used), caller-owned, 8-byte aligned.
+ *   cc:  device float32 [n_vox][ld_cc] (ld_cc >= entry_count), caller-owned.
+ * One launch per fingerprint on `stream`; returns without waiting (profile
+ * name "k_cc_map").
+ * Errors: NULL pointers with work to do, n_tr outside [1, sequence length],
+ * ld_vox < n_tr, ld_cc < entry_count, a range outside the grid, an invalid
+ * grid -> MRF_ERR_INVALID (nothing launched). */
+int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid, int32_t n_tr,
+               const void* vox, int32_t n_vox, int64_t ld_vox, int64_t entry_begin,
+               int64_t entry_count, float* cc, int64_t ld_cc, void* stream);
+
 /* Simulate fingerprints at arbitrary (not necessarily on-grid) parameter
  * values: params is a device FP64 array [count][4] = (T1 ms, T2 ms, df Hz,
  * B1). Output complex64 out[i*ld_out + j], j < n_tr (raw signal, M0 = 1). */
@@ -389,6 +409,35 @@ int mrf_serve_cancel(mrf_server* srv, uint64_t ticket);
 int mrf_server_stats_read(mrf_server* srv, mrf_server_stats* out);
 /* Drains: waits for every submitted request to finish, then frees the slots. */
 int mrf_server_destroy(mrf_server* srv);
+
+/* ------------------------------------------------------------------------
+ * Device peak probes (measurement aids; not steps of the method). They give
+ * the rates this GPU sustains for the operations the matching GEMMs and the
+ * dictionary generator are bound by, so that achieved rates can be quoted as
+ * fractions of measured peaks beside the published ones. Both launch on
+ * `stream` (a hipStream_t, NULL = default), return without waiting, and are
+ * timed by mrf_profile_* under the names given below.
+ *
+ * mrf_probe_mfma ("k_probe_mfma_f32" / "k_probe_mfma_bf16"): out_len / 256
+ * workgroups of 256 threads; every wave runs `iters` rounds of four
+ * independent MFMAs on register operands (MRF_F32: v_mfma_f32_32x32x2_f32,
+ * 4096 flop each; MRF_BF16: v_mfma_f32_32x32x16_bf16, 32768 flop each), all
+ * operand elements 0.5 and 0.25. out (device float[out_len], caller-owned)
+ * receives each lane's sum of its 64 accumulator values, exactly 16 * iters
+ * (MRF_F32) or 128 * iters (MRF_BF16) while that stays below 2^24. *flops
+ * (host, may be NULL) receives the flops the launch performs.
+ * Errors: out_len not a positive multiple of 256, iters < 1, bad dtype ->
+ * MRF_ERR_INVALID (nothing launched).
+ *
+ * mrf_probe_write ("k_probe_write"): fills `bytes` (a multiple of 16) at dst
+ * (16-byte aligned device memory, caller-owned) with one 16 B store per
+ * thread, each workgroup writing one contiguous 4 KB piece; 16-byte element
+ * i holds the words (pattern, i, pattern, i), i taken modulo 2^32.
+ * Errors: bad size or alignment -> MRF_ERR_INVALID.
+ * ---------------------------------------------------------------------- */
+int mrf_probe_mfma(mrf_context* ctx, mrf_dtype dtype, int64_t iters, float* out, int64_t out_len,
+                   double* flops, void* stream);
+int mrf_probe_write(mrf_context* ctx, void* dst, int64_t bytes, uint32_t pattern, void* stream);
 
 /* ------------------------------------------------------------------------
  * Kernel timing. When enabled, every launch of a named kernel

@@ -65,6 +65,9 @@ _SIGS = [
     ("mrf_simulate_dictionary", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int64, C.c_int64, C.c_int,
       C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("mrf_cc_map", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_void_p, C.c_int32, C.c_int64,
+      C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     ("mrf_simulate_signals", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
       C.c_void_p]),
@@ -74,6 +77,9 @@ _SIGS = [
      [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
       C.POINTER(GridDesc), ResultView, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("mrf_probe_mfma", C.c_int,
+     [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p]),
+    ("mrf_probe_write", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]),
     ("mrf_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
     ("mrf_profile_read", C.c_int,
      [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),

@@ -174,6 +174,33 @@ def simulate_dictionary(ctx: Context, seq: Sequence, grid, n_tr: Optional[int] =
     return d
 
 
+def cc_map(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, n_tr: Optional[int] = None,
+           entry_begin: int = 0, entry_count: Optional[int] = None,
+           out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """CC of Eq. 1 between each fingerprint (complex64 cuda [n_vox, >= n_tr])
+    and every entry of [entry_begin, entry_begin + entry_count) of the grid,
+    simulated on the fly (Experiment 1). Returns float32 cuda [n_vox, count]."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda:
+        raise ValueError("vox must be a complex64 CUDA tensor")
+    if vox.dim() == 1:
+        vox = vox[None]
+    if vox.stride(1) != 1:
+        raise ValueError("vox rows must be contiguous")
+    n_tr = seq.n if n_tr is None else int(n_tr)
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    count = g.grid.size - entry_begin if entry_count is None else int(entry_count)
+    n_vox = vox.shape[0]
+    if out is None:
+        out = torch.empty((n_vox, count), dtype=torch.float32, device=ctx.device)
+    if out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1 or \
+            out.shape[0] < n_vox or out.shape[1] < count:
+        raise ValueError("out must be float32 [>= n_vox, >= count] with contiguous rows")
+    L.check(ctx._lib.mrf_cc_map(ctx.handle, seq.handle, g.ptr, n_tr, vox.data_ptr(), n_vox,
+                                vox.stride(0), int(entry_begin), count, out.data_ptr(),
+                                out.stride(0), _stream_ptr(stream)))
+    return out
+
+
 def simulate_signals(ctx: Context, seq: Sequence, params: torch.Tensor,
                      n_tr: Optional[int] = None, stream=None) -> torch.Tensor:
     """params: float64 cuda [count, 4] (T1, T2, df, B1) -> complex64 [count, n_tr]."""
@@ -513,3 +540,29 @@ def zoom_search_lattice(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, wi
         int(n_slices), vox.stride(0), n_tr, int(stride), _result_view(r), buf.data_ptr(),
         buf.numel(), _stream_ptr(stream)))
     return r
+
+
+# ---- device peak probes (measurement aids, not steps of the method) ----
+
+def probe_mfma(ctx: Context, dtype: str, iters: int, out: torch.Tensor, stream=None) -> float:
+    """MFMA-only loop (libmrf mrf_probe_mfma) writing each lane's accumulator
+    sum into out (float32 cuda, length a multiple of 256: one workgroup per
+    256). Returns the flops the launch performs; it does not wait."""
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 CUDA tensor")
+    fl = C.c_double()
+    L.check(ctx._lib.mrf_probe_mfma(ctx.handle, L.MRF_F32 if dtype == "f32" else L.MRF_BF16,
+                                    int(iters), out.data_ptr(), out.numel(), C.byref(fl),
+                                    _stream_ptr(stream)))
+    return float(fl.value)
+
+
+def probe_write(ctx: Context, dst: torch.Tensor, pattern: int = 0x5A5A5A5A, stream=None) -> int:
+    """Fill a contiguous CUDA tensor with non-temporal 16 B stores (libmrf
+    mrf_probe_write). Returns the bytes written; it does not wait."""
+    if not dst.is_cuda or not dst.is_contiguous():
+        raise ValueError("dst must be a contiguous CUDA tensor")
+    nbytes = dst.numel() * dst.element_size()
+    L.check(ctx._lib.mrf_probe_write(ctx.handle, dst.data_ptr(), nbytes, int(pattern) & 0xFFFFFFFF,
+                                     _stream_ptr(stream)))
+    return nbytes

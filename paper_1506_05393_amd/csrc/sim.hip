@@ -117,6 +117,7 @@ struct SimArgs {
   float* im;
   uint4* packed;    // BF16 blocks
   double* norm;
+  float* cc;        // CC map output (MODE 3)
 };
 
 struct EntryState {
@@ -125,15 +126,25 @@ struct EntryState {
   float r1ti[kQ];
 };
 
+// CC-map accumulators (MODE 3): <v, d> per entry and ||v||^2, FP32 partial
+// sums of four readouts added into FP64 (as the entry norms).
+struct Dots {
+  double re[kQ], im[kQ];
+  double vn2;
+};
+
 // One pass over all readouts for the thread's kQ entries. MODE 0 accumulates
 // the norm only, MODE 1 stores FP32 planes, MODE 2 stores BF16 blocks and
-// also accumulates the norm of the stored (scaled, rounded) values into nb.
+// also accumulates the norm of the stored (scaled, rounded) values into nb,
+// MODE 3 stores nothing and accumulates v conj(d) against the fingerprint
+// `vox` (one value per readout, the same for every thread) into dt.
 template <int MODE, int PK, bool DF_LDS, bool SCALED>
 __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
                                          const float* __restrict__ rftab, rsrc_t r1s, rsrc_t r2s,
                                          rsrc_t rds, float4* sdf, int64_t blk0, int32_t nrec,
                                          const float (&scale)[kQ], double (&n2)[kQ],
-                                         double (&nb)[kQ]) {
+                                         double (&nb)[kQ], const float2* __restrict__ vox,
+                                         Dots& dt) {
   const uint32_t tid = threadIdx.x;
   const int32_t n_tr = a.n_tr, n3 = a.n3;
   const int32_t per = kChunk * n3;  // staged float4 per chunk
@@ -143,7 +154,9 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
     m[q] = initial_spin(a.inversion, st.r1ti[q]);
     n2[q] = 0.0;
     nb[q] = 0.0;
+    dt.re[q] = dt.im[q] = 0.0;
   }
+  dt.vn2 = 0.0;
   float4 pf[kPrefetch];
   if (DF_LDS) {
 #pragma unroll
@@ -166,10 +179,10 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       for (int p = 0; p < kPrefetch; ++p)
         pf[p] = load4(rds, row + 16u * (tid + kThreads * p), 0);
     }
-    float part[kQ], partb[kQ];
+    float part[kQ], partb[kQ], pre[kQ], pim[kQ], pv = 0.f;
     uint32_t w[kQ][4];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) part[q] = partb[q] = 0.f;
+    for (int q = 0; q < kQ; ++q) part[q] = partb[q] = pre[q] = pim[q] = 0.f;
 #pragma unroll
     for (int jj = 0; jj < kChunk; ++jj) {
       const int32_t j = j0 + jj;
@@ -178,6 +191,11 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
                                               : (const void*)(a.re + (int64_t)j * a.ld + blk0),
                                     nrec);
         const rsrc_t wi = make_rsrc(a.im + (int64_t)j * a.ld + blk0, nrec);
+        float2 vj = make_float2(0.f, 0.f);
+        if (MODE == 3) {
+          vj = vox[j];
+          pv = fmaf(vj.x, vj.x, fmaf(vj.y, vj.y, pv));
+        }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
           const float2 r1 = load2(r1s, st.o1[q], (uint32_t)j * a.n1 * 8u);
@@ -203,6 +221,9 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
             const bf16x2_t b = __builtin_bit_cast(bf16x2_t, v);
             partb[q] = __builtin_amdgcn_fdot2_f32_bf16(b, b, partb[q], false);
             if ((jj & 3) == 3) store4(w[q], wr, 16u * (tid + kThreads * q));
+          } else if (MODE == 3) {
+            pre[q] = fmaf(vj.x, ox, fmaf(vj.y, oy, pre[q]));
+            pim[q] = fmaf(vj.y, ox, fmaf(-vj.x, oy, pim[q]));
           }
           free_evolve(m[q], pc.z, pc.w, r2.y, r1.y);
         }
@@ -213,6 +234,15 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
           n2[q] += (double)part[q];
           nb[q] += (double)partb[q];
           part[q] = partb[q] = 0.f;
+          if (MODE == 3) {
+            dt.re[q] += (double)pre[q];
+            dt.im[q] += (double)pim[q];
+            pre[q] = pim[q] = 0.f;
+          }
+        }
+        if (MODE == 3) {
+          dt.vn2 += (double)pv;
+          pv = 0.f;
         }
       }
     }
@@ -233,7 +263,8 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
                                                        const float2* __restrict__ t2tab,
                                                        const float4* __restrict__ dftab,
                                                        const float* __restrict__ rftab,
-                                                       const float* __restrict__ t1ti) {
+                                                       const float* __restrict__ t1ti,
+                                                       const float2* __restrict__ vox) {
   extern __shared__ float4 sdf[];
   const uint32_t tid = threadIdx.x;
   const int64_t blk0 = (int64_t)blockIdx.x * kBlockEntries;
@@ -258,21 +289,34 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
   const rsrc_t rds = make_rsrc(dftab, a.df_bytes);
   float scale[kQ];
   double n2[kQ], nb[kQ];
-  if (a.unit_norm) {
+  Dots dt;
+  if (MODE != 3 && a.unit_norm) {
     // two passes: the norm first, then the entries divided by it
 #pragma unroll
     for (int q = 0; q < kQ; ++q) scale[q] = 1.0f;
-    sim_pass<0, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb);
+    sim_pass<0, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb,
+                                   vox, dt);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) scale[q] = n2[q] > 0.0 ? (float)(1.0 / sqrt(n2[q])) : 0.0f;
     double n2b[kQ];
-    sim_pass<MODE, PK, DF_LDS, true>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2b, nb);
+    sim_pass<MODE, PK, DF_LDS, true>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2b, nb,
+                                     vox, dt);
   } else {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) scale[q] = 1.0f;
-    sim_pass<MODE, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb);
+    sim_pass<MODE, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb,
+                                      vox, dt);
   }
-  if (a.norm) {
+  if (MODE == 3) {
+    // CC = |<v, d>| / (||v|| ||d||) (Eq. 1), 0 when either norm is 0
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int64_t e = blk0 + tid + kThreads * q;
+      const double den = n2[q] * dt.vn2;
+      const double num = dt.re[q] * dt.re[q] + dt.im[q] * dt.im[q];
+      if (e < a.count) a.cc[e] = den > 0.0 ? (float)sqrt(num / den) : 0.0f;
+    }
+  } else if (a.norm) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int64_t e = blk0 + tid + kThreads * q;
@@ -284,29 +328,30 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
 
 template <int MODE, int PK>
 static void launch_sim_variant(const SimArgs& a, const Tables& t, bool df_lds, int64_t blocks,
-                               hipStream_t stream) {
+                               hipStream_t stream, const float2* vox) {
   const dim3 g((unsigned)blocks), b(kThreads);
   const size_t lds = df_lds ? 2 * sizeof(float4) * kChunk * (size_t)a.n3 : 0;
   if (df_lds)
     hipLaunchKernelGGL((k_sim_dict<MODE, PK, true>), g, b, lds, stream, a, t.t1, t.t2, t.df, t.rf,
-                       t.t1ti);
+                       t.t1ti, vox);
   else
     hipLaunchKernelGGL((k_sim_dict<MODE, PK, false>), g, b, 0, stream, a, t.t1, t.t2, t.df, t.rf,
-                       t.t1ti);
+                       t.t1ti, vox);
 }
 
 template <int MODE>
-static void launch_sim_mode(const SimArgs& a, const Tables& t, int64_t blocks, hipStream_t stream) {
+static void launch_sim_mode(const SimArgs& a, const Tables& t, int64_t blocks, hipStream_t stream,
+                            const float2* vox = nullptr) {
   const bool df_lds = a.n3 <= kLdsMaxN3;
   const bool lane = a.n4 > 1;
   if (!lane && t.x_axis_pulses)
-    launch_sim_variant<MODE, kXAxisUniform>(a, t, df_lds, blocks, stream);
+    launch_sim_variant<MODE, kXAxisUniform>(a, t, df_lds, blocks, stream, vox);
   else if (!lane)
-    launch_sim_variant<MODE, kGeneralUniform>(a, t, df_lds, blocks, stream);
+    launch_sim_variant<MODE, kGeneralUniform>(a, t, df_lds, blocks, stream, vox);
   else if (t.x_axis_pulses)
-    launch_sim_variant<MODE, kXAxisLane>(a, t, df_lds, blocks, stream);
+    launch_sim_variant<MODE, kXAxisLane>(a, t, df_lds, blocks, stream, vox);
   else
-    launch_sim_variant<MODE, kGeneralLane>(a, t, df_lds, blocks, stream);
+    launch_sim_variant<MODE, kGeneralLane>(a, t, df_lds, blocks, stream, vox);
 }
 
 // Fingerprints at arbitrary parameters: the factors are computed per readout
@@ -344,10 +389,8 @@ __global__ __launch_bounds__(256) void k_sim_signals(SigArgs a) {
   }
 }
 
-int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count,
-                    mrf_dtype dtype, void* re, void* im, int64_t ld, double* norm, int unit_norm,
-                    hipStream_t stream) {
-  if (count == 0) return MRF_OK;
+// Launch arguments shared by the dictionary and CC-map launches.
+static int sim_args(const Tables& t, int64_t k0, int64_t count, SimArgs* out, int64_t* blocks) {
   // the step tables are addressed through 32-bit buffer ranges
   const int64_t nt = t.n_tr;
   const int64_t b1 = 8 * nt * t.n1, b2 = 8 * nt * t.n2, b3 = 16 * nt * t.n3;
@@ -355,34 +398,62 @@ int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count
     set_error("grid axis too long: a step table of n_tr x axis length exceeds 2 GiB");
     return MRF_ERR_INVALID;
   }
-  SimArgs a;
+  SimArgs a{};
   a.n_tr = t.n_tr;
   a.n1 = t.n1;
   a.n2 = t.n2;
   a.n3 = t.n3;
   a.n4 = t.n4;
   a.inversion = t.inversion;
-  a.unit_norm = unit_norm;
   a.t1_bytes = (int32_t)b1;
   a.t2_bytes = (int32_t)b2;
   a.df_bytes = (int32_t)b3;
   a.k0 = k0;
   a.count = count;
+  *blocks = (count + kBlockEntries - 1) / kBlockEntries;
+  if (*blocks > INT32_MAX) {
+    set_error("too many entries in one call");
+    return MRF_ERR_INVALID;
+  }
+  *out = a;
+  return MRF_OK;
+}
+
+int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count,
+                    mrf_dtype dtype, void* re, void* im, int64_t ld, double* norm, int unit_norm,
+                    hipStream_t stream) {
+  if (count == 0) return MRF_OK;
+  SimArgs a;
+  int64_t blocks = 0;
+  int rc = sim_args(t, k0, count, &a, &blocks);
+  if (rc) return rc;
+  a.unit_norm = unit_norm;
   a.ld = ld;
   a.re = (float*)re;
   a.im = (float*)im;
   a.packed = (uint4*)re;
   a.norm = norm;
-  const int64_t blocks = (count + kBlockEntries - 1) / kBlockEntries;
-  if (blocks > INT32_MAX) {
-    set_error("too many entries in one call");
-    return MRF_ERR_INVALID;
-  }
   ProfScope prof(ctx, "k_sim_dict", stream);
   if (dtype == MRF_F32)
     launch_sim_mode<1>(a, t, blocks, stream);
   else
     launch_sim_mode<2>(a, t, blocks, stream);
+  MRF_HIP(hipGetLastError());
+  return MRF_OK;
+}
+
+// CC map of one fingerprint (Experiment 1): the dictionary recursion of every
+// entry, with the CC of Eq. 1 accumulated on the fly; nothing else is stored.
+static int launch_cc_map(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count,
+                         const float2* vox, float* cc, hipStream_t stream) {
+  if (count == 0) return MRF_OK;
+  SimArgs a;
+  int64_t blocks = 0;
+  int rc = sim_args(t, k0, count, &a, &blocks);
+  if (rc) return rc;
+  a.cc = cc;
+  ProfScope prof(ctx, "k_cc_map", stream);
+  launch_sim_mode<3>(a, t, blocks, stream, vox);
   MRF_HIP(hipGetLastError());
   return MRF_OK;
 }
@@ -420,6 +491,36 @@ extern "C" int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq
   if (rc) return rc;
   return launch_sim_dict(ctx, *t, entry_begin, entry_count, dtype, re, im, ld, norm, unit_norm ? 1 : 0,
                          (hipStream_t)stream);
+}
+
+extern "C" int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                          int32_t n_tr, const void* vox, int32_t n_vox, int64_t ld_vox,
+                          int64_t entry_begin, int64_t entry_count, float* cc, int64_t ld_cc,
+                          void* stream) {
+  MRF_CHECK_ARG(ctx && seq, "context and sequence must not be NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_tr >= 1 && n_tr <= seq->n, "n_tr %d must be in [1, %d]", n_tr, seq->n);
+  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
+  MRF_CHECK_ARG(ld_vox >= n_tr, "ld_vox (%lld) must be >= n_tr (%d)", (long long)ld_vox, n_tr);
+  const int64_t E = grid_size_checked(grid);
+  MRF_CHECK_ARG(entry_begin >= 0 && entry_count >= 0 && entry_begin + entry_count <= E,
+                "entry range [%lld, %lld) outside the grid of %lld entries",
+                (long long)entry_begin, (long long)(entry_begin + entry_count), (long long)E);
+  MRF_CHECK_ARG(ld_cc >= entry_count, "ld_cc (%lld) must be >= entry_count (%lld)",
+                (long long)ld_cc, (long long)entry_count);
+  if (n_vox == 0 || entry_count == 0) return MRF_OK;
+  MRF_CHECK_ARG(vox && cc, "vox and cc must not be NULL");
+  MRF_CHECK_ARG(((uintptr_t)vox & 7) == 0, "vox must be 8-byte aligned (complex64)");
+  const Tables* t = nullptr;
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &t);
+  if (rc) return rc;
+  for (int32_t v = 0; v < n_vox; ++v) {
+    rc = launch_cc_map(ctx, *t, entry_begin, entry_count, (const float2*)vox + (int64_t)v * ld_vox,
+                       cc + (int64_t)v * ld_cc, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return MRF_OK;
 }
 
 extern "C" int mrf_simulate_signals(mrf_context* ctx, const mrf_sequence* seq, int32_t n_tr,

@@ -117,6 +117,41 @@ def make_sequence(n: int, seed: int) -> Sequence:
     return Sequence(fa.astype(np.float64), phase.astype(np.float64), tr, te, 1, 0.0)
 
 
+def _perlin_1d(n: int, spacing: float, rng) -> np.ndarray:
+    """1-D gradient (Perlin) noise at x = 0 .. n-1: random gradients in
+    [-1, 1] on lattice points `spacing` apart, blended with the quintic fade
+    6t^5 - 15t^4 + 10t^3."""
+    x = np.arange(n, dtype=np.float64) / spacing
+    k = np.floor(x).astype(np.int64)
+    t = x - k
+    g = rng.uniform(-1.0, 1.0, int(k.max()) + 2)
+    fade = t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+    return (1.0 - fade) * g[k] * t + fade * g[k + 1] * (t - 1.0)
+
+
+def make_sequence_exp1(n: int = 500, seed: int = 0) -> Sequence:
+    """IR-bSSFP sequence after the description of Experiment 1: flip angles
+    in 0-79 deg from 1-D Perlin noise (lattice spacing 25 readouts, remapped
+    to span 0..79), RF phases cycling 0, 90, 180, 90 deg, TR = 14 ms plus
+    Gaussian noise remapped to span 0..6 ms; TE = TR / 2 (not stated there),
+    ideal inversion, TI = 0."""
+    if n <= 0:
+        raise ValueError("sequence length must be positive")
+    fa_rng, tr_rng = np.random.default_rng(seed).spawn(2)
+    p = _perlin_1d(n, 25.0, fa_rng)
+    fa = 79.0 * (p - p.min()) / max(float(np.ptp(p)), 1e-300)
+    phase = np.array([0.0, 90.0, 180.0, 90.0])[np.arange(n) % 4]
+    g = tr_rng.normal(size=n)
+    tr = 14.0 + 6.0 * (g - g.min()) / max(float(np.ptp(g)), 1e-300)
+    return Sequence(fa, phase, tr, tr / 2.0, 1, 0.0)
+
+
+def grid_halfopen(lo: float, hi: float, step: float) -> np.ndarray:
+    """lo, lo + step, ... below hi (hi excluded)."""
+    n = int(math.ceil((hi - lo) / step - 1e-9))
+    return lo + step * np.arange(n, dtype=np.float64)
+
+
 def grid_linspace(lo: float, hi: float, n: int) -> np.ndarray:
     return np.linspace(lo, hi, n, dtype=np.float64)
 

@@ -60,6 +60,21 @@ def volume(n_slices: int = 8, side: int = 256) -> Workload:
     return Workload(f"volume{n_slices}x{side}x{side}_N1000_B1", seq, grid, ph, 1000)
 
 
+def exp1_ccmap():
+    """CC mapping after Experiment 1: T1 100-5500 ms and T2 50-1200 ms at
+    10 ms, df -300-300 Hz at 1 Hz (half-open ranges: 540 x 115 x 600 =
+    37,260,000 entries), N = 500, one noise-free fingerprint at T1/T2/df =
+    1400 ms / 500 ms / 100 Hz. Returns (name, sequence, grid, truth params,
+    truth grid indices)."""
+    seq = I.make_sequence_exp1(500, 7)
+    grid = I.make_grid(I.grid_halfopen(100, 5500, 10), I.grid_halfopen(50, 1200, 10),
+                       I.grid_halfopen(-300, 300, 1))
+    truth = (1400.0, 500.0, 100.0)
+    idx = (int(np.searchsorted(grid.t1_ms, truth[0])), int(np.searchsorted(grid.t2_ms, truth[1])),
+           int(np.searchsorted(grid.df_hz, truth[2])))
+    return "exp1_ccmap_E37260000_N500", seq, grid, truth, idx
+
+
 def serving_grid() -> I.Grid:
     """Resident serving dictionaries: 196 x 200 x 41 = 1,607,200 entries."""
     return I.make_grid(I.grid_arange(100, 4000, 20), I.grid_arange(10, 2000, 10),

@@ -54,6 +54,9 @@ def test_host_only_calls_without_gpu():
     assert b"strictly increasing" in lib.mrf_last_error()
     neg = inputs.Grid(np.array([-1.0]), np.array([10.0]), np.array([0.0]))
     assert lib.mrf_grid_size(api.GridArg(neg).ptr) == -1
+    # argument checks of the peak probes come before any device work
+    assert lib.mrf_probe_mfma(None, 0, 10, None, 256, None, None) == 1  # MRF_ERR_INVALID
+    assert lib.mrf_probe_write(None, None, 16, 0, None) == 1  # MRF_ERR_INVALID
 
 
 def test_local_refine_schedule_builder():

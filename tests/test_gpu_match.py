@@ -26,8 +26,9 @@ def _check(res, ref, label):
     cc = res["cc"].cpu().numpy().astype(np.float64)
     pinned = ref["margin"] > MARGIN
     agree = idx == ref["idx"]
+    ap = f"{agree[pinned].mean():.4f}" if pinned.any() else "n/a"
     print(f"{label}: pinned {pinned.sum()}/{len(idx)}, agreement pinned "
-          f"{agree[pinned].mean():.4f} all {agree.mean():.4f}, max |dCC| "
+          f"{ap} all {agree.mean():.4f}, max |dCC| "
           f"{np.abs(cc - ref['cc']).max():.2e}")
     assert bool(np.all(agree[pinned])), np.flatnonzero(pinned & ~agree)[:10]
     dcc = float(np.abs(cc - ref["cc"]).max())
