@@ -26,6 +26,7 @@ struct ZoomArgs {
   const float4* dfT;
   const float* rf;
   int32_t n_tr, inversion;
+  int32_t x_axis;  // every RF phase a multiple of 180 deg: pulses rotate about x
   int32_t dims[4];
   const float2* vox;
   int64_t ld_vox;
@@ -88,7 +89,7 @@ struct EngineParams {
   const float2* t2T;
   const float4* dfT;
   const float* rf;
-  int32_t n_tr, inversion, memo_cap;
+  int32_t n_tr, inversion, memo_cap, x_axis;
   int32_t dims[4];
 };
 
@@ -120,36 +121,122 @@ struct Engine {
     return true;
   }
 
-  // CC of this lane's entry against the voxel (Eq. 1 with a unit-norm voxel)
-  __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
-                               double* pn2 = nullptr) const {
+  // CC of this lane's entry against the voxel (Eq. 1 with a unit-norm voxel).
+  // The readout loop is latency-bound unless its loads run ahead: the table
+  // rows, the pulse and the voxel value of readout j + kAhead are requested
+  // while readout j is computed (a ring of kAhead readouts in registers,
+  // filled by a branch-free steady-state loop). Typed pointers keep the loads
+  // off the generic (flat) path: tables through the global address space,
+  // the voxel through LDS. With x-axis pulses (every RF phase a multiple of
+  // 180 deg) only the four entries R11, R12, R21, R22 of the rotation are
+  // read: R00 = 1 and the other terms are exact zeros, so the product rounds
+  // as the full 3 x 3 one does.
+  static constexpr int kAhead = 3;
+  template <bool LANE_R, bool X_AXIS>
+  __device__ float simulate_cc_t(const int32_t* i, float* pdr, float* pdi, double* pn2) const {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) v2 gf2;
+    typedef const __attribute__((address_space(1))) v4 gf4;
+    typedef const __attribute__((address_space(1))) float gf1;
+    typedef const __attribute__((address_space(3))) v2 lf2;
+    constexpr int NR = X_AXIS ? 4 : 9;  // pulse values read per readout
     const int32_t n = pa.n_tr;
-    const float2* p1 = pa.t1T + (int64_t)i[0] * n;
-    const float2* p2 = pa.t2T + (int64_t)i[1] * n;
-    const float4* pd = pa.dfT + (int64_t)i[2] * n;
-    const float* R = pa.rf + (int64_t)i[3] * n * 9;
+    gf2* p1 = (gf2*)(pa.t1T + (int64_t)i[0] * n);
+    gf2* p2 = (gf2*)(pa.t2T + (int64_t)i[1] * n);
+    gf4* pd = (gf4*)(pa.dfT + (int64_t)i[2] * n);
+    gf1* Rp = (gf1*)(pa.rf + (LANE_R ? (int64_t)i[3] * n * 9 : 0));
+    lf2* vl = (lf2*)vs;
+    // the pulse values of readout j: R[0..8], or R11, R12, R21, R22
+    auto ld_pulse = [&](int32_t j, float (&r)[NR]) {
+      if (X_AXIS) {
+        r[0] = Rp[9 * j + 4];
+        r[1] = Rp[9 * j + 5];
+        r[2] = Rp[9 * j + 7];
+        r[3] = Rp[9 * j + 8];
+      } else {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) r[k] = Rp[9 * j + k];
+      }
+    };
     Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
-    for (int32_t j = 0; j < n; ++j) {
-      const float2 r1 = p1[j];
-      const float2 r2 = p2[j];
-      const float4 pc = pd[j];
-      rf_pulse(m, R + 9 * j);
+    // one readout: the pulse, free evolution over TE, the sample's product
+    // with the voxel, free evolution to the end of the TR
+    auto step = [&](v2 r1, v2 r2, v4 pc, v2 v, const float (&R)[NR]) {
+      const float x = m.x, y = m.y, z = m.z;
+      if (X_AXIS) {
+        m.y = fmaf(R[1], z, R[0] * y);
+        m.z = fmaf(R[3], z, R[2] * y);
+      } else {
+        m.x = fmaf(R[2], z, fmaf(R[1], y, R[0] * x));
+        m.y = fmaf(R[5], z, fmaf(R[4], y, R[3] * x));
+        m.z = fmaf(R[8], z, fmaf(R[7], y, R[6] * x));
+      }
       free_evolve(m, pc.x, pc.y, r2.x, r1.x);
-      const float2 v = vs[j];
       // v conj(d): (vr + i vi)(x - i y)
       dr = fmaf(v.x, m.x, fmaf(v.y, m.y, dr));
       di = fmaf(v.y, m.x, fmaf(-v.x, m.y, di));
       n2 = fma((double)m.x, (double)m.x, n2);
       n2 = fma((double)m.y, (double)m.y, n2);
       free_evolve(m, pc.z, pc.w, r2.y, r1.y);
+    };
+    int32_t j = 0;
+    if (n >= 2 * kAhead) {
+      v2 q1[kAhead], q2[kAhead], qv[kAhead];
+      v4 qd[kAhead];
+      float qr[kAhead][NR];
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) {
+        q1[q] = p1[q];
+        q2[q] = p2[q];
+        qd[q] = pd[q];
+        qv[q] = vl[q];
+        ld_pulse(q, qr[q]);
+      }
+      // the ring holds readouts j .. j + kAhead - 1, and j + kAhead <= n
+      for (; j + 2 * kAhead <= n; j += kAhead) {
+#pragma unroll
+        for (int q = 0; q < kAhead; ++q) {
+          const v2 r1 = q1[q], r2 = q2[q], v = qv[q];
+          const v4 pc = qd[q];
+          float R[NR];
+#pragma unroll
+          for (int k = 0; k < NR; ++k) R[k] = qr[q][k];
+          const int32_t jn = j + q + kAhead;
+          q1[q] = p1[jn];
+          q2[q] = p2[jn];
+          qd[q] = pd[jn];
+          qv[q] = vl[jn];
+          ld_pulse(jn, qr[q]);
+          step(r1, r2, pc, v, R);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) step(q1[q], q2[q], qd[q], qv[q], qr[q]);
+      j += kAhead;
+    }
+    for (; j < n; ++j) {
+      float R[NR];
+      ld_pulse(j, R);
+      const v2 r1 = p1[j], r2 = p2[j], v = vl[j];
+      const v4 pc = pd[j];
+      step(r1, r2, pc, v, R);
     }
     if (pdr) *pdr = dr;
     if (pdi) *pdi = di;
     if (pn2) *pn2 = n2;
     if (!(n2 > 0.0)) return 0.0f;
     return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
+  }
+  __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
+                               double* pn2 = nullptr) const {
+    if (pa.dims[3] > 1)
+      return pa.x_axis ? simulate_cc_t<true, true>(i, pdr, pdi, pn2)
+                       : simulate_cc_t<true, false>(i, pdr, pdi, pn2);
+    return pa.x_axis ? simulate_cc_t<false, true>(i, pdr, pdi, pn2)
+                     : simulate_cc_t<false, false>(i, pdr, pdi, pn2);
   }
 
   // Memo: this wave's private open-addressing table in global memory. A slot
@@ -569,6 +656,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.pa.rf = a.rf;
     e.pa.n_tr = a.n_tr;
     e.pa.inversion = a.inversion;
+    e.pa.x_axis = a.x_axis;
     e.pa.memo_cap = a.memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
@@ -857,6 +945,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.rf = t->rf;
   a.n_tr = n_tr;
   a.inversion = t->inversion;
+  a.x_axis = t->x_axis_pulses;
   for (int q = 0; q < 4; ++q) a.dims[q] = dims[q];
   a.vox = (const float2*)vox;
   a.ld_vox = ld_vox;
