@@ -54,16 +54,22 @@ __device__ __forceinline__ int32_t round_half_away(double x) {
   return (int32_t)(x >= 0.0 ? floor(x + 0.5) : -floor(-x + 0.5));
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+// Reductions over the G lanes of a voxel's group (G divides 64; xor offsets
+// below G stay inside the group).
+template <int G>
+__device__ __forceinline__ float grp_max(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, G));
   return v;
 }
 
-// (best, runner-up) of the values held by the lanes
-__device__ __forceinline__ void wave_top2(float v, float& b1, float& b2) {
+// (best, runner-up) of the values held by the group's lanes
+template <int G>
+__device__ __forceinline__ void grp_top2(float v, float& b1, float& b2) {
   float a1 = v, a2 = -INFINITY;
-  for (int o = 32; o > 0; o >>= 1) {
-    const float c1 = __shfl_xor(a1, o), c2 = __shfl_xor(a2, o);
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const float c1 = __shfl_xor(a1, o, G), c2 = __shfl_xor(a2, o, G);
     const float n1 = fmaxf(a1, c1);
     const float n2 = fmaxf(fminf(a1, c1), fmaxf(a2, c2));
     a1 = n1;
@@ -73,12 +79,26 @@ __device__ __forceinline__ void wave_top2(float v, float& b1, float& b2) {
   b2 = a2;
 }
 
-// first lane holding the maximum (ties: lowest lane); -1 if all are -inf
-__device__ __forceinline__ int wave_first_max(float v, float& best) {
-  best = wave_max(v);
+// the group's lanes (bit l = group lane l) for which p holds
+template <int G>
+__device__ __forceinline__ uint64_t grp_ballot(bool p, int gbase) {
+  const uint64_t m = __ballot(p);
+  return G == 64 ? m : (m >> gbase) & ((1ull << (G & 63)) - 1);
+}
+
+// first group lane holding the maximum (ties: lowest lane); -1 if all are -inf
+template <int G>
+__device__ __forceinline__ int grp_first_max(float v, float& best, int gbase) {
+  best = grp_max<G>(v);
   if (!(best > -INFINITY)) return -1;
-  const uint64_t m = __ballot(v == best);
-  return __ffsll((unsigned long long)m) - 1;
+  return __ffsll((unsigned long long)grp_ballot<G>(v == best, gbase)) - 1;
+}
+
+// Orders this wave's earlier LDS and global memory operations before its
+// later ones (a block is one wave; the groups of a wave diverge, so no
+// barrier can be used inside the search).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
 // The fields of ZoomArgs the engine needs, copied into registers (taking the
@@ -93,6 +113,7 @@ struct EngineParams {
   int32_t dims[4];
 };
 
+template <int G>
 struct Engine {
   EngineParams pa;
 
@@ -102,7 +123,8 @@ struct Engine {
   float* mval;
   int64_t tag;       // voxel serial << 40
   float* nbv;  // [8] neighbour values of one pruned move (LDS)
-  int32_t lane;
+  int32_t lane;   // lane within the voxel's group of G lanes
+  int32_t gbase;  // wave lane of the group's lane 0
   int32_t memo_count;
   int32_t n_sim;
   bool overflow;
@@ -273,13 +295,13 @@ struct Engine {
       }
     }
     if (need) val = simulate_cc(i);
-    uint64_t m = __ballot(need);
+    uint64_t m = grp_ballot<G>(need, gbase);
     n_sim += __popcll(m);
     while (m) {
       const int src = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const int64_t ks = __shfl(k, src);
-      const float vv = __shfl(val, src);
+      const int64_t ks = __shfl(k, src, G);
+      const float vv = __shfl(val, src, G);
       if (memo_count * 4 < cap * 3) {
         if (lane == 0) {
           uint32_t s = memo_home(ks);
@@ -292,22 +314,22 @@ struct Engine {
         overflow = true;
       }
     }
-    __syncthreads();  // one wave per block: the memo stores complete before later loads
+    wave_fence();  // the memo stores complete before later loads
     return val;
   }
 
   __device__ void need_centre() {
     if (!cknown) {
       const float v = eval(lane == 0, c);
-      cval = __shfl(v, 0);
+      cval = __shfl(v, 0, G);
       cknown = true;
     }
   }
 
   __device__ void log_top2(float v, bool include_centre) {
     float b1, b2;
-    wave_top2(v, b1, b2);
-    const int nf = __popcll(__ballot(v > -INFINITY));
+    grp_top2<G>(v, b1, b2);
+    const int nf = __popcll(grp_ballot<G>(v > -INFINITY, gbase));
     if (include_centre) {
       const float c1 = cval;
       const float n1 = fmaxf(b1, c1);
@@ -328,23 +350,23 @@ struct Engine {
     float best = -INFINITY, r1 = -INFINITY, r2 = -INFINITY;
     int32_t bp = c[ax];
     int nf = 0;
-    for (int32_t base = 0; base < count; base += 64) {
+    for (int32_t base = 0; base < count; base += G) {
       const int32_t q = base + lane;
       int32_t p[4] = {c[0], c[1], c[2], c[3]};
       p[ax] = lo[ax] + q * s;
       const float v = eval(q < count, p);
       float rb;
-      const int src = wave_first_max(v, rb);
+      const int src = grp_first_max<G>(v, rb, gbase);
       if (src >= 0 && rb > best) {  // earlier rounds hold lower indices: keep them on ties
         best = rb;
-        bp = __shfl(p[ax], src);
+        bp = __shfl(p[ax], src, G);
       }
       float t1, t2;
-      wave_top2(v, t1, t2);
+      grp_top2<G>(v, t1, t2);
       const float n1 = fmaxf(r1, t1), n2 = fmaxf(fminf(r1, t1), fmaxf(r2, t2));
       r1 = n1;
       r2 = n2;
-      nf += __popcll(__ballot(v > -INFINITY));
+      nf += __popcll(grp_ballot<G>(v > -INFINITY, gbase));
     }
     if (nf >= 2) mm = fminf(mm, r1 - r2);
     if (best > -INFINITY) {
@@ -362,23 +384,23 @@ struct Engine {
     float best = cval, r1 = cval, r2 = -INFINITY;
     int32_t bp = c[ax];
     int nf = 1;
-    for (int32_t base = 0; base < count; base += 64) {
+    for (int32_t base = 0; base < count; base += G) {
       const int32_t q = base + lane;
       int32_t p[4] = {c[0], c[1], c[2], c[3]};
       p[ax] = q < count ? gen(q) : c[ax];
       const float v = eval(q < count, p);
       float rb;
-      const int src = wave_first_max(v, rb);
+      const int src = grp_first_max<G>(v, rb, gbase);
       if (src >= 0 && rb > best) {
         best = rb;
-        bp = __shfl(p[ax], src);
+        bp = __shfl(p[ax], src, G);
       }
       float t1, t2;
-      wave_top2(v, t1, t2);
+      grp_top2<G>(v, t1, t2);
       const float n1 = fmaxf(r1, t1), n2 = fmaxf(fminf(r1, t1), fmaxf(r2, t2));
       r1 = n1;
       r2 = n2;
-      nf += __popcll(__ballot(v > -INFINITY));
+      nf += __popcll(grp_ballot<G>(v > -INFINITY, gbase));
     }
     if (nf >= 2) mm = fminf(mm, r1 - r2);
     c[ax] = bp;
@@ -427,13 +449,13 @@ struct Engine {
       L[ax] -= s;
       R[ax] += s;
       if (pruned) {
-        const float vr = __shfl(eval(lane == 0, R), 0);
+        const float vr = __shfl(eval(lane == 0, R), 0, G);
         log_pair(vr, cval);
         if (vr > cval) {
           move_to(R, vr);
           continue;
         }
-        const float vl = __shfl(eval(lane == 0, L), 0);
+        const float vl = __shfl(eval(lane == 0, L), 0, G);
         log_pair(vl, cval);
         if (vl > cval) {
           move_to(L, vl);
@@ -444,7 +466,7 @@ struct Engine {
       const int32_t* P = lane == 0 ? L : R;
       const float v = eval(lane < 2, P);
       log_top2(lane < 2 ? v : -INFINITY, true);
-      const float vl = __shfl(v, 0), vr = __shfl(v, 1);
+      const float vl = __shfl(v, 0, G), vr = __shfl(v, 1, G);
       const bool right = vr > vl;
       const float bv = right ? vr : vl;
       if (bv > cval)
@@ -468,7 +490,7 @@ struct Engine {
     const bool mine = lane < 8 && ((mask >> lane) & 1u);
     const float v = eval(mine, p);
     if (mine) nbv[lane] = v;
-    __syncthreads();
+    wave_fence();
   }
 
   __device__ void zoom2(int a0, int a1, int s0, int s1, bool pruned) {
@@ -483,7 +505,7 @@ struct Engine {
         const float v = eval(lane < 8, p);
         log_top2(lane < 8 ? v : -INFINITY, true);
         float bv;
-        const int src = wave_first_max(lane < 8 ? v : -INFINITY, bv);
+        const int src = grp_first_max<G>(lane < 8 ? v : -INFINITY, bv, gbase);
         if (src >= 0 && bv > cval) {
           int32_t q[4];
           neighbour(src, a0, a1, s0, s1, q);
@@ -496,7 +518,7 @@ struct Engine {
       // evaluation-saving rules (Theory section)
       float* v = nbv;
       if (lane < 8) v[lane] = -INFINITY;
-      __syncthreads();
+      wave_fence();
       const float C = cval;
       eval_nb((1u << NL) | (1u << ND), a0, a1, s0, s1);
       log_pair(v[NL], C);
@@ -584,20 +606,35 @@ __global__ void k_zoom_init(int32_t* counter, mrf_zoom_schedule sch, mrf_zoom_sc
   }
 }
 
+// LDS bytes per voxel group: the unit-norm voxel, the per-start results and
+// the neighbour values of one pruned move.
+__host__ __device__ inline size_t zoom_group_lds(int32_t n_tr) {
+  return ((size_t)n_tr * sizeof(float2) + 15) / 16 * 16 +
+         MRF_ZOOM_MAX_STARTS * (sizeof(int64_t) + sizeof(float)) + 8 * sizeof(float);
+}
+
+// One wave per block, 64 / G voxels per wave: each group of G lanes runs its
+// own voxel's stage machine and pulls its own voxels from the queue, so the
+// lanes that a decision leaves idle in one group work for the others.
+template <int G>
 __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
+  constexpr int NG = 64 / G;
   extern __shared__ __align__(16) unsigned char sm[];
   const int32_t n = a.n_tr;
-  float2* vs = (float2*)sm;
-  int64_t* fin_k = (int64_t*)(sm + ((size_t)n * sizeof(float2) + 15) / 16 * 16);  // [MAX_STARTS]
-  float* fin_v = (float*)(fin_k + MRF_ZOOM_MAX_STARTS);                            // [MAX_STARTS]
-  float* nbv = fin_v + MRF_ZOOM_MAX_STARTS;                                       // [8]
   const int lane = threadIdx.x;
+  const int grp = lane / G, glane = lane % G, gbase = grp * G;
+  unsigned char* gsm = sm + (size_t)grp * zoom_group_lds(n);
+  float2* vs = (float2*)gsm;
+  int64_t* fin_k = (int64_t*)(gsm + ((size_t)n * sizeof(float2) + 15) / 16 * 16);  // [MAX_STARTS]
+  float* fin_v = (float*)(fin_k + MRF_ZOOM_MAX_STARTS);                             // [MAX_STARTS]
+  float* nbv = fin_v + MRF_ZOOM_MAX_STARTS;                                        // [8]
   const mrf_zoom_schedule* __restrict__ S = a.sch;
-  // this wave's memo; serial 0 marks never-used slots
-  int64_t* mkey = a.memo_keys + (int64_t)blockIdx.x * a.memo_cap;
-  float* mval = a.memo_vals + (int64_t)blockIdx.x * a.memo_cap;
-  for (int32_t i = lane; i < a.memo_cap; i += 64)
-    __hip_atomic_store(mkey + i, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // this group's memo; serial 0 marks never-used slots
+  int64_t* mkey = a.memo_keys + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
+  float* mval = a.memo_vals + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
+  for (int32_t i = lane; i < NG * a.memo_cap; i += 64)
+    __hip_atomic_store(a.memo_keys + (int64_t)blockIdx.x * NG * a.memo_cap + i, (int64_t)0,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   int64_t serial = 0;
 
@@ -605,8 +642,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   const int32_t lw = a.lat_pass ? (W + L - 1) / L : 0, lh = a.lat_pass ? (H + L - 1) / L : 0;
   for (;;) {
     int p = 0;
-    if (lane == 0) p = atomicAdd(a.counter, 1);
-    p = __shfl(p, 0);
+    if (glane == 0) p = atomicAdd(a.counter, 1);
+    p = __shfl(p, 0, G);
     if (p >= a.n_items) break;
     // queue position -> voxel (slice-major raster order for the lattice passes)
     int v = p;
@@ -633,22 +670,22 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     // unit-norm voxel (norm in FP64) into LDS
     const float2* src = a.vox + (int64_t)v * a.ld_vox;
     double s2 = 0.0;
-    for (int32_t j = lane; j < n; j += 64) {
+    for (int32_t j = glane; j < n; j += G) {
       const float2 x = src[j];
       s2 = fma((double)x.x, (double)x.x, s2);
       s2 = fma((double)x.y, (double)x.y, s2);
     }
-    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    for (int o = G / 2; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, G);
     const double nv = sqrt(s2);
     const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
-    for (int32_t j = lane; j < n; j += 64) {
+    for (int32_t j = glane; j < n; j += G) {
       const float2 x = src[j];
       vs[j] = make_float2(x.x * inv, x.y * inv);
     }
     ++serial;
-    __syncthreads();
+    wave_fence();
 
-    Engine e;
+    Engine<G> e;
     e.pa.t1T = a.t1T;
     e.pa.t1ti = a.t1ti;
     e.pa.t2T = a.t2T;
@@ -665,7 +702,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.mval = mval;
     e.tag = serial << 40;
     e.nbv = nbv;
-    e.lane = lane;
+    e.lane = glane;
+    e.gbase = gbase;
     e.memo_count = 0;
     e.n_sim = 0;
     e.overflow = false;
@@ -708,7 +746,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       }
       e.need_centre();
       const int64_t k = e.key(e.c);
-      if (lane == 0) {
+      if (glane == 0) {
         fin_v[st] = e.cval;
         fin_k[st] = k;
       }
@@ -718,15 +756,15 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
         for (int q = 0; q < 4; ++q) bi[q] = e.c[q];
       }
     }
-    __syncthreads();
+    wave_fence();
     for (int st = 0; st < n_starts; ++st)
       if (fin_k[st] != bk) e.log_pair(bv, fin_v[st]);
 
     // proton density of the found entry: <v, d> / ||d||^2
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
-    if (lane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
-    if (lane == 0) {
+    if (glane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
+    if (glane == 0) {
       a.idx[v] = bk;
       if (a.cc) a.cc[v] = bv;
       if (a.margin) a.margin[v] = e.mm;
@@ -734,7 +772,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       if (a.pd_re) a.pd_re[v] = n2 > 0.0 ? (float)(nv * (double)dr / n2) : 0.0f;
       if (a.pd_im) a.pd_im[v] = n2 > 0.0 ? (float)(nv * (double)di / n2) : 0.0f;
     }
-    __syncthreads();
+    wave_fence();
   }
 }
 
@@ -776,23 +814,35 @@ static mrf_zoom_stage stage(int32_t kind, int32_t a0, int32_t a1, int32_t s0, in
 struct ZoomPlan {
   size_t lds;
   int blocks;
+  int group;  // lanes per voxel
   int32_t cap;
   size_t off_sched, off_keys, off_vals, total;
 };
 
+// Smallest voxel group (most voxels per wave) whose LDS fits 64 KB per wave.
+constexpr int kZoomGroups[] = {16, 32, 64};
+
 static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_entries) {
   ZoomPlan p;
-  // memo slots per wave: fine 4-parameter grids make long unit-step walks
+  // memo slots per voxel group: fine 4-parameter grids make long unit-step walks
   p.cap = grid_entries > ((int64_t)1 << 26) ? 32768 : 4096;
-  p.lds = ((size_t)n_tr * sizeof(float2) + 15) / 16 * 16 +
-          MRF_ZOOM_MAX_STARTS * (sizeof(float) + sizeof(int64_t)) + 8 * sizeof(float) + 16;
+  p.group = 64;
+  for (int g : kZoomGroups)
+    if ((size_t)(64 / g) * zoom_group_lds(n_tr) + 16 <= 64 * 1024) {
+      p.group = g;
+      break;
+    }
+  const int ng = 64 / p.group;
+  p.lds = (size_t)ng * zoom_group_lds(n_tr) + 16;
   const int per_cu = std::max(1, std::min(16, (int)((160 * 1024) / p.lds)));
-  p.blocks = std::max(1, std::min(n_vox, n_cu * per_cu));
+  const int64_t waves_needed = ((int64_t)n_vox + ng - 1) / ng;
+  p.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(waves_needed, (int64_t)n_cu * per_cu));
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t slots = (size_t)p.blocks * ng * p.cap;
   p.off_sched = 256;
   p.off_keys = al(p.off_sched + sizeof(mrf_zoom_schedule));
-  p.off_vals = al(p.off_keys + sizeof(int64_t) * (size_t)p.blocks * p.cap);
-  p.total = al(p.off_vals + sizeof(float) * (size_t)p.blocks * p.cap);
+  p.off_vals = al(p.off_keys + sizeof(int64_t) * slots);
+  p.total = al(p.off_vals + sizeof(float) * slots);
   return p;
 }
 
@@ -976,32 +1026,38 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   MRF_HIP(hipGetLastError());
   static bool attr = false;
   if (!attr) {
-    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                64 * 1024));
+    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom<16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom<32>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom<64>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
     attr = true;
   }
-  if (!lattice) {
+  auto launch = [&]() {
     ProfScope prof(ctx, "k_zoom", st);
-    hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
+    if (plan.group == 16)
+      hipLaunchKernelGGL(k_zoom<16>, dim3(blocks), dim3(64), lds, st, a);
+    else if (plan.group == 32)
+      hipLaunchKernelGGL(k_zoom<32>, dim3(blocks), dim3(64), lds, st, a);
+    else
+      hipLaunchKernelGGL(k_zoom<64>, dim3(blocks), dim3(64), lds, st, a);
+  };
+  if (!lattice) {
+    launch();
   } else {
     // pass 1: the lattice voxels, no prior
     const int32_t L = lattice[3];
     a.lat_pass = 1;
     a.n_items = lattice[2] * ((lattice[0] + L - 1) / L) * ((lattice[1] + L - 1) / L);
-    {
-      ProfScope prof(ctx, "k_zoom", st);
-      hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
-    }
+    launch();
     MRF_HIP(hipGetLastError());
     // pass 2: every other voxel from its nearest lattice voxel's result
     hipLaunchKernelGGL(k_zoom_init, dim3(1), dim3(64), 0, st, a.counter, *sched, dsch);
     MRF_HIP(hipGetLastError());
     a.lat_pass = 2;
     a.n_items = n_vox;
-    {
-      ProfScope prof(ctx, "k_zoom", st);
-      hipLaunchKernelGGL(k_zoom, dim3(blocks), dim3(64), lds, st, a);
-    }
+    launch();
   }
   MRF_HIP(hipGetLastError());
   return MRF_OK;
