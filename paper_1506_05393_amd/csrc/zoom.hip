@@ -1,14 +1,15 @@
 // K6: MRF-ZOOM (Theory: MRF ZOOM; Methods: Experiment 2 zooming steps 1-5;
 // Experiment 3 neighbour prior) as a persistent kernel.
 //
-// One wavefront per voxel, pulled from an atomic queue so that voxels with
-// uneven numbers of evaluations balance across the machine. The stage machine
-// runs in wave-uniform control flow; each decision's candidate entries are
-// evaluated one per lane (rounds of 64), simulated on the fly with the same
+// Each voxel is searched by a group of G lanes (8 voxels per wave for G = 8),
+// pulled from an atomic queue so that voxels with uneven numbers of
+// evaluations balance across the machine. A group's stage machine runs in
+// group-uniform control flow; each decision's candidate entries are
+// evaluated one per lane (rounds of G), simulated on the fly with the same
 // step function as the dictionary kernel (bit-identical entries), with the
-// correlation against the unit-norm voxel accumulated inside the readout loop.
-// The unit-norm voxel lives in LDS; each wave owns a memo (entry -> CC, so
-// every distinct entry is simulated once per voxel) in global memory.
+// correlation against the unit-norm voxel accumulated inside the readout
+// loop. Each group owns a memo (entry -> CC, so every distinct entry is
+// simulated once per voxel) in global memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -118,7 +119,8 @@ struct Engine {
   EngineParams pa;
 
   static constexpr int64_t kIndexMask = ((int64_t)1 << 40) - 1;
-  const float2* vs;  // unit-norm voxel in LDS
+  const float2* vx;  // the voxel's fingerprint (global memory, read-only)
+  float vinv;        // 1 / ||v||: the unit-norm voxel is vx * vinv
   int64_t* mkey;     // this wave's memo (global memory)
   float* mval;
   int64_t tag;       // voxel serial << 40
@@ -161,14 +163,13 @@ struct Engine {
     typedef const __attribute__((address_space(1))) v2 gf2;
     typedef const __attribute__((address_space(1))) v4 gf4;
     typedef const __attribute__((address_space(1))) float gf1;
-    typedef const __attribute__((address_space(3))) v2 lf2;
     constexpr int NR = X_AXIS ? 4 : 9;  // pulse values read per readout
     const int32_t n = pa.n_tr;
     gf2* p1 = (gf2*)(pa.t1T + (int64_t)i[0] * n);
     gf2* p2 = (gf2*)(pa.t2T + (int64_t)i[1] * n);
     gf4* pd = (gf4*)(pa.dfT + (int64_t)i[2] * n);
     gf1* Rp = (gf1*)(pa.rf + (LANE_R ? (int64_t)i[3] * n * 9 : 0));
-    lf2* vl = (lf2*)vs;
+    gf2* vl = (gf2*)vx;
     // the pulse values of readout j: R[0..8], or R11, R12, R21, R22
     auto ld_pulse = [&](int32_t j, float (&r)[NR]) {
       if (X_AXIS) {
@@ -197,9 +198,10 @@ struct Engine {
         m.z = fmaf(R[8], z, fmaf(R[7], y, R[6] * x));
       }
       free_evolve(m, pc.x, pc.y, r2.x, r1.x);
-      // v conj(d): (vr + i vi)(x - i y)
-      dr = fmaf(v.x, m.x, fmaf(v.y, m.y, dr));
-      di = fmaf(v.y, m.x, fmaf(-v.x, m.y, di));
+      // v conj(d): (vr + i vi)(x - i y), v the unit-norm voxel
+      const float vr = v.x * vinv, vi = v.y * vinv;
+      dr = fmaf(vr, m.x, fmaf(vi, m.y, dr));
+      di = fmaf(vi, m.x, fmaf(-vr, m.y, di));
       n2 = fma((double)m.x, (double)m.x, n2);
       n2 = fma((double)m.y, (double)m.y, n2);
       free_evolve(m, pc.z, pc.w, r2.y, r1.y);
@@ -606,11 +608,10 @@ __global__ void k_zoom_init(int32_t* counter, mrf_zoom_schedule sch, mrf_zoom_sc
   }
 }
 
-// LDS bytes per voxel group: the unit-norm voxel, the per-start results and
-// the neighbour values of one pruned move.
-__host__ __device__ inline size_t zoom_group_lds(int32_t n_tr) {
-  return ((size_t)n_tr * sizeof(float2) + 15) / 16 * 16 +
-         MRF_ZOOM_MAX_STARTS * (sizeof(int64_t) + sizeof(float)) + 8 * sizeof(float);
+// LDS bytes per voxel group: the per-start results and the neighbour values
+// of one pruned move.
+__host__ __device__ inline size_t zoom_group_lds() {
+  return MRF_ZOOM_MAX_STARTS * (sizeof(int64_t) + sizeof(float)) + 8 * sizeof(float);
 }
 
 // One wave per block, 64 / G voxels per wave: each group of G lanes runs its
@@ -623,9 +624,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   const int32_t n = a.n_tr;
   const int lane = threadIdx.x;
   const int grp = lane / G, glane = lane % G, gbase = grp * G;
-  unsigned char* gsm = sm + (size_t)grp * zoom_group_lds(n);
-  float2* vs = (float2*)gsm;
-  int64_t* fin_k = (int64_t*)(gsm + ((size_t)n * sizeof(float2) + 15) / 16 * 16);  // [MAX_STARTS]
+  unsigned char* gsm = sm + (size_t)grp * zoom_group_lds();
+  int64_t* fin_k = (int64_t*)gsm;                                                  // [MAX_STARTS]
   float* fin_v = (float*)(fin_k + MRF_ZOOM_MAX_STARTS);                             // [MAX_STARTS]
   float* nbv = fin_v + MRF_ZOOM_MAX_STARTS;                                        // [8]
   const mrf_zoom_schedule* __restrict__ S = a.sch;
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       prior_v = (s * H + py) * W + px;
     }
 
-    // unit-norm voxel (norm in FP64) into LDS
+    // the voxel's norm (FP64); the search reads the voxel scaled by 1 / norm
     const float2* src = a.vox + (int64_t)v * a.ld_vox;
     double s2 = 0.0;
     for (int32_t j = glane; j < n; j += G) {
@@ -678,12 +678,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     for (int o = G / 2; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, G);
     const double nv = sqrt(s2);
     const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
-    for (int32_t j = glane; j < n; j += G) {
-      const float2 x = src[j];
-      vs[j] = make_float2(x.x * inv, x.y * inv);
-    }
     ++serial;
-    wave_fence();
 
     Engine<G> e;
     e.pa.t1T = a.t1T;
@@ -697,7 +692,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.pa.memo_cap = a.memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
-    e.vs = vs;
+    e.vx = src;
+    e.vinv = inv;
     e.mkey = mkey;
     e.mval = mval;
     e.tag = serial << 40;
@@ -819,21 +815,27 @@ struct ZoomPlan {
   size_t off_sched, off_keys, off_vals, total;
 };
 
-// Smallest voxel group (most voxels per wave) whose LDS fits 64 KB per wave.
-constexpr int kZoomGroups[] = {16, 32, 64};
+// Lanes per voxel: the smallest group (most voxels per wave) that still
+// gives every SIMD a wave. A 2-D move evaluates up to 8 neighbours at once,
+// so groups of 8 leave the fewest lanes idle once there are enough voxels
+// (measured on the four-parameter volume: 8 lanes 825 ms, 16 lanes 1035 ms,
+// 64 lanes 2233 ms per 256 x 256 slice; on a 64 x 64 slice 16 lanes, one
+// wave per SIMD, beat 8 lanes, half a wave per SIMD).
+constexpr int kZoomGroups[] = {8, 16, 32, 64};
 
 static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_entries) {
   ZoomPlan p;
   // memo slots per voxel group: fine 4-parameter grids make long unit-step walks
   p.cap = grid_entries > ((int64_t)1 << 26) ? 32768 : 4096;
+  (void)n_tr;
   p.group = 64;
   for (int g : kZoomGroups)
-    if ((size_t)(64 / g) * zoom_group_lds(n_tr) + 16 <= 64 * 1024) {
+    if (((int64_t)n_vox + 64 / g - 1) / (64 / g) >= 4 * (int64_t)n_cu) {
       p.group = g;
       break;
     }
   const int ng = 64 / p.group;
-  p.lds = (size_t)ng * zoom_group_lds(n_tr) + 16;
+  p.lds = (size_t)ng * zoom_group_lds() + 16;
   const int per_cu = std::max(1, std::min(16, (int)((160 * 1024) / p.lds)));
   const int64_t waves_needed = ((int64_t)n_vox + ng - 1) / ng;
   p.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(waves_needed, (int64_t)n_cu * per_cu));
@@ -981,7 +983,6 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   const ZoomPlan plan = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid));
   MRF_CHECK_ARG(workspace != nullptr && ws_bytes >= plan.total,
                 "workspace too small (%zu < %zu bytes)", ws_bytes, plan.total);
-  MRF_CHECK_ARG(plan.lds <= 64 * 1024, "n_tr %d too long for the ZOOM kernel", n_tr);
   hipStream_t st = (hipStream_t)stream;
   const Tables* t = nullptr;
   rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, st, &t);
@@ -1024,19 +1025,11 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   const size_t lds = plan.lds;
   hipLaunchKernelGGL(k_zoom_init, dim3(1), dim3(64), 0, st, a.counter, *sched, dsch);
   MRF_HIP(hipGetLastError());
-  static bool attr = false;
-  if (!attr) {
-    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom<16>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
-    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom<32>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
-    MRF_HIP(hipFuncSetAttribute((const void*)k_zoom<64>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
-    attr = true;
-  }
   auto launch = [&]() {
     ProfScope prof(ctx, "k_zoom", st);
-    if (plan.group == 16)
+    if (plan.group == 8)
+      hipLaunchKernelGGL(k_zoom<8>, dim3(blocks), dim3(64), lds, st, a);
+    else if (plan.group == 16)
       hipLaunchKernelGGL(k_zoom<16>, dim3(blocks), dim3(64), lds, st, a);
     else if (plan.group == 32)
       hipLaunchKernelGGL(k_zoom<32>, dim3(blocks), dim3(64), lds, st, a);
