@@ -35,7 +35,7 @@ class Seq(C.Structure):
     _fields_ = [("n", C.c_int32), ("fa_deg", C.POINTER(C.c_double)),
                 ("phase_deg", C.POINTER(C.c_double)), ("tr_ms", C.POINTER(C.c_double)),
                 ("te_ms", C.POINTER(C.c_double)), ("inversion", C.c_int32),
-                ("ti_ms", C.c_double)]
+                ("ti_ms", C.c_double), ("smooth", C.c_int32)]
 
 
 class GridS(C.Structure):
@@ -77,6 +77,7 @@ def lib():
         L.orc_simulate_grid.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32,
                                         C.c_int64, C.c_int64, dp, dp, dp, C.c_int32]
         L.orc_cc.argtypes = [C.c_int32, dp, dp, dp, dp]
+        L.orc_smooth.argtypes = [C.c_int32, C.c_int32, dp, dp]
         L.orc_cc.restype = C.c_double
         L.orc_bruteforce.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
                                      C.c_int32, C.c_int32, lp, dp, dp, dp, dp, lp, dp,
@@ -109,7 +110,7 @@ def make_seq(seq) -> tuple:
     k.tr = np.ascontiguousarray(seq.tr_ms, np.float64)
     k.te = np.ascontiguousarray(seq.te_ms, np.float64)
     s = Seq(len(k.fa), _dp(k.fa), _dp(k.ph), _dp(k.tr), _dp(k.te), int(seq.inversion),
-            float(seq.ti_ms))
+            float(seq.ti_ms), int(getattr(seq, "smooth", 0)))
     return s, k
 
 
@@ -165,6 +166,24 @@ def simulate_grid(seq, grid, k0=0, count=None, n_tr=None, threads=0):
     if rc:
         raise ValueError(f"orc_simulate_grid failed ({rc})")
     return re + 1j * im, nrm
+
+
+def smooth(x, taps: int) -> np.ndarray:
+    """Temporal smoothing of complex signals along the last axis (Methods,
+    Experiment 4): binomial 3- or 5-point weights, renormalised at the ends;
+    taps 0 or 1 return a copy."""
+    x = np.asarray(x, np.complex128)
+    flat = x.reshape(-1, x.shape[-1]) if x.ndim else x.reshape(1, 1)
+    out = np.empty_like(flat)
+    n = flat.shape[-1]
+    for r in range(flat.shape[0]):
+        re = np.ascontiguousarray(flat[r].real)
+        im = np.ascontiguousarray(flat[r].imag)
+        rc = lib().orc_smooth(n, int(taps), _dp(re), _dp(im))
+        if rc != 0:
+            raise ValueError(f"orc_smooth failed ({rc}): taps must be 0, 1, 3 or 5")
+        out[r] = re + 1j * im
+    return out.reshape(x.shape)
 
 
 def cc(v, d) -> float:

@@ -160,6 +160,7 @@ typedef struct {
   double* dftab;  /* [n3][4][n_tr] */
   double* rftab;  /* [n4][n_tr][4] */
   int32_t inversion;
+  int32_t smooth;  /* temporal smoothing of dictionary entries: 0, 3 or 5 taps */
 } tables;
 
 static void tables_free(tables* t) {
@@ -172,9 +173,11 @@ static int tables_build(const orc_seq* seq, const orc_grid* g, int32_t n_tr,
   memset(t, 0, sizeof *t);
   if (!seq_ok(seq, n_tr) || !g || g->n1 < 1 || g->n2 < 1 || g->n3 < 1 || g->n4 < 0)
     return 1;
+  if (!(seq->smooth == 0 || seq->smooth == 1 || seq->smooth == 3 || seq->smooth == 5)) return 1;
   t->n_tr = n_tr; t->n1 = g->n1; t->n2 = g->n2; t->n3 = g->n3;
   t->n4 = g->n4 > 0 ? g->n4 : 1;
   t->inversion = seq->inversion;
+  t->smooth = seq->smooth > 1 ? seq->smooth : 0;
   size_t n = (size_t)n_tr;
   t->t1tab = (double*)malloc(sizeof(double) * (size_t)t->n1 * 2 * n + 8);
   t->t1ti = (double*)malloc(sizeof(double) * (size_t)t->n1);
@@ -213,6 +216,53 @@ static int tables_build(const orc_seq* seq, const orc_grid* g, int32_t n_tr,
                  t->rftab + ((size_t)i * n + j) * 4);
   }
   return 0;
+}
+
+/* Temporal smoothing (Methods, Experiment 4; Results, Fig. 7B): a moving
+ * Gaussian of 3 or 5 points applied along the readouts, here the binomial
+ * weights (1, 2, 1) / 4 and (1, 4, 6, 4, 1) / 16; at the first and last
+ * readouts the points that exist are used and their weights renormalised.
+ * In place; taps 0 or 1 leave the signal unchanged. */
+int orc_smooth(int32_t n, int32_t taps, double* re, double* im) {
+  static const double w3[3] = {1.0, 2.0, 1.0};
+  static const double w5[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
+  if (taps == 0 || taps == 1) return 0;
+  if (!(taps == 3 || taps == 5) || n < 0) return 1;
+  const double* w = taps == 3 ? w3 : w5;
+  const int32_t h = taps / 2;
+  double* xr = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  double* xi = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  if (!xr || !xi) {
+    free(xr);
+    free(xi);
+    return 2;
+  }
+  for (int32_t j = 0; j < n; ++j) {
+    xr[j] = re[j];
+    xi[j] = im[j];
+  }
+  for (int32_t j = 0; j < n; ++j) {
+    double sr = 0.0, si = 0.0, sw = 0.0;
+    for (int32_t k = -h; k <= h; ++k) {
+      const int32_t q = j + k;
+      if (q < 0 || q >= n) continue;
+      sr += w[k + h] * xr[q];
+      si += w[k + h] * xi[q];
+      sw += w[k + h];
+    }
+    re[j] = sr / sw;
+    im[j] = si / sw;
+  }
+  free(xr);
+  free(xi);
+  return 0;
+}
+
+/* The samples of dictionary entry f: the recursion, then the sequence's
+ * temporal smoothing (if any). */
+static void entry_samples(const tables* t, const entry_factors* f, double* re, double* im) {
+  run_entry(t->n_tr, t->inversion, f, re, im, NULL);
+  if (t->smooth) orc_smooth(t->n_tr, t->smooth, re, im);
 }
 
 static void tables_view(const tables* t, int64_t k, entry_factors* f) {
@@ -259,7 +309,7 @@ int orc_simulate_grid(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
     tables_view(&t, k0 + e, &f);
     double* r = re + (size_t)e * n_tr;
     double* i = im + (size_t)e * n_tr;
-    run_entry(n_tr, t.inversion, &f, r, i, NULL);
+    entry_samples(&t, &f, r, i);
     if (norm) norm[e] = sqrt(norm2(n_tr, r, i));
   }
   tables_free(&t);
@@ -350,7 +400,7 @@ int orc_bruteforce(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
     for (int64_t k = 0; k < E; ++k) {
       entry_factors f;
       tables_view(&t, k, &f);
-      run_entry(n_tr, t.inversion, &f, re, im, NULL);
+      entry_samples(&t, &f, re, im);
       double nd = sqrt(norm2(n_tr, re, im));
       for (int32_t v = 0; v < n_vox; ++v) {
         double c = 0.0;
@@ -389,7 +439,7 @@ int orc_bruteforce(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
       /* proton density from the scale: <v, d> / ||d||^2 (Theory section) */
       entry_factors f;
       tables_view(&t, lk[0], &f);
-      run_entry(n_tr, t.inversion, &f, re, im, NULL);
+      entry_samples(&t, &f, re, im);
       double n2d = norm2(n_tr, re, im), sr = 0.0, si = 0.0;
       cdot(n_tr, vr + (size_t)v * n_tr, vi + (size_t)v * n_tr, re, im, &sr, &si);
       if (pd_re) pd_re[v] = n2d > 0.0 ? sr / n2d : 0.0;
@@ -436,7 +486,7 @@ int orc_cc_map(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
     for (int64_t i = 0; i < count; ++i) {
       entry_factors f;
       tables_view(&t, k0 + i, &f);
-      run_entry(n_tr, t.inversion, &f, re, im, NULL);
+      entry_samples(&t, &f, re, im);
       double nd = sqrt(norm2(n_tr, re, im));
       for (int32_t v = 0; v < n_vox; ++v) {
         double c = 0.0;
@@ -993,7 +1043,7 @@ static double phys_objective(void* p, const int32_t* i) {
   int64_t k = (((int64_t)i[0] * c->dims[1] + i[1]) * c->dims[2] + i[2]) * c->dims[3] + i[3];
   entry_factors f;
   tables_view(c->t, k, &f);
-  run_entry(c->t->n_tr, c->t->inversion, &f, c->re, c->im, NULL);
+  entry_samples(c->t, &f, c->re, c->im);
   double nd = sqrt(norm2(c->t->n_tr, c->re, c->im));
   if (nd == 0.0 || c->vnorm == 0.0) return 0.0;
   double sr, si;

@@ -44,6 +44,7 @@ class Sequence:
     te_ms: np.ndarray
     inversion: int = 1
     ti_ms: float = 0.0
+    smooth: int = 0  # dictionary entries smoothed over 3 or 5 readouts (0: none)
 
     @property
     def n(self) -> int:
@@ -52,7 +53,7 @@ class Sequence:
     def prefix(self, n: int) -> "Sequence":
         return Sequence(self.fa_deg[:n].copy(), self.phase_deg[:n].copy(),
                         self.tr_ms[:n].copy(), self.te_ms[:n].copy(),
-                        self.inversion, self.ti_ms)
+                        self.inversion, self.ti_ms, self.smooth)
 
 
 @dataclasses.dataclass
