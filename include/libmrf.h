@@ -76,6 +76,14 @@ typedef struct {
   const double* te_ms;
   int32_t inversion;
   double ti_ms;
+  /* Temporal smoothing of dictionary entries (Methods, Experiment 4): 0 or 1
+   * none, 3 or 5 readouts (binomial weights (1, 2, 1) / 4 and
+   * (1, 4, 6, 4, 1) / 16, renormalised over the readouts that exist at the
+   * first and last readouts). Every dictionary entry the library simulates
+   * for this sequence (dictionaries, CC maps, ZOOM candidates, BF16
+   * re-scoring) is smoothed; fingerprints from mrf_simulate_signals are not:
+   * smooth them with mrf_smooth_signals. Other values: MRF_ERR_INVALID. */
+  int32_t smooth;
 } mrf_sequence_desc;
 
 int mrf_sequence_create(mrf_context* ctx, const mrf_sequence_desc* desc, mrf_sequence** out);
@@ -142,6 +150,18 @@ int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq, const mrf
 int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid, int32_t n_tr,
                const void* vox, int32_t n_vox, int64_t ld_vox, int64_t entry_begin,
                int64_t entry_count, float* cc, int64_t ld_cc, void* stream);
+
+/* Temporal smoothing of complex64 signals along their readouts (Methods,
+ * Experiment 4: the fingerprints are smoothed like the dictionary). Row i of
+ * n_sig: in[i*ld_in + j] -> out[i*ld_out + j], j < n_tr, device memory,
+ * caller-owned. taps 3 or 5: the weights of mrf_sequence_desc.smooth, with
+ * the same end renormalisation; taps 0 or 1: a copy. in == out with
+ * ld_in == ld_out smooths in place; otherwise the two must not overlap.
+ * Returns without waiting (profile name "k_smooth_signals").
+ * Errors: other taps, ld < n_tr, NULL or misaligned (8 B) pointers with work
+ * to do, partially overlapping rows -> MRF_ERR_INVALID (nothing launched). */
+int mrf_smooth_signals(mrf_context* ctx, const void* in, int64_t ld_in, void* out, int64_t ld_out,
+                       int64_t n_sig, int32_t n_tr, int32_t taps, void* stream);
 
 /* Simulate fingerprints at arbitrary (not necessarily on-grid) parameter
  * values: params is a device FP64 array [count][4] = (T1 ms, T2 ms, df Hz,
@@ -393,7 +413,9 @@ typedef struct {
 int mrf_server_create(mrf_context* ctx, const mrf_server_config* cfg, mrf_server** out);
 /* n_tr: n_lengths readout counts (each <= the sequence length; multiples of
  * 4 for BF16). Blocks until the dictionary is built. MRF_ERR_REJECTED if the
- * dictionary does not fit in the budget. */
+ * dictionary does not fit in the budget. A sequence with temporal smoothing
+ * is MRF_ERR_INVALID (shorter readout counts are served from prefixes of one
+ * dictionary, and a smoothed entry's prefix is not the smoothed prefix). */
 int mrf_server_register(mrf_server* srv, const mrf_sequence* seq, const mrf_grid* grid,
                         mrf_dtype dtype, const int32_t* n_tr, int32_t n_lengths, int32_t* slot);
 int mrf_serve_submit(mrf_server* srv, const mrf_request* req, uint64_t* ticket);

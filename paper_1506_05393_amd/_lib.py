@@ -28,7 +28,7 @@ class SequenceDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("fa_deg", C.POINTER(C.c_double)),
                 ("phase_deg", C.POINTER(C.c_double)), ("tr_ms", C.POINTER(C.c_double)),
                 ("te_ms", C.POINTER(C.c_double)), ("inversion", C.c_int32),
-                ("ti_ms", C.c_double)]
+                ("ti_ms", C.c_double), ("smooth", C.c_int32)]
 
 
 class Axis(C.Structure):
@@ -68,6 +68,9 @@ _SIGS = [
     ("mrf_cc_map", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_void_p, C.c_int32, C.c_int64,
       C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    ("mrf_smooth_signals", C.c_int,
+     [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+      C.c_void_p]),
     ("mrf_simulate_signals", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
       C.c_void_p]),

@@ -43,6 +43,8 @@ struct Tables {
   // each pulse is a rotation about the x axis (pulse_matrix then gives exact
   // zeros off that axis and R00 = 1)
   int32_t x_axis_pulses = 0;
+  // dictionary entries smoothed over 3 or 5 readouts (0: none), from the sequence
+  int32_t smooth = 0;
   float2* t1 = nullptr;   // [n_tr][n1]  (1-E1 over TE, 1-E1 over TR-TE)
   float* t1ti = nullptr;  // [n1]        (1-E1 over TI)
   float2* t2 = nullptr;   // [n_tr][n2]  (1-E2 over TE, 1-E2 over TR-TE)
@@ -93,6 +95,7 @@ struct mrf_sequence {
   std::vector<double> fa, ph, tr, te;
   int32_t inversion = 1;
   double ti = 0.0;
+  int32_t smooth = 0;     // temporal smoothing of dictionary entries: 0, 3 or 5 readouts
   double omega_hz = 0.0;  // 1000 / min TR: CC pseudo-period in df (Property II)
   double* dev = nullptr;  // device FP64 [4][n]: TE, TR-TE, flip angle, RF phase
   std::mutex mu;

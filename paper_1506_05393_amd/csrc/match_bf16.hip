@@ -17,6 +17,7 @@
 #include "internal.h"
 #include "match_common.h"
 #include "match_kernels.h"
+#include "smooth.h"
 
 namespace mrf {
 
@@ -319,8 +320,10 @@ __global__ __launch_bounds__(64) void k_pack_bf16(const float2* __restrict__ vox
 
 // K5: re-simulate each voxel's BF16 candidates in FP32 (same step function
 // and tables as the dictionary) and re-score them exactly; one lane per
-// (voxel, candidate), 8 lanes per voxel.
+// (voxel, candidate), 8 lanes per voxel. SM: the candidates are smoothed as
+// the dictionary is (the same delay line, weights and order of operations).
 struct RescoreArgs {
+  SmoothW sm;
   const float2* t1T;
   const float* t1ti;
   const float2* t2T;
@@ -351,6 +354,7 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
   s = t;
 }
 
+template <bool SM>
 __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
   const int lane = threadIdx.x;
   const int v = blockIdx.x * 8 + (lane >> 3);
@@ -380,19 +384,45 @@ __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
     const float* R = a.rf + (int64_t)i4 * n * 9;
     const float2* x = a.vox + (int64_t)v * a.ld_vox;
     Spin m = initial_spin(a.inversion, a.t1ti[i1]);
+    // output sample o (= j, or j - 2 behind the smoothing delay line)
+    auto acc = [&](int32_t o, float dx, float dy) {
+      const float2 s = x[o];
+      // v conj(d)
+      two_sum_acc(sr, cr, fmaf(s.x, dx, s.y * dy));
+      two_sum_acc(si, ci, fmaf(s.y, dx, -(s.x * dy)));
+      n2 = fma((double)dx, (double)dx, n2);
+      n2 = fma((double)dy, (double)dy, n2);
+    };
+    float hx[kSmoothLen], hy[kSmoothLen];
+#pragma unroll
+    for (int k = 0; k < kSmoothLen; ++k) hx[k] = hy[k] = 0.f;
     for (int32_t j = 0; j < n; ++j) {
       const float2 r1 = p1[j];
       const float2 r2 = p2[j];
       const float4 pc = pd[j];
       rf_pulse(m, R + 9 * j);
       free_evolve(m, pc.x, pc.y, r2.x, r1.x);
-      const float2 s = x[j];
-      // v conj(d)
-      two_sum_acc(sr, cr, fmaf(s.x, m.x, s.y * m.y));
-      two_sum_acc(si, ci, fmaf(s.y, m.x, -(s.x * m.y)));
-      n2 = fma((double)m.x, (double)m.x, n2);
-      n2 = fma((double)m.y, (double)m.y, n2);
+      if (SM) {
+        const int32_t o = j - kSmoothLag;
+        const float sc = o >= 2 ? a.sm.full : (o == 1 ? a.sm.head[1] : a.sm.head[0]);
+        float dx, dy;
+        smooth_push(hx, hy, m.x, m.y);
+        smooth_out(a.sm, hx, hy, sc, dx, dy);
+        if (o >= 0) acc(o, dx, dy);
+      } else {
+        acc(j, m.x, m.y);
+      }
       free_evolve(m, pc.z, pc.w, r2.y, r1.y);
+    }
+    if (SM) {
+#pragma unroll
+      for (int t = 0; t < kSmoothLag; ++t) {
+        const int32_t o = n - kSmoothLag + t;
+        float dx, dy;
+        smooth_push(hx, hy, 0.f, 0.f);
+        smooth_out(a.sm, hx, hy, a.sm.tail[t], dx, dy);
+        if (o >= 0) acc(o, dx, dy);
+      }
     }
   }
   const double dr = (double)sr + (double)cr, di = (double)si + (double)ci;
@@ -580,9 +610,13 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   r.pd_im = out.pd_im;
   r.topk_idx = topk_idx;
   r.topk_cc = topk_cc;
+  r.sm = smooth_weights(t->smooth ? t->smooth : 3, d->n_tr);
   {
     ProfScope prof(ctx, "k_rescore", st);
-    hipLaunchKernelGGL(k_rescore, dim3((n_vox + 7) / 8), dim3(64), 0, st, r);
+    if (t->smooth)
+      hipLaunchKernelGGL(k_rescore<true>, dim3((n_vox + 7) / 8), dim3(64), 0, st, r);
+    else
+      hipLaunchKernelGGL(k_rescore<false>, dim3((n_vox + 7) / 8), dim3(64), 0, st, r);
   }
   MRF_HIP(hipGetLastError());
   return MRF_OK;

@@ -194,6 +194,7 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   t.n3 = g->df_hz.n;
   t.n4 = g->b1.n > 0 ? g->b1.n : 1;
   t.inversion = seq->inversion;
+  t.smooth = seq->smooth;
   t.x_axis_pulses = 1;
   for (int32_t j = 0; j < n_tr; ++j)
     if (std::fmod(seq->ph[j], 180.0) != 0.0) t.x_axis_pulses = 0;
@@ -398,6 +399,8 @@ int mrf_sequence_create(mrf_context* ctx, const mrf_sequence_desc* d, mrf_sequen
   MRF_CHECK_ARG(d->n >= 1, "sequence length %d must be >= 1", d->n);
   MRF_CHECK_ARG(d->fa_deg && d->phase_deg && d->tr_ms && d->te_ms, "sequence arrays must not be NULL");
   MRF_CHECK_ARG(d->ti_ms >= 0.0 && std::isfinite(d->ti_ms), "ti_ms must be finite and >= 0");
+  MRF_CHECK_ARG(d->smooth == 0 || d->smooth == 1 || d->smooth == 3 || d->smooth == 5,
+                "smooth must be 0, 1, 3 or 5 (got %d)", d->smooth);
   double trmin = INFINITY;
   for (int32_t j = 0; j < d->n; ++j) {
     MRF_CHECK_ARG(std::isfinite(d->fa_deg[j]) && std::isfinite(d->phase_deg[j]),
@@ -419,6 +422,7 @@ int mrf_sequence_create(mrf_context* ctx, const mrf_sequence_desc* d, mrf_sequen
   s->te.assign(d->te_ms, d->te_ms + d->n);
   s->inversion = d->inversion ? 1 : 0;
   s->ti = d->ti_ms;
+  s->smooth = d->smooth > 1 ? d->smooth : 0;
   s->omega_hz = 1000.0 / trmin;
   {
     std::vector<double> h(4 * (size_t)d->n);

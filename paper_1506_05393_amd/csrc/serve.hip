@@ -527,6 +527,10 @@ extern "C" int mrf_server_register(mrf_server* srv, const mrf_sequence* seq, con
                                    int32_t* slot) {
   MRF_CHECK_ARG(srv && slot && n_tr && n_lengths >= 1, "server, n_tr, slot must be given");
   MRF_CHECK_ARG(srv->fake || seq, "sequence must not be NULL");
+  // a slot serves shorter readout counts from prefixes of one resident
+  // dictionary; a smoothed entry's prefix is not the smoothed prefix
+  MRF_CHECK_ARG(!seq || seq->smooth == 0,
+                "sequences with temporal smoothing cannot be served (prefix dictionaries)");
   MRF_CHECK_ARG(dtype == MRF_F32 || dtype == MRF_BF16, "unknown dtype %d", (int)dtype);
   int rc = check_grid(grid);
   if (rc) return rc;

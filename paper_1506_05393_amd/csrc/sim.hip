@@ -24,6 +24,7 @@
 #include "bloch.h"
 #include "internal.h"
 #include "sim_kernels.h"
+#include "smooth.h"
 
 namespace mrf {
 
@@ -118,6 +119,7 @@ struct SimArgs {
   uint4* packed;    // BF16 blocks
   double* norm;
   float* cc;        // CC map output (MODE 3)
+  SmoothW sm;       // temporal smoothing weights (SM kernels)
 };
 
 struct EntryState {
@@ -138,7 +140,10 @@ struct Dots {
 // also accumulates the norm of the stored (scaled, rounded) values into nb,
 // MODE 3 stores nothing and accumulates v conj(d) against the fingerprint
 // `vox` (one value per readout, the same for every thread) into dt.
-template <int MODE, int PK, bool DF_LDS, bool SCALED>
+// SM: the entry is smoothed over the readouts (a five-sample delay line per
+// entry; output o = j - 2 leaves the line while raw sample j enters it, and
+// two zero pushes after the last readout give the last two outputs).
+template <int MODE, int PK, bool DF_LDS, bool SCALED, bool SM>
 __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
                                          const float* __restrict__ rftab, rsrc_t r1s, rsrc_t r2s,
                                          rsrc_t rds, float4* sdf, int64_t blk0, int32_t nrec,
@@ -149,14 +154,66 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
   const int32_t n_tr = a.n_tr, n3 = a.n3;
   const int32_t per = kChunk * n3;  // staged float4 per chunk
   Spin m[kQ];
+  float hx[kQ][kSmoothLen], hy[kQ][kSmoothLen];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     m[q] = initial_spin(a.inversion, st.r1ti[q]);
     n2[q] = 0.0;
     nb[q] = 0.0;
     dt.re[q] = dt.im[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSmoothLen; ++k) hx[q][k] = hy[q][k] = 0.f;
   }
   dt.vn2 = 0.0;
+  // FP32 partial sums over (up to) four outputs, added into FP64
+  float part[kQ], partb[kQ], pre[kQ], pim[kQ], pv = 0.f;
+  uint32_t w[kQ][4];  // one BF16 block of four outputs
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) part[q] = partb[q] = pre[q] = pim[q] = 0.f;
+  auto flush = [&]() {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      n2[q] += (double)part[q];
+      nb[q] += (double)partb[q];
+      part[q] = partb[q] = 0.f;
+      if (MODE == 3) {
+        dt.re[q] += (double)pre[q];
+        dt.im[q] += (double)pim[q];
+        pre[q] = pim[q] = 0.f;
+      }
+    }
+    if (MODE == 3) {
+      dt.vn2 += (double)pv;
+      pv = 0.f;
+    }
+  };
+  // output sample o of entry q (ol = o & 3, a compile-time constant at every
+  // call): norm, store or fingerprint product
+  auto emit = [&](int q, int ol, int32_t o, float sx, float sy, float2 vo) {
+    part[q] = fmaf(sx, sx, part[q]);
+    part[q] = fmaf(sy, sy, part[q]);
+    const float ox = SCALED ? sx * scale[q] : sx;
+    const float oy = SCALED ? sy * scale[q] : sy;
+    if (MODE == 1) {
+      const rsrc_t wr = make_rsrc(a.re + (int64_t)o * a.ld + blk0, nrec);
+      const rsrc_t wi = make_rsrc(a.im + (int64_t)o * a.ld + blk0, nrec);
+      store1(ox, wr, 4u * (tid + kThreads * q));
+      store1(oy, wi, 4u * (tid + kThreads * q));
+    } else if (MODE == 2) {
+      const uint32_t v = pack_bf16x2(ox, oy);
+      w[q][ol] = v;
+      // |stored value|^2: BF16 products are exact in FP32 (v_dot2_f32_bf16)
+      const bf16x2_t b = __builtin_bit_cast(bf16x2_t, v);
+      partb[q] = __builtin_amdgcn_fdot2_f32_bf16(b, b, partb[q], false);
+      if (ol == 3) {
+        const rsrc_t wr = make_rsrc(a.packed + (int64_t)(o >> 2) * a.ld + blk0, nrec);
+        store4(w[q], wr, 16u * (tid + kThreads * q));
+      }
+    } else if (MODE == 3) {
+      pre[q] = fmaf(vo.x, ox, fmaf(vo.y, oy, pre[q]));
+      pim[q] = fmaf(vo.y, ox, fmaf(-vo.x, oy, pim[q]));
+    }
+  };
   float4 pf[kPrefetch];
   if (DF_LDS) {
 #pragma unroll
@@ -179,22 +236,21 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       for (int p = 0; p < kPrefetch; ++p)
         pf[p] = load4(rds, row + 16u * (tid + kThreads * p), 0);
     }
-    float part[kQ], partb[kQ], pre[kQ], pim[kQ], pv = 0.f;
-    uint32_t w[kQ][4];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) part[q] = partb[q] = pre[q] = pim[q] = 0.f;
 #pragma unroll
     for (int jj = 0; jj < kChunk; ++jj) {
       const int32_t j = j0 + jj;
       if (j < n_tr) {
-        const rsrc_t wr = make_rsrc(MODE == 2 ? (const void*)(a.packed + (int64_t)(j >> 2) * a.ld + blk0)
-                                              : (const void*)(a.re + (int64_t)j * a.ld + blk0),
-                                    nrec);
-        const rsrc_t wi = make_rsrc(a.im + (int64_t)j * a.ld + blk0, nrec);
-        float2 vj = make_float2(0.f, 0.f);
-        if (MODE == 3) {
-          vj = vox[j];
-          pv = fmaf(vj.x, vj.x, fmaf(vj.y, vj.y, pv));
+        // the output of this readout (j0 is a multiple of 4, so o & 3 is
+        // known at compile time)
+        const int32_t o = SM ? j - kSmoothLag : j;
+        const int ol = SM ? ((jj - kSmoothLag) & 3) : (jj & 3);
+        const bool out = !SM || o >= 0;
+        float sc = 1.f;
+        if (SM) sc = o >= 2 ? a.sm.full : (o == 1 ? a.sm.head[1] : a.sm.head[0]);
+        float2 vo = make_float2(0.f, 0.f);
+        if (MODE == 3 && out) {
+          vo = vox[o];
+          pv = fmaf(vo.x, vo.x, fmaf(vo.y, vo.y, pv));
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
@@ -207,44 +263,16 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
           else
             pulse<PK>(m[q], st.rq[q] + 9 * j);
           free_evolve(m[q], pc.x, pc.y, r2.x, r1.x);
-          part[q] = fmaf(m[q].x, m[q].x, part[q]);
-          part[q] = fmaf(m[q].y, m[q].y, part[q]);
-          const float ox = SCALED ? m[q].x * scale[q] : m[q].x;
-          const float oy = SCALED ? m[q].y * scale[q] : m[q].y;
-          if (MODE == 1) {
-            store1(ox, wr, 4u * (tid + kThreads * q));
-            store1(oy, wi, 4u * (tid + kThreads * q));
-          } else if (MODE == 2) {
-            const uint32_t v = pack_bf16x2(ox, oy);
-            w[q][jj & 3] = v;
-            // |stored value|^2: BF16 products are exact in FP32 (v_dot2_f32_bf16)
-            const bf16x2_t b = __builtin_bit_cast(bf16x2_t, v);
-            partb[q] = __builtin_amdgcn_fdot2_f32_bf16(b, b, partb[q], false);
-            if ((jj & 3) == 3) store4(w[q], wr, 16u * (tid + kThreads * q));
-          } else if (MODE == 3) {
-            pre[q] = fmaf(vj.x, ox, fmaf(vj.y, oy, pre[q]));
-            pim[q] = fmaf(vj.y, ox, fmaf(-vj.x, oy, pim[q]));
+          float sx = m[q].x, sy = m[q].y;
+          if (SM) {
+            smooth_push(hx[q], hy[q], sx, sy);
+            smooth_out(a.sm, hx[q], hy[q], sc, sx, sy);
           }
+          if (out) emit(q, ol, o, sx, sy, vo);
           free_evolve(m[q], pc.z, pc.w, r2.y, r1.y);
         }
       }
-      if ((jj & 3) == 3) {
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-          n2[q] += (double)part[q];
-          nb[q] += (double)partb[q];
-          part[q] = partb[q] = 0.f;
-          if (MODE == 3) {
-            dt.re[q] += (double)pre[q];
-            dt.im[q] += (double)pim[q];
-            pre[q] = pim[q] = 0.f;
-          }
-        }
-        if (MODE == 3) {
-          dt.vn2 += (double)pv;
-          pv = 0.f;
-        }
-      }
+      if ((jj & 3) == 3) flush();
     }
     if (DF_LDS) {
       if (c + 1 < nch) {
@@ -256,9 +284,30 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       lds_barrier();
     }
   }
+  if (SM) {
+    // the last two outputs (BF16 entries have n_tr % 4 == 0: they fill
+    // positions 2 and 3 of the last block)
+#pragma unroll
+    for (int t = 0; t < kSmoothLag; ++t) {
+      const int32_t o = n_tr - kSmoothLag + t;
+      float2 vo = make_float2(0.f, 0.f);
+      if (MODE == 3 && o >= 0) {
+        vo = vox[o];
+        pv = fmaf(vo.x, vo.x, fmaf(vo.y, vo.y, pv));
+      }
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        float sx, sy;
+        smooth_push(hx[q], hy[q], 0.f, 0.f);
+        smooth_out(a.sm, hx[q], hy[q], a.sm.tail[t], sx, sy);
+        if (o >= 0) emit(q, 2 + t, o, sx, sy, vo);
+      }
+    }
+    flush();
+  }
 }
 
-template <int MODE, int PK, bool DF_LDS>
+template <int MODE, int PK, bool DF_LDS, bool SM>
 __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* __restrict__ t1tab,
                                                        const float2* __restrict__ t2tab,
                                                        const float4* __restrict__ dftab,
@@ -294,17 +343,17 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
     // two passes: the norm first, then the entries divided by it
 #pragma unroll
     for (int q = 0; q < kQ; ++q) scale[q] = 1.0f;
-    sim_pass<0, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb,
+    sim_pass<0, PK, DF_LDS, false, SM>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb,
                                    vox, dt);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) scale[q] = n2[q] > 0.0 ? (float)(1.0 / sqrt(n2[q])) : 0.0f;
     double n2b[kQ];
-    sim_pass<MODE, PK, DF_LDS, true>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2b, nb,
+    sim_pass<MODE, PK, DF_LDS, true, SM>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2b, nb,
                                      vox, dt);
   } else {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) scale[q] = 1.0f;
-    sim_pass<MODE, PK, DF_LDS, false>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb,
+    sim_pass<MODE, PK, DF_LDS, false, SM>(a, st, rftab, r1s, r2s, rds, sdf, blk0, nrec, scale, n2, nb,
                                       vox, dt);
   }
   if (MODE == 3) {
@@ -326,23 +375,33 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
   }
 }
 
-template <int MODE, int PK>
-static void launch_sim_variant(const SimArgs& a, const Tables& t, bool df_lds, int64_t blocks,
-                               hipStream_t stream, const float2* vox) {
+template <int MODE, int PK, bool SM>
+static void launch_sim_smooth(const SimArgs& a, const Tables& t, bool df_lds, int64_t blocks,
+                              hipStream_t stream, const float2* vox) {
   const dim3 g((unsigned)blocks), b(kThreads);
   const size_t lds = df_lds ? 2 * sizeof(float4) * kChunk * (size_t)a.n3 : 0;
   if (df_lds)
-    hipLaunchKernelGGL((k_sim_dict<MODE, PK, true>), g, b, lds, stream, a, t.t1, t.t2, t.df, t.rf,
-                       t.t1ti, vox);
+    hipLaunchKernelGGL((k_sim_dict<MODE, PK, true, SM>), g, b, lds, stream, a, t.t1, t.t2, t.df,
+                       t.rf, t.t1ti, vox);
   else
-    hipLaunchKernelGGL((k_sim_dict<MODE, PK, false>), g, b, 0, stream, a, t.t1, t.t2, t.df, t.rf,
-                       t.t1ti, vox);
+    hipLaunchKernelGGL((k_sim_dict<MODE, PK, false, SM>), g, b, 0, stream, a, t.t1, t.t2, t.df,
+                       t.rf, t.t1ti, vox);
+}
+
+template <int MODE, int PK>
+static void launch_sim_variant(const SimArgs& a, const Tables& t, bool df_lds, int64_t blocks,
+                               hipStream_t stream, const float2* vox) {
+  if (t.smooth)
+    launch_sim_smooth<MODE, PK, true>(a, t, df_lds, blocks, stream, vox);
+  else
+    launch_sim_smooth<MODE, PK, false>(a, t, df_lds, blocks, stream, vox);
 }
 
 template <int MODE>
-static void launch_sim_mode(const SimArgs& a, const Tables& t, int64_t blocks, hipStream_t stream,
+static void launch_sim_mode(SimArgs a, const Tables& t, int64_t blocks, hipStream_t stream,
                             const float2* vox = nullptr) {
   const bool df_lds = a.n3 <= kLdsMaxN3;
+  if (t.smooth) a.sm = smooth_weights(t.smooth, a.n_tr);
   const bool lane = a.n4 > 1;
   if (!lane && t.x_axis_pulses)
     launch_sim_variant<MODE, kXAxisUniform>(a, t, df_lds, blocks, stream, vox);
@@ -386,6 +445,57 @@ __global__ __launch_bounds__(256) void k_sim_signals(SigArgs a) {
     free_evolve(m, cma, sa, (float)one_minus_exp(ta[j], T2), (float)one_minus_exp(ta[j], T1));
     a.out[i * a.ld + j] = make_float2(m.x, m.y);
     free_evolve(m, cmb, sb, (float)one_minus_exp(tb[j], T2), (float)one_minus_exp(tb[j], T1));
+  }
+}
+
+// Temporal smoothing of complex64 signals (fingerprints, Experiment 4): one
+// wave per signal walks its readouts 64 at a time, holding the previous,
+// current and next 64 raw values in registers and taking the window from
+// neighbouring lanes; every load of a chunk precedes the stores that
+// overwrite it, so in == out (same row stride) is safe. Same weights, order
+// of operations and end scales as the dictionary's delay line.
+struct SmoothArgs {
+  const float2* in;
+  float2* out;
+  int64_t ld_in, ld_out, n_sig;
+  int32_t n_tr;
+  SmoothW sm;
+};
+
+__global__ __launch_bounds__(256) void k_smooth_signals(SmoothArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.n_sig) return;  // the whole wave (row is uniform over it)
+  const float2* x = a.in + row * a.ld_in;
+  float2* y = a.out + row * a.ld_out;
+  const int32_t n = a.n_tr;
+  float2 prev = make_float2(0.f, 0.f);
+  float2 cur = lane < n ? x[lane] : make_float2(0.f, 0.f);
+  for (int32_t j0 = 0; j0 < n; j0 += 64) {
+    const int32_t jn = j0 + 64 + lane;
+    const float2 nxt = jn < n ? x[jn] : make_float2(0.f, 0.f);
+    float hx[kSmoothLen], hy[kSmoothLen];
+#pragma unroll
+    for (int k = 0; k < kSmoothLen; ++k) {
+      const int l = lane + k - kSmoothLag;  // lane of raw sample j + k - 2 in its chunk
+      const int src = l & 63;
+      const float px = __shfl(prev.x, src), py = __shfl(prev.y, src);
+      const float cx = __shfl(cur.x, src), cy = __shfl(cur.y, src);
+      const float nx = __shfl(nxt.x, src), ny = __shfl(nxt.y, src);
+      hx[k] = l < 0 ? px : (l >= 64 ? nx : cx);
+      hy[k] = l < 0 ? py : (l >= 64 ? ny : cy);
+    }
+    const int32_t j = j0 + lane;
+    const float sc = j == n - 1   ? a.sm.tail[1]
+                     : j == n - 2 ? a.sm.tail[0]
+                     : j == 0     ? a.sm.head[0]
+                     : j == 1     ? a.sm.head[1]
+                                  : a.sm.full;
+    float ox, oy;
+    smooth_out(a.sm, hx, hy, sc, ox, oy);
+    if (j < n) y[j] = make_float2(ox, oy);
+    prev = cur;
+    cur = nxt;
   }
 }
 
@@ -520,6 +630,46 @@ extern "C" int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_g
                        cc + (int64_t)v * ld_cc, (hipStream_t)stream);
     if (rc) return rc;
   }
+  return MRF_OK;
+}
+
+extern "C" int mrf_smooth_signals(mrf_context* ctx, const void* in, int64_t ld_in, void* out,
+                                  int64_t ld_out, int64_t n_sig, int32_t n_tr, int32_t taps,
+                                  void* stream) {
+  MRF_CHECK_ARG(ctx, "context must not be NULL");
+  MRF_CHECK_ARG(taps == 0 || taps == 1 || taps == 3 || taps == 5,
+                "taps must be 0, 1, 3 or 5 (got %d)", taps);
+  MRF_CHECK_ARG(n_sig >= 0 && n_tr >= 0, "n_sig and n_tr must be >= 0");
+  MRF_CHECK_ARG(ld_in >= n_tr && ld_out >= n_tr, "row strides must be >= n_tr");
+  if (n_sig == 0 || n_tr == 0) return MRF_OK;
+  MRF_CHECK_ARG(in && out, "in and out must not be NULL");
+  MRF_CHECK_ARG(((uintptr_t)in & 7) == 0 && ((uintptr_t)out & 7) == 0,
+                "signals must be 8-byte aligned (complex64)");
+  const uintptr_t ib = (uintptr_t)in, ob = (uintptr_t)out;
+  const uintptr_t ie = ib + 8 * (uintptr_t)((n_sig - 1) * ld_in + n_tr);
+  const uintptr_t oe = ob + 8 * (uintptr_t)((n_sig - 1) * ld_out + n_tr);
+  MRF_CHECK_ARG((ib == ob && ld_in == ld_out) || ie <= ob || oe <= ib,
+                "in and out must be the same rows or not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if (taps <= 1) {
+    if (ib != ob)
+      MRF_HIP(hipMemcpy2DAsync(out, 8 * (size_t)ld_out, in, 8 * (size_t)ld_in, 8 * (size_t)n_tr,
+                               (size_t)n_sig, hipMemcpyDeviceToDevice, s));
+    return MRF_OK;
+  }
+  const int64_t blocks = (n_sig + 3) / 4;
+  MRF_CHECK_ARG(blocks <= INT32_MAX, "too many signals in one call");
+  SmoothArgs a;
+  a.in = (const float2*)in;
+  a.out = (float2*)out;
+  a.ld_in = ld_in;
+  a.ld_out = ld_out;
+  a.n_sig = n_sig;
+  a.n_tr = n_tr;
+  a.sm = smooth_weights(taps, n_tr);
+  ProfScope prof(ctx, "k_smooth_signals", s);
+  hipLaunchKernelGGL(k_smooth_signals, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  MRF_HIP(hipGetLastError());
   return MRF_OK;
 }
 

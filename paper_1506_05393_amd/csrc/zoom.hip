@@ -14,9 +14,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "bloch.h"
 #include "internal.h"
+#include "smooth.h"
 
 namespace mrf {
 
@@ -49,6 +51,7 @@ struct ZoomArgs {
   int64_t* memo_keys;  // [grid blocks][memo_cap]
   float* memo_vals;
   const mrf_zoom_schedule* sch;  // device copy (workspace)
+  SmoothW sm;  // temporal smoothing of the entries (SM kernels)
 };
 
 __device__ __forceinline__ int32_t round_half_away(double x) {
@@ -114,7 +117,7 @@ struct EngineParams {
   int32_t dims[4];
 };
 
-template <int G>
+template <int G, bool SM>
 struct Engine {
   EngineParams pa;
 
@@ -135,6 +138,8 @@ struct Engine {
   float cval;
   bool cknown;
   float mm;  // smallest decision margin
+  // smoothing weights (SM only; the plain kernel carries no copy)
+  std::conditional_t<SM, SmoothW, char> sw;
 
   __device__ int64_t key(const int32_t* i) const {
     return (((int64_t)i[0] * pa.dims[1] + i[1]) * pa.dims[2] + i[2]) * pa.dims[3] + i[3];
@@ -185,9 +190,32 @@ struct Engine {
     Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
+    // SM: a delay line of five raw samples; readout j yields smoothed sample
+    // o = j - 2 (scale 0 while o < 0), which meets voxel value o
+    float hx[kSmoothLen], hy[kSmoothLen];
+#pragma unroll
+    for (int k = 0; k < kSmoothLen; ++k) hx[k] = hy[k] = 0.f;
+    auto vidx = [&](int32_t j) { return SM ? max(j - kSmoothLag, 0) : j; };
+    auto scale_of = [&](int32_t j) -> float {
+      if constexpr (SM) {
+        const int32_t o = j - kSmoothLag;
+        return o >= 2 ? sw.full : (o == 1 ? sw.head[1] : (o == 0 ? sw.head[0] : 0.0f));
+      } else {
+        return 1.0f;
+      }
+    };
+    // the output sample's product with the voxel and its norm
+    auto accumulate = [&](float sx, float sy, v2 v) {
+      // v conj(d): (vr + i vi)(x - i y), v the unit-norm voxel
+      const float vr = v.x * vinv, vi = v.y * vinv;
+      dr = fmaf(vr, sx, fmaf(vi, sy, dr));
+      di = fmaf(vi, sx, fmaf(-vr, sy, di));
+      n2 = fma((double)sx, (double)sx, n2);
+      n2 = fma((double)sy, (double)sy, n2);
+    };
     // one readout: the pulse, free evolution over TE, the sample's product
     // with the voxel, free evolution to the end of the TR
-    auto step = [&](v2 r1, v2 r2, v4 pc, v2 v, const float (&R)[NR]) {
+    auto step = [&](v2 r1, v2 r2, v4 pc, v2 v, const float (&R)[NR], float sc) {
       const float x = m.x, y = m.y, z = m.z;
       if (X_AXIS) {
         m.y = fmaf(R[1], z, R[0] * y);
@@ -198,12 +226,12 @@ struct Engine {
         m.z = fmaf(R[8], z, fmaf(R[7], y, R[6] * x));
       }
       free_evolve(m, pc.x, pc.y, r2.x, r1.x);
-      // v conj(d): (vr + i vi)(x - i y), v the unit-norm voxel
-      const float vr = v.x * vinv, vi = v.y * vinv;
-      dr = fmaf(vr, m.x, fmaf(vi, m.y, dr));
-      di = fmaf(vi, m.x, fmaf(-vr, m.y, di));
-      n2 = fma((double)m.x, (double)m.x, n2);
-      n2 = fma((double)m.y, (double)m.y, n2);
+      float sx = m.x, sy = m.y;
+      if constexpr (SM) {
+        smooth_push(hx, hy, sx, sy);
+        smooth_out(sw, hx, hy, sc, sx, sy);
+      }
+      accumulate(sx, sy, v);
       free_evolve(m, pc.z, pc.w, r2.y, r1.y);
     };
     int32_t j = 0;
@@ -216,7 +244,7 @@ struct Engine {
         q1[q] = p1[q];
         q2[q] = p2[q];
         qd[q] = pd[q];
-        qv[q] = vl[q];
+        qv[q] = vl[vidx(q)];
         ld_pulse(q, qr[q]);
       }
       // the ring holds readouts j .. j + kAhead - 1, and j + kAhead <= n
@@ -232,21 +260,33 @@ struct Engine {
           q1[q] = p1[jn];
           q2[q] = p2[jn];
           qd[q] = pd[jn];
-          qv[q] = vl[jn];
+          qv[q] = vl[vidx(jn)];
           ld_pulse(jn, qr[q]);
-          step(r1, r2, pc, v, R);
+          step(r1, r2, pc, v, R, scale_of(j + q));
         }
       }
 #pragma unroll
-      for (int q = 0; q < kAhead; ++q) step(q1[q], q2[q], qd[q], qv[q], qr[q]);
+      for (int q = 0; q < kAhead; ++q)
+        step(q1[q], q2[q], qd[q], qv[q], qr[q], scale_of(j + q));
       j += kAhead;
     }
     for (; j < n; ++j) {
       float R[NR];
       ld_pulse(j, R);
-      const v2 r1 = p1[j], r2 = p2[j], v = vl[j];
+      const v2 r1 = p1[j], r2 = p2[j], v = vl[vidx(j)];
       const v4 pc = pd[j];
-      step(r1, r2, pc, v, R);
+      step(r1, r2, pc, v, R, scale_of(j));
+    }
+    if constexpr (SM) {
+      // the last two outputs: zeros pushed after the last readout
+#pragma unroll
+      for (int t = 0; t < kSmoothLag; ++t) {
+        const int32_t o = n - kSmoothLag + t;
+        float sx, sy;
+        smooth_push(hx, hy, 0.f, 0.f);
+        smooth_out(sw, hx, hy, sw.tail[t], sx, sy);
+        if (o >= 0) accumulate(sx, sy, vl[o]);
+      }
     }
     if (pdr) *pdr = dr;
     if (pdi) *pdi = di;
@@ -617,7 +657,7 @@ __host__ __device__ inline size_t zoom_group_lds() {
 // One wave per block, 64 / G voxels per wave: each group of G lanes runs its
 // own voxel's stage machine and pulls its own voxels from the queue, so the
 // lanes that a decision leaves idle in one group work for the others.
-template <int G>
+template <int G, bool SM>
 __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   constexpr int NG = 64 / G;
   extern __shared__ __align__(16) unsigned char sm[];
@@ -680,7 +720,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
     ++serial;
 
-    Engine<G> e;
+    Engine<G, SM> e;
     e.pa.t1T = a.t1T;
     e.pa.t1ti = a.t1ti;
     e.pa.t2T = a.t2T;
@@ -689,6 +729,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.pa.n_tr = a.n_tr;
     e.pa.inversion = a.inversion;
     e.pa.x_axis = a.x_axis;
+    if constexpr (SM) e.sw = a.sm;
     e.pa.memo_cap = a.memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
@@ -775,6 +816,19 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+template <bool SM>
+static void launch_zoom_groups(int group, int blocks, size_t lds, hipStream_t st,
+                               const ZoomArgs& a) {
+  if (group == 8)
+    hipLaunchKernelGGL((k_zoom<8, SM>), dim3(blocks), dim3(64), lds, st, a);
+  else if (group == 16)
+    hipLaunchKernelGGL((k_zoom<16, SM>), dim3(blocks), dim3(64), lds, st, a);
+  else if (group == 32)
+    hipLaunchKernelGGL((k_zoom<32, SM>), dim3(blocks), dim3(64), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_zoom<64, SM>), dim3(blocks), dim3(64), lds, st, a);
+}
+
 static int32_t h_round_half_away(double x) {
   return (int32_t)(x >= 0.0 ? std::floor(x + 0.5) : -std::floor(-x + 0.5));
 }
@@ -997,6 +1051,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.n_tr = n_tr;
   a.inversion = t->inversion;
   a.x_axis = t->x_axis_pulses;
+  a.sm = smooth_weights(t->smooth ? t->smooth : 3, n_tr);
   for (int q = 0; q < 4; ++q) a.dims[q] = dims[q];
   a.vox = (const float2*)vox;
   a.ld_vox = ld_vox;
@@ -1027,14 +1082,10 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   MRF_HIP(hipGetLastError());
   auto launch = [&]() {
     ProfScope prof(ctx, "k_zoom", st);
-    if (plan.group == 8)
-      hipLaunchKernelGGL(k_zoom<8>, dim3(blocks), dim3(64), lds, st, a);
-    else if (plan.group == 16)
-      hipLaunchKernelGGL(k_zoom<16>, dim3(blocks), dim3(64), lds, st, a);
-    else if (plan.group == 32)
-      hipLaunchKernelGGL(k_zoom<32>, dim3(blocks), dim3(64), lds, st, a);
+    if (t->smooth)
+      launch_zoom_groups<true>(plan.group, blocks, lds, st, a);
     else
-      hipLaunchKernelGGL(k_zoom<64>, dim3(blocks), dim3(64), lds, st, a);
+      launch_zoom_groups<false>(plan.group, blocks, lds, st, a);
   };
   if (!lattice) {
     launch();
