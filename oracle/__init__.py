@@ -77,7 +77,7 @@ def lib():
         L.orc_simulate_grid.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32,
                                         C.c_int64, C.c_int64, dp, dp, dp, C.c_int32]
         L.orc_cc.argtypes = [C.c_int32, dp, dp, dp, dp]
-        L.orc_smooth.argtypes = [C.c_int32, C.c_int32, dp, dp]
+        L.orc_smooth.argtypes = [C.c_int32, C.c_int32, dp, dp, dp]
         L.orc_cc.restype = C.c_double
         L.orc_bruteforce.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
                                      C.c_int32, C.c_int32, lp, dp, dp, dp, dp, lp, dp,
@@ -168,18 +168,27 @@ def simulate_grid(seq, grid, k0=0, count=None, n_tr=None, threads=0):
     return re + 1j * im, nrm
 
 
-def smooth(x, taps: int) -> np.ndarray:
+def smooth(x, taps: int, phase_deg=None) -> np.ndarray:
     """Temporal smoothing of complex signals along the last axis (Methods,
-    Experiment 4): binomial 3- or 5-point weights, renormalised at the ends;
-    taps 0 or 1 return a copy."""
+    Experiment 4): binomial 3- or 5-point weights, renormalised at the ends,
+    applied in the frame demodulated by the RF phases phase_deg (one per
+    readout; a sequence, whose phase_deg is taken, or None for zero phases)
+    and modulated back; taps 0 or 1 return a copy."""
+    if phase_deg is not None and hasattr(phase_deg, "phase_deg"):
+        phase_deg = phase_deg.phase_deg
     x = np.asarray(x, np.complex128)
     flat = x.reshape(-1, x.shape[-1]) if x.ndim else x.reshape(1, 1)
     out = np.empty_like(flat)
     n = flat.shape[-1]
+    ph = None
+    if phase_deg is not None:
+        ph = np.ascontiguousarray(np.asarray(phase_deg, np.float64)[:n])
+        if ph.shape[0] < n:
+            raise ValueError("phase_deg shorter than the signals")
     for r in range(flat.shape[0]):
         re = np.ascontiguousarray(flat[r].real)
         im = np.ascontiguousarray(flat[r].imag)
-        rc = lib().orc_smooth(n, int(taps), _dp(re), _dp(im))
+        rc = lib().orc_smooth(n, int(taps), _dp(ph) if ph is not None else None, _dp(re), _dp(im))
         if rc != 0:
             raise ValueError(f"orc_smooth failed ({rc}): taps must be 0, 1, 3 or 5")
         out[r] = re + 1j * im

@@ -161,10 +161,12 @@ typedef struct {
   double* rftab;  /* [n4][n_tr][4] */
   int32_t inversion;
   int32_t smooth;  /* temporal smoothing of dictionary entries: 0, 3 or 5 taps */
+  double* demod;   /* [2][n_tr] cos, sin of the RF phase (smoothing frame) */
 } tables;
 
 static void tables_free(tables* t) {
   free(t->t1tab); free(t->t1ti); free(t->t2tab); free(t->dftab); free(t->rftab);
+  free(t->demod);
   memset(t, 0, sizeof *t);
 }
 
@@ -179,6 +181,13 @@ static int tables_build(const orc_seq* seq, const orc_grid* g, int32_t n_tr,
   t->inversion = seq->inversion;
   t->smooth = seq->smooth > 1 ? seq->smooth : 0;
   size_t n = (size_t)n_tr;
+  t->demod = (double*)malloc(sizeof(double) * 2 * n + 8);
+  if (!t->demod) return 2;
+  for (size_t j = 0; j < n; ++j) {
+    const double a = seq->phase_deg[j] * (ORC_PI / 180.0);
+    t->demod[j] = cos(a);
+    t->demod[n + j] = sin(a);
+  }
   t->t1tab = (double*)malloc(sizeof(double) * (size_t)t->n1 * 2 * n + 8);
   t->t1ti = (double*)malloc(sizeof(double) * (size_t)t->n1);
   t->t2tab = (double*)malloc(sizeof(double) * (size_t)t->n2 * 2 * n + 8);
@@ -222,8 +231,13 @@ static int tables_build(const orc_seq* seq, const orc_grid* g, int32_t n_tr,
  * Gaussian of 3 or 5 points applied along the readouts, here the binomial
  * weights (1, 2, 1) / 4 and (1, 4, 6, 4, 1) / 16; at the first and last
  * readouts the points that exist are used and their weights renormalised.
- * In place; taps 0 or 1 leave the signal unchanged. */
-int orc_smooth(int32_t n, int32_t taps, double* re, double* im) {
+ * The smoothing acts on the signal as the receiver records it, demodulated
+ * by each readout's RF phase (sample j times exp(-i phi_j)); the result is
+ * modulated back, so it stays in the frame of the unsmoothed signals. With
+ * c = s = NULL the phases are taken as zero. In place; taps 0 or 1 leave the
+ * signal unchanged. */
+static int smooth_in_frame(int32_t n, int32_t taps, const double* c, const double* s, double* re,
+                           double* im) {
   static const double w3[3] = {1.0, 2.0, 1.0};
   static const double w5[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
   if (taps == 0 || taps == 1) return 0;
@@ -237,9 +251,10 @@ int orc_smooth(int32_t n, int32_t taps, double* re, double* im) {
     free(xi);
     return 2;
   }
-  for (int32_t j = 0; j < n; ++j) {
-    xr[j] = re[j];
-    xi[j] = im[j];
+  for (int32_t j = 0; j < n; ++j) {  /* demodulate: (re + i im)(c - i s) */
+    const double cj = c ? c[j] : 1.0, sj = s ? s[j] : 0.0;
+    xr[j] = re[j] * cj + im[j] * sj;
+    xi[j] = im[j] * cj - re[j] * sj;
   }
   for (int32_t j = 0; j < n; ++j) {
     double sr = 0.0, si = 0.0, sw = 0.0;
@@ -250,19 +265,38 @@ int orc_smooth(int32_t n, int32_t taps, double* re, double* im) {
       si += w[k + h] * xi[q];
       sw += w[k + h];
     }
-    re[j] = sr / sw;
-    im[j] = si / sw;
+    sr /= sw;
+    si /= sw;
+    const double cj = c ? c[j] : 1.0, sj = s ? s[j] : 0.0;  /* modulate back: (sr + i si)(c + i s) */
+    re[j] = sr * cj - si * sj;
+    im[j] = sr * sj + si * cj;
   }
   free(xr);
   free(xi);
   return 0;
 }
 
+int orc_smooth(int32_t n, int32_t taps, const double* phase_deg, double* re, double* im) {
+  if (!phase_deg || taps == 0 || taps == 1) return smooth_in_frame(n, taps, NULL, NULL, re, im);
+  if (n < 0) return 1;
+  double* cs = (double*)malloc(sizeof(double) * 2 * (size_t)(n + 1));
+  if (!cs) return 2;
+  for (int32_t j = 0; j < n; ++j) {
+    const double a = phase_deg[j] * (ORC_PI / 180.0);
+    cs[j] = cos(a);
+    cs[n + j] = sin(a);
+  }
+  const int rc = smooth_in_frame(n, taps, cs, cs + n, re, im);
+  free(cs);
+  return rc;
+}
+
 /* The samples of dictionary entry f: the recursion, then the sequence's
  * temporal smoothing (if any). */
 static void entry_samples(const tables* t, const entry_factors* f, double* re, double* im) {
   run_entry(t->n_tr, t->inversion, f, re, im, NULL);
-  if (t->smooth) orc_smooth(t->n_tr, t->smooth, re, im);
+  if (t->smooth)
+    smooth_in_frame(t->n_tr, t->smooth, t->demod, t->demod + t->n_tr, re, im);
 }
 
 static void tables_view(const tables* t, int64_t k, entry_factors* f) {

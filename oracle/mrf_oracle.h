@@ -36,7 +36,8 @@ typedef struct {
   const double* te_ms;       /* [n] echo times, 0 < te < tr */
   int32_t inversion;         /* 1: ideal inversion at t = 0 */
   double ti_ms;              /* inversion to first pulse */
-  int32_t smooth;            /* dictionary entries smoothed over 3 or 5 readouts (0: none) */
+  int32_t smooth;            /* dictionary entries smoothed over 3 or 5 readouts (0: none),
+                                in the frame demodulated by the RF phases */
 } orc_seq;
 
 typedef struct {
@@ -97,8 +98,10 @@ int orc_bruteforce(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
                    double* pd_re, double* pd_im, int64_t* topk_idx,
                    double* topk_cc, int32_t n_threads);
 
-/* ---- temporal smoothing (Experiment 4): binomial 3 / 5 points, in place ---- */
-int orc_smooth(int32_t n, int32_t taps, double* re, double* im);
+/* ---- temporal smoothing (Experiment 4): binomial 3 / 5 points, in place,
+ * in the frame demodulated by the RF phases phase_deg[0..n) (NULL: zero
+ * phases); the result is modulated back ---- */
+int orc_smooth(int32_t n, int32_t taps, const double* phase_deg, double* re, double* im);
 
 /* ---- CC map (Experiment 1): out[v][i] = CC(v, entry k0 + i), Eq. 1 ---- */
 int orc_cc_map(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,

@@ -3,10 +3,12 @@ Fig. 7B): a moving Gaussian of 3 or 5 points along the readouts, applied to
 the fingerprints and to the dictionary.
 
 The weights are the binomial ones, (1, 2, 1) / 4 and (1, 4, 6, 4, 1) / 16,
-truncated and renormalised at the first and last readouts. Checked against
-NumPy's convolution, against closed forms (constants and ramps pass, the
-alternating signal is removed, 5 points = 3 points twice), and, for the
-dictionary side, against an independent expm dictionary smoothed by NumPy.
+truncated and renormalised at the first and last readouts, applied to the
+signal demodulated by each readout's RF phase and modulated back. Checked
+against NumPy's convolution, against closed forms (constants and ramps pass,
+the alternating signal is removed, 5 points = 3 points twice, a constant in
+the demodulated frame passes under any phases), and, for the dictionary side,
+against an independent expm dictionary smoothed by NumPy.
 """
 import dataclasses
 
@@ -19,12 +21,14 @@ from tests import bloch_ref
 W = {3: np.array([1.0, 2.0, 1.0]), 5: np.array([1.0, 4.0, 6.0, 4.0, 1.0])}
 
 
-def _np_smooth(x, taps):
-    """Smoothing along the last axis by np.convolve; edge weights renormalised."""
+def _np_smooth(x, taps, phase_deg=None):
+    """Smoothing along the last axis by np.convolve; edge weights renormalised;
+    with phases: M conv(M^H x), M = diag(exp(i phase))."""
     x = np.atleast_2d(np.asarray(x, np.complex128))
     n = x.shape[-1]
+    m = np.ones(n) if phase_deg is None else np.exp(1j * np.deg2rad(phase_deg[:n]))
     den = np.convolve(np.ones(n), W[taps], "same")
-    return np.stack([np.convolve(r, W[taps], "same") / den for r in x])
+    return np.stack([m * np.convolve(r * m.conj(), W[taps], "same") / den for r in x])
 
 
 def _rand(shape, seed):
@@ -50,6 +54,22 @@ def test_smooth_closed_forms(orc, taps):
     assert np.max(np.abs(orc.smooth(ramp, taps)[h:n - h] - ramp[h:n - h])) < 1e-12
     alt = (-1.0) ** np.arange(n) * (1.5 - 0.5j)
     assert np.max(np.abs(orc.smooth(alt, taps)[h:n - h])) < 1e-15
+
+
+@pytest.mark.parametrize("taps", [3, 5])
+def test_smooth_in_the_demodulated_frame(orc, taps):
+    """Against M conv(M^H x); a signal constant after demodulation passes
+    unchanged whatever the phases (with phases 0/180 it alternates in sign,
+    which the plain smoothing would remove); zero phases = plain smoothing."""
+    rng = np.random.default_rng(30 + taps)
+    ph = rng.choice([0.0, 90.0, 180.0], 41) + rng.uniform(-20, 20, 41)
+    x = _rand((3, 41), 31)
+    assert np.max(np.abs(orc.smooth(x, taps, ph) - _np_smooth(x, taps, ph))) < 1e-14
+    alt = np.tile([0.0, 180.0], 21)[:41]
+    c = (0.4 - 1.1j) * np.exp(1j * np.deg2rad(alt))
+    assert np.max(np.abs(orc.smooth(c, taps, alt) - c)) < 1e-15
+    assert np.max(np.abs(orc.smooth(c, taps)[2:-2])) < 1e-15
+    assert np.array_equal(orc.smooth(x, taps, np.zeros(41)), orc.smooth(x, taps))
 
 
 def test_smooth_five_is_three_twice_in_the_interior(orc):
@@ -91,12 +111,12 @@ def test_smoothed_dictionary_matches_independent_one(orc, taps):
     seq, grid = _tiny(taps)
     D0 = np.stack([bloch_ref.simulate(seq, *map(float, grid.values(k)))
                    for k in range(grid.size)])
-    Ds = _np_smooth(D0, taps)
+    Ds = _np_smooth(D0, taps, seq.phase_deg)
     D, _ = orc.simulate_grid(seq, grid)
     assert np.max(np.abs(D - Ds)) < 1e-12 * np.max(np.abs(Ds))
     rng = np.random.default_rng(12)
     V = _rand((5, 24), 13) * 0.1 + D0[rng.integers(0, grid.size, 5)]
-    Vs = _np_smooth(V, taps)
+    Vs = _np_smooth(V, taps, seq.phase_deg)
     m = orc.cc_map(seq, grid, Vs)
     Dn = Ds / np.linalg.norm(Ds, axis=1, keepdims=True)
     Vn = Vs / np.linalg.norm(Vs, axis=1, keepdims=True)
@@ -125,7 +145,7 @@ def test_zoom_on_smoothed_on_grid_fingerprints_is_exact(orc):
     seq, grid = _tiny(3)
     D, _ = orc.simulate_grid(seq, grid)
     ks = np.array([3, 61, 100, grid.size - 2])
-    V = orc.smooth(np.stack([orc.simulate(seq, *map(float, grid.values(k))) for k in ks]), 3)
+    V = orc.smooth(np.stack([orc.simulate(seq, *map(float, grid.values(k))) for k in ks]), 3, seq)
     z = orc.zoom(seq, grid, orc.schedule_paper(seq, grid), V)
     b = orc.bruteforce(seq, grid, V)
     assert np.array_equal(b["idx"], ks)
