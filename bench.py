@@ -39,6 +39,8 @@ def parse():
                         "for scaling HBM byte counters, and exit")
     p.add_argument("--no-ccmap", action="store_true",
                    help="skip the CC map of Experiment 1 and its Property I-III checks")
+    p.add_argument("--no-smooth", action="store_true",
+                   help="skip the temporal smoothing measurement")
     p.add_argument("--no-peaks", action="store_true",
                    help="skip the measured device peaks (MFMA-only loops, write and copy streams)")
     p.add_argument("--serve-requests", type=int, default=60)
@@ -333,6 +335,58 @@ def cc_map_bench(api, ctx, torch, repeats: int = 5):
                              "maps (C++, 2.0 GHz dual-core laptop)"}
 
 
+def smoothing_bench(api, ctx, torch, w, vox, d32, ws, wsz, base, repeats: int = 3):
+    """Temporal 3-point smoothing (Methods, Experiment 4; Fig. 7B) on the
+    slice: the fingerprints smoothed by mrf_smooth_signals, the dictionary
+    smoothed by K1's delay line, then brute force and ZOOM; times beside the
+    unsmoothed ones (`base`) and T1/T2/df errors against the phantom's truth."""
+    import dataclasses
+    seq3 = dataclasses.replace(w.seq, smooth=3)
+    sq3 = api.Sequence(ctx, seq3)
+    ga = api.GridArg(w.grid)
+    sched = api.schedule_paper(ctx, sq3, ga)
+    n_vox = vox.shape[0]
+    vs = torch.empty_like(vox)
+    out = api._result_tensors(n_vox, ctx.device)
+    outz = api._result_tensors(n_vox, ctx.device, with_nsim=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    t = {"smooth_signals": [], "dict_f32": [], "match_f32": [], "zoom": []}
+    for r in range(repeats + 1):
+        e = [ev() for _ in range(5)]
+        e[0].record()
+        api.smooth_signals(ctx, vox, 3, out=vs, seq=sq3)
+        e[1].record()
+        api.simulate_dictionary(ctx, sq3, ga, dtype="f32", out=d32)
+        e[2].record()
+        api.match_bruteforce(ctx, d32, vs, top_k=2, workspace=ws, out=out)
+        e[3].record()
+        api.zoom_search(ctx, sq3, ga, vs, sched=sched, workspace=wsz, out=outz)
+        e[4].record()
+        torch.cuda.synchronize()
+        if r:
+            for k, a_, b_ in zip(t, e[:-1], e[1:]):
+                t[k].append(a_.elapsed_time(b_))
+    med = {k: float(np.median(v)) for k, v in t.items()}
+    ph = w.phantom
+
+    def err(idx):
+        t1, t2, df, _ = w.grid.values(idx)
+        return {"T1_ms": float(np.mean(np.abs(t1 - ph.t1))),
+                "T2_ms": float(np.mean(np.abs(t2 - ph.t2))),
+                "df_Hz": float(np.mean(np.abs(df - ph.df)))}
+
+    idx_b = out["idx"].cpu().numpy()
+    idx_z = outz["idx"].cpu().numpy()
+    return {"taps": 3, "ms": med,
+            "dict_f32_ratio_vs_unsmoothed": med["dict_f32"] / base["dict_f32"],
+            "zoom_ratio_vs_unsmoothed": med["zoom"] / base["zoom"],
+            "zoom_index_agreement_vs_brute": float(np.mean(idx_z == idx_b)),
+            "mean_abs_error_brute_smoothed": err(idx_b),
+            "mean_abs_error_brute_unsmoothed": err(base["idx_f32"]),
+            "mean_abs_error_zoom_smoothed": err(idx_z),
+            "mean_abs_error_zoom_unsmoothed": err(base["idx_zoom"])}
+
+
 def device_peaks(api, ctx, torch, write_gb: float = 16.0):
     """Measured device peaks: MFMA-only loops per dtype and a non-temporal
     write stream (libmrf probe kernels, timed by HIP events on their launch
@@ -591,6 +645,12 @@ def main():
         "paper_context": "paper: 116.72 s per 1731-voxel 64x64 slice (ZOOM, df dictionary) on a "
                          "2.0 GHz dual-core laptop, C++",
     }
+    if not args.no_smooth:
+        log("smoothing ...")
+        res["smoothing"] = smoothing_bench(
+            api, ctx, torch, w, vox, d32, ws, wsz,
+            {"dict_f32": res["rows_ms"]["dict_f32"], "zoom": res["zoom"]["slice_ms_p50"],
+             "idx_f32": idx32, "idx_zoom": idxz})
     if not args.no_volume:
         log("volume ...")
         del d32, d16

@@ -79,7 +79,8 @@ typedef struct {
   /* Temporal smoothing of dictionary entries (Methods, Experiment 4): 0 or 1
    * none, 3 or 5 readouts (binomial weights (1, 2, 1) / 4 and
    * (1, 4, 6, 4, 1) / 16, renormalised over the readouts that exist at the
-   * first and last readouts). Every dictionary entry the library simulates
+   * first and last readouts), applied to the samples demodulated by their RF
+   * phase (times exp(-i phase_j)) and modulated back. Every dictionary entry the library simulates
    * for this sequence (dictionaries, CC maps, ZOOM candidates, BF16
    * re-scoring) is smoothed; fingerprints from mrf_simulate_signals are not:
    * smooth them with mrf_smooth_signals. Other values: MRF_ERR_INVALID. */
@@ -155,13 +156,16 @@ int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid, 
  * Experiment 4: the fingerprints are smoothed like the dictionary). Row i of
  * n_sig: in[i*ld_in + j] -> out[i*ld_out + j], j < n_tr, device memory,
  * caller-owned. taps 3 or 5: the weights of mrf_sequence_desc.smooth, with
- * the same end renormalisation; taps 0 or 1: a copy. in == out with
- * ld_in == ld_out smooths in place; otherwise the two must not overlap.
+ * the same end renormalisation, in the frame demodulated by seq's RF phases
+ * and modulated back (seq NULL: zero phases); taps 0 or 1: a copy. in == out
+ * with ld_in == ld_out smooths in place; otherwise the two must not overlap.
  * Returns without waiting (profile name "k_smooth_signals").
- * Errors: other taps, ld < n_tr, NULL or misaligned (8 B) pointers with work
- * to do, partially overlapping rows -> MRF_ERR_INVALID (nothing launched). */
-int mrf_smooth_signals(mrf_context* ctx, const void* in, int64_t ld_in, void* out, int64_t ld_out,
-                       int64_t n_sig, int32_t n_tr, int32_t taps, void* stream);
+ * Errors: other taps, n_tr above seq's length, ld < n_tr, NULL or misaligned
+ * (8 B) pointers with work to do, partially overlapping rows ->
+ * MRF_ERR_INVALID (nothing launched). */
+int mrf_smooth_signals(mrf_context* ctx, const mrf_sequence* seq, const void* in, int64_t ld_in,
+                       void* out, int64_t ld_out, int64_t n_sig, int32_t n_tr, int32_t taps,
+                       void* stream);
 
 /* Simulate fingerprints at arbitrary (not necessarily on-grid) parameter
  * values: params is a device FP64 array [count][4] = (T1 ms, T2 ms, df Hz,

@@ -69,8 +69,8 @@ _SIGS = [
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_void_p, C.c_int32, C.c_int64,
       C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     ("mrf_smooth_signals", C.c_int,
-     [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
-      C.c_void_p]),
+     [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_int32,
+      C.c_int32, C.c_void_p]),
     ("mrf_simulate_signals", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
       C.c_void_p]),

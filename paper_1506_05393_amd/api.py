@@ -214,17 +214,19 @@ def simulate_signals(ctx: Context, seq: Sequence, params: torch.Tensor,
 
 
 def smooth_signals(ctx: Context, x: torch.Tensor, taps: int, out: Optional[torch.Tensor] = None,
-                   stream=None) -> torch.Tensor:
+                   seq: Optional[Sequence] = None, stream=None) -> torch.Tensor:
     """Temporal smoothing of complex64 cuda signals [n_sig, n_tr] along the
-    readouts (taps 3 or 5; 0 or 1 copy). out=None returns a new tensor;
-    out=x smooths in place."""
+    readouts (taps 3 or 5; 0 or 1 copy), in the frame demodulated by seq's RF
+    phases (None: zero phases). out=None returns a new tensor; out=x smooths
+    in place."""
     if x.dtype != torch.complex64 or x.dim() != 2 or x.stride(1) != 1:
         raise ValueError("x must be complex64 [n_sig, n_tr] with unit stride along readouts")
     if out is None:
         out = torch.empty_like(x, memory_format=torch.contiguous_format)
     if out.dtype != torch.complex64 or out.shape != x.shape or out.stride(1) != 1:
         raise ValueError("out must be complex64 of x's shape with unit readout stride")
-    L.check(ctx._lib.mrf_smooth_signals(ctx.handle, x.data_ptr(), x.stride(0), out.data_ptr(),
+    L.check(ctx._lib.mrf_smooth_signals(ctx.handle, seq.handle if seq is not None else None,
+                                        x.data_ptr(), x.stride(0), out.data_ptr(),
                                         out.stride(0), x.shape[0], x.shape[1], int(taps),
                                         _stream_ptr(stream)))
     return out

@@ -45,6 +45,7 @@ struct Tables {
   int32_t x_axis_pulses = 0;
   // dictionary entries smoothed over 3 or 5 readouts (0: none), from the sequence
   int32_t smooth = 0;
+  const float2* demod = nullptr;  // [n_tr] (cos, sin) of the RF phases (the sequence's)
   float2* t1 = nullptr;   // [n_tr][n1]  (1-E1 over TE, 1-E1 over TR-TE)
   float* t1ti = nullptr;  // [n1]        (1-E1 over TI)
   float2* t2 = nullptr;   // [n_tr][n2]  (1-E2 over TE, 1-E2 over TR-TE)
@@ -98,6 +99,7 @@ struct mrf_sequence {
   int32_t smooth = 0;     // temporal smoothing of dictionary entries: 0, 3 or 5 readouts
   double omega_hz = 0.0;  // 1000 / min TR: CC pseudo-period in df (Property II)
   double* dev = nullptr;  // device FP64 [4][n]: TE, TR-TE, flip angle, RF phase
+  float2* demod = nullptr;  // device [n] (cos, sin) of the RF phase (inside dev's allocation)
   std::mutex mu;
   std::vector<mrf::Tables> cache;  // small LRU keyed by grid contents and n_tr
 };

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(64) void k_pack_bf16(const float2* __restrict__ vox
 // the dictionary is (the same delay line, weights and order of operations).
 struct RescoreArgs {
   SmoothW sm;
+  const float2* demod;  // [n_tr] (cos, sin) of the RF phases (SM)
   const float2* t1T;
   const float* t1ti;
   const float2* t2T;
@@ -405,10 +406,14 @@ __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
       if (SM) {
         const int32_t o = j - kSmoothLag;
         const float sc = o >= 2 ? a.sm.full : (o == 1 ? a.sm.head[1] : a.sm.head[0]);
-        float dx, dy;
-        smooth_push(hx, hy, m.x, m.y);
+        float dx = m.x, dy = m.y;
+        smooth_demod(a.demod[j], dx, dy);
+        smooth_push(hx, hy, dx, dy);
         smooth_out(a.sm, hx, hy, sc, dx, dy);
-        if (o >= 0) acc(o, dx, dy);
+        if (o >= 0) {
+          smooth_remod(a.demod[o], dx, dy);
+          acc(o, dx, dy);
+        }
       } else {
         acc(j, m.x, m.y);
       }
@@ -421,7 +426,10 @@ __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {
         float dx, dy;
         smooth_push(hx, hy, 0.f, 0.f);
         smooth_out(a.sm, hx, hy, a.sm.tail[t], dx, dy);
-        if (o >= 0) acc(o, dx, dy);
+        if (o >= 0) {
+          smooth_remod(a.demod[o], dx, dy);
+          acc(o, dx, dy);
+        }
       }
     }
   }
@@ -611,6 +619,7 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   r.topk_idx = topk_idx;
   r.topk_cc = topk_cc;
   r.sm = smooth_weights(t->smooth ? t->smooth : 3, d->n_tr);
+  r.demod = t->demod;
   {
     ProfScope prof(ctx, "k_rescore", st);
     if (t->smooth)

@@ -195,6 +195,7 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   t.n4 = g->b1.n > 0 ? g->b1.n : 1;
   t.inversion = seq->inversion;
   t.smooth = seq->smooth;
+  t.demod = seq->demod;
   t.x_axis_pulses = 1;
   for (int32_t j = 0; j < n_tr; ++j)
     if (std::fmod(seq->ph[j], 180.0) != 0.0) t.x_axis_pulses = 0;
@@ -432,12 +433,30 @@ int mrf_sequence_create(mrf_context* ctx, const mrf_sequence_desc* d, mrf_sequen
       h[2 * (size_t)d->n + j] = d->fa_deg[j];
       h[3 * (size_t)d->n + j] = d->phase_deg[j];
     }
-    if (hipMalloc(&s->dev, sizeof(double) * h.size()) != hipSuccess) {
+    // (cos, sin) of each RF phase in FP32, exact for multiples of 90 degrees:
+    // the frame that temporal smoothing demodulates into
+    std::vector<float2> cs(d->n);
+    for (int32_t j = 0; j < d->n; ++j) {
+      const double p = d->phase_deg[j];
+      if (std::fmod(p, 90.0) == 0.0) {
+        const int q = (int)(((long long)(p / 90.0) % 4 + 4) % 4);
+        static const float qc[4] = {1.0f, 0.0f, -1.0f, 0.0f}, qs[4] = {0.0f, 1.0f, 0.0f, -1.0f};
+        cs[j] = make_float2(qc[q], qs[q]);
+      } else {
+        const double a = p * (M_PI / 180.0);
+        cs[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+    }
+    const size_t bytes = sizeof(double) * h.size() + sizeof(float2) * cs.size();
+    if (hipMalloc(&s->dev, bytes) != hipSuccess) {
       delete s;
       set_error("out of device memory for the sequence");
       return MRF_ERR_OOM;
     }
+    s->demod = (float2*)(s->dev + h.size());
     hipError_t e = hipMemcpy(s->dev, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(s->demod, cs.data(), sizeof(float2) * cs.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(s->dev);
       delete s;

@@ -120,6 +120,7 @@ struct SimArgs {
   double* norm;
   float* cc;        // CC map output (MODE 3)
   SmoothW sm;       // temporal smoothing weights (SM kernels)
+  const float2* demod;  // [n_tr] (cos, sin) of the RF phases (SM kernels)
 };
 
 struct EntryState {
@@ -141,8 +142,9 @@ struct Dots {
 // MODE 3 stores nothing and accumulates v conj(d) against the fingerprint
 // `vox` (one value per readout, the same for every thread) into dt.
 // SM: the entry is smoothed over the readouts (a five-sample delay line per
-// entry; output o = j - 2 leaves the line while raw sample j enters it, and
-// two zero pushes after the last readout give the last two outputs).
+// entry, in the frame demodulated by the RF phase; output o = j - 2 leaves
+// the line while raw sample j enters it, and two zero pushes after the last
+// readout give the last two outputs).
 template <int MODE, int PK, bool DF_LDS, bool SCALED, bool SM>
 __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
                                          const float* __restrict__ rftab, rsrc_t r1s, rsrc_t r2s,
@@ -246,7 +248,12 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
         const int ol = SM ? ((jj - kSmoothLag) & 3) : (jj & 3);
         const bool out = !SM || o >= 0;
         float sc = 1.f;
-        if (SM) sc = o >= 2 ? a.sm.full : (o == 1 ? a.sm.head[1] : a.sm.head[0]);
+        float2 dmj = make_float2(1.f, 0.f), dmo = make_float2(1.f, 0.f);
+        if (SM) {
+          sc = o >= 2 ? a.sm.full : (o == 1 ? a.sm.head[1] : a.sm.head[0]);
+          dmj = a.demod[j];
+          dmo = a.demod[o >= 0 ? o : 0];
+        }
         float2 vo = make_float2(0.f, 0.f);
         if (MODE == 3 && out) {
           vo = vox[o];
@@ -265,8 +272,10 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
           free_evolve(m[q], pc.x, pc.y, r2.x, r1.x);
           float sx = m[q].x, sy = m[q].y;
           if (SM) {
+            smooth_demod(dmj, sx, sy);
             smooth_push(hx[q], hy[q], sx, sy);
             smooth_out(a.sm, hx[q], hy[q], sc, sx, sy);
+            smooth_remod(dmo, sx, sy);
           }
           if (out) emit(q, ol, o, sx, sy, vo);
           free_evolve(m[q], pc.z, pc.w, r2.y, r1.y);
@@ -295,11 +304,13 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
         vo = vox[o];
         pv = fmaf(vo.x, vo.x, fmaf(vo.y, vo.y, pv));
       }
+      const float2 dmo = a.demod[o >= 0 ? o : 0];
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
         float sx, sy;
         smooth_push(hx[q], hy[q], 0.f, 0.f);
         smooth_out(a.sm, hx[q], hy[q], a.sm.tail[t], sx, sy);
+        smooth_remod(dmo, sx, sy);
         if (o >= 0) emit(q, 2 + t, o, sx, sy, vo);
       }
     }
@@ -401,7 +412,10 @@ template <int MODE>
 static void launch_sim_mode(SimArgs a, const Tables& t, int64_t blocks, hipStream_t stream,
                             const float2* vox = nullptr) {
   const bool df_lds = a.n3 <= kLdsMaxN3;
-  if (t.smooth) a.sm = smooth_weights(t.smooth, a.n_tr);
+  if (t.smooth) {
+    a.sm = smooth_weights(t.smooth, a.n_tr);
+    a.demod = t.demod;
+  }
   const bool lane = a.n4 > 1;
   if (!lane && t.x_axis_pulses)
     launch_sim_variant<MODE, kXAxisUniform>(a, t, df_lds, blocks, stream, vox);
@@ -460,6 +474,7 @@ struct SmoothArgs {
   int64_t ld_in, ld_out, n_sig;
   int32_t n_tr;
   SmoothW sm;
+  const float2* demod;  // [n_tr] (cos, sin) of the RF phases, or NULL (zero phases)
 };
 
 __global__ __launch_bounds__(256) void k_smooth_signals(SmoothArgs a) {
@@ -469,11 +484,20 @@ __global__ __launch_bounds__(256) void k_smooth_signals(SmoothArgs a) {
   const float2* x = a.in + row * a.ld_in;
   float2* y = a.out + row * a.ld_out;
   const int32_t n = a.n_tr;
+  // raw sample j demodulated by its RF phase
+  auto load = [&](int32_t j) {
+    float2 v = make_float2(0.f, 0.f);
+    if (j < n) {
+      v = x[j];
+      if (a.demod) smooth_demod(a.demod[j], v.x, v.y);
+    }
+    return v;
+  };
   float2 prev = make_float2(0.f, 0.f);
-  float2 cur = lane < n ? x[lane] : make_float2(0.f, 0.f);
+  float2 cur = load(lane);
   for (int32_t j0 = 0; j0 < n; j0 += 64) {
     const int32_t jn = j0 + 64 + lane;
-    const float2 nxt = jn < n ? x[jn] : make_float2(0.f, 0.f);
+    const float2 nxt = load(jn);
     float hx[kSmoothLen], hy[kSmoothLen];
 #pragma unroll
     for (int k = 0; k < kSmoothLen; ++k) {
@@ -493,7 +517,10 @@ __global__ __launch_bounds__(256) void k_smooth_signals(SmoothArgs a) {
                                   : a.sm.full;
     float ox, oy;
     smooth_out(a.sm, hx, hy, sc, ox, oy);
-    if (j < n) y[j] = make_float2(ox, oy);
+    if (j < n) {
+      if (a.demod) smooth_remod(a.demod[j], ox, oy);
+      y[j] = make_float2(ox, oy);
+    }
     prev = cur;
     cur = nxt;
   }
@@ -633,10 +660,12 @@ extern "C" int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_g
   return MRF_OK;
 }
 
-extern "C" int mrf_smooth_signals(mrf_context* ctx, const void* in, int64_t ld_in, void* out,
-                                  int64_t ld_out, int64_t n_sig, int32_t n_tr, int32_t taps,
-                                  void* stream) {
+extern "C" int mrf_smooth_signals(mrf_context* ctx, const mrf_sequence* seq, const void* in,
+                                  int64_t ld_in, void* out, int64_t ld_out, int64_t n_sig,
+                                  int32_t n_tr, int32_t taps, void* stream) {
   MRF_CHECK_ARG(ctx, "context must not be NULL");
+  MRF_CHECK_ARG(!seq || n_tr <= seq->n, "n_tr (%d) exceeds the sequence length (%d)", n_tr,
+                seq ? seq->n : 0);
   MRF_CHECK_ARG(taps == 0 || taps == 1 || taps == 3 || taps == 5,
                 "taps must be 0, 1, 3 or 5 (got %d)", taps);
   MRF_CHECK_ARG(n_sig >= 0 && n_tr >= 0, "n_sig and n_tr must be >= 0");
@@ -667,6 +696,7 @@ extern "C" int mrf_smooth_signals(mrf_context* ctx, const void* in, int64_t ld_i
   a.n_sig = n_sig;
   a.n_tr = n_tr;
   a.sm = smooth_weights(taps, n_tr);
+  a.demod = seq ? seq->demod : nullptr;
   ProfScope prof(ctx, "k_smooth_signals", s);
   hipLaunchKernelGGL(k_smooth_signals, dim3((unsigned)blocks), dim3(256), 0, s, a);
   MRF_HIP(hipGetLastError());

@@ -4,6 +4,13 @@
 // window passes the first or last readout only the points that exist count
 // and the weights are renormalised over them.
 //
+// The window acts on the signal as the receiver records it: sample j is
+// demodulated by its RF phase (times exp(-i phi_j)) before it enters the
+// window, and each output is modulated back (times exp(i phi_o)), so smoothed
+// entries and fingerprints stay in the frame of the unsmoothed ones. The
+// (cos, sin) pairs are exact for phases that are multiples of 90 degrees,
+// where both steps only swap and negate components.
+//
 // Kernels that simulate an entry readout by readout smooth it with a delay
 // line of five raw samples: after raw sample j is pushed, the line holds
 // samples j-4 .. j and yields smoothed sample o = j - 2. The 3-point weights
@@ -61,6 +68,20 @@ inline SmoothW smooth_weights(int taps, int32_t n_tr) {
   s.tail[0] = inv_den((int64_t)n_tr - 2);
   s.tail[1] = inv_den((int64_t)n_tr - 1);
   return s;
+}
+
+// Device: (x + i y) times exp(-i phi), cs = (cos phi, sin phi).
+__device__ __forceinline__ void smooth_demod(float2 cs, float& x, float& y) {
+  const float a = x, b = y;
+  x = fmaf(a, cs.x, b * cs.y);
+  y = fmaf(b, cs.x, -(a * cs.y));
+}
+
+// Device: (x + i y) times exp(i phi).
+__device__ __forceinline__ void smooth_remod(float2 cs, float& x, float& y) {
+  const float a = x, b = y;
+  x = fmaf(a, cs.x, -(b * cs.y));
+  y = fmaf(a, cs.y, b * cs.x);
 }
 
 // Device: push raw sample (x, y) into the delay line.

@@ -52,6 +52,7 @@ struct ZoomArgs {
   float* memo_vals;
   const mrf_zoom_schedule* sch;  // device copy (workspace)
   SmoothW sm;  // temporal smoothing of the entries (SM kernels)
+  const float2* demod;  // [n_tr] (cos, sin) of the RF phases (SM kernels)
 };
 
 __device__ __forceinline__ int32_t round_half_away(double x) {
@@ -140,6 +141,7 @@ struct Engine {
   float mm;  // smallest decision margin
   // smoothing weights (SM only; the plain kernel carries no copy)
   std::conditional_t<SM, SmoothW, char> sw;
+  std::conditional_t<SM, const float2*, char> dm;  // (cos, sin) of the RF phases
 
   __device__ int64_t key(const int32_t* i) const {
     return (((int64_t)i[0] * pa.dims[1] + i[1]) * pa.dims[2] + i[2]) * pa.dims[3] + i[3];
@@ -190,8 +192,9 @@ struct Engine {
     Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
-    // SM: a delay line of five raw samples; readout j yields smoothed sample
-    // o = j - 2 (scale 0 while o < 0), which meets voxel value o
+    // SM: a delay line of five raw samples, demodulated by the RF phase;
+    // readout j yields smoothed sample o = j - 2 (scale 0 while o < 0),
+    // modulated back, which meets voxel value o
     float hx[kSmoothLen], hy[kSmoothLen];
 #pragma unroll
     for (int k = 0; k < kSmoothLen; ++k) hx[k] = hy[k] = 0.f;
@@ -215,7 +218,7 @@ struct Engine {
     };
     // one readout: the pulse, free evolution over TE, the sample's product
     // with the voxel, free evolution to the end of the TR
-    auto step = [&](v2 r1, v2 r2, v4 pc, v2 v, const float (&R)[NR], float sc) {
+    auto step = [&](v2 r1, v2 r2, v4 pc, v2 v, const float (&R)[NR], int32_t jr) {
       const float x = m.x, y = m.y, z = m.z;
       if (X_AXIS) {
         m.y = fmaf(R[1], z, R[0] * y);
@@ -228,8 +231,10 @@ struct Engine {
       free_evolve(m, pc.x, pc.y, r2.x, r1.x);
       float sx = m.x, sy = m.y;
       if constexpr (SM) {
+        smooth_demod(dm[jr], sx, sy);
         smooth_push(hx, hy, sx, sy);
-        smooth_out(sw, hx, hy, sc, sx, sy);
+        smooth_out(sw, hx, hy, scale_of(jr), sx, sy);
+        smooth_remod(dm[max(jr - kSmoothLag, 0)], sx, sy);
       }
       accumulate(sx, sy, v);
       free_evolve(m, pc.z, pc.w, r2.y, r1.y);
@@ -262,12 +267,12 @@ struct Engine {
           qd[q] = pd[jn];
           qv[q] = vl[vidx(jn)];
           ld_pulse(jn, qr[q]);
-          step(r1, r2, pc, v, R, scale_of(j + q));
+          step(r1, r2, pc, v, R, j + q);
         }
       }
 #pragma unroll
       for (int q = 0; q < kAhead; ++q)
-        step(q1[q], q2[q], qd[q], qv[q], qr[q], scale_of(j + q));
+        step(q1[q], q2[q], qd[q], qv[q], qr[q], j + q);
       j += kAhead;
     }
     for (; j < n; ++j) {
@@ -275,7 +280,7 @@ struct Engine {
       ld_pulse(j, R);
       const v2 r1 = p1[j], r2 = p2[j], v = vl[vidx(j)];
       const v4 pc = pd[j];
-      step(r1, r2, pc, v, R, scale_of(j));
+      step(r1, r2, pc, v, R, j);
     }
     if constexpr (SM) {
       // the last two outputs: zeros pushed after the last readout
@@ -285,7 +290,10 @@ struct Engine {
         float sx, sy;
         smooth_push(hx, hy, 0.f, 0.f);
         smooth_out(sw, hx, hy, sw.tail[t], sx, sy);
-        if (o >= 0) accumulate(sx, sy, vl[o]);
+        if (o >= 0) {
+          smooth_remod(dm[o], sx, sy);
+          accumulate(sx, sy, vl[o]);
+        }
       }
     }
     if (pdr) *pdr = dr;
@@ -729,7 +737,10 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.pa.n_tr = a.n_tr;
     e.pa.inversion = a.inversion;
     e.pa.x_axis = a.x_axis;
-    if constexpr (SM) e.sw = a.sm;
+    if constexpr (SM) {
+      e.sw = a.sm;
+      e.dm = a.demod;
+    }
     e.pa.memo_cap = a.memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
@@ -1052,6 +1063,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.inversion = t->inversion;
   a.x_axis = t->x_axis_pulses;
   a.sm = smooth_weights(t->smooth ? t->smooth : 3, n_tr);
+  a.demod = t->demod;
   for (int q = 0; q < 4; ++q) a.dims[q] = dims[q];
   a.vox = (const float2*)vox;
   a.ld_vox = ld_vox;

@@ -2,9 +2,11 @@
 against the oracle.
 
 Fingerprints: mrf_smooth_signals against the oracle's smoothing, FP32 vs FP64
-(a 3- or 5-term weighted sum: a few FP32 ulps). Dictionary side: every path
-that simulates entries of a smoothing sequence (K1 FP32 and BF16, CC map,
-BF16 re-scoring, ZOOM) against the oracle with the dictionary-parity bars:
+(a 3- or 5-term weighted sum between two complex rotations: a few FP32
+ulps), with and without a sequence's RF phases (the demodulated frame).
+Dictionary side: every path that simulates entries of a smoothing sequence
+(K1 FP32 and BF16, CC map, BF16 re-scoring, ZOOM) against the oracle with the
+dictionary-parity bars:
 unit-entry L2 error below 5e-6, |CC| within 1e-5, the oracle's index where
 its margin exceeds 1e-5. The oracle smooths its own copy of the fingerprints.
 """
@@ -50,20 +52,33 @@ def _small(taps):
     return dataclasses.replace(w, seq=dataclasses.replace(w.seq, smooth=taps))
 
 
+def _phase_seq(n, seed):
+    """A sequence whose RF phases are multiples of 90 degrees on even readouts
+    and arbitrary on odd ones (both demodulation paths)."""
+    rng = np.random.default_rng(seed)
+    s = I.make_sequence(n, seed)
+    ph = rng.choice([0.0, 90.0, 180.0, 270.0, -90.0], n)
+    ph[1::2] = rng.uniform(-180.0, 180.0, ph[1::2].shape)
+    return dataclasses.replace(s, phase_deg=ph)
+
+
 @pytest.mark.parametrize("taps", [3, 5])
 @pytest.mark.parametrize("n_tr", [1, 2, 3, 4, 5, 63, 64, 65, 130, 1000])
-def test_smooth_signals_matches_oracle(ctx, orc, taps, n_tr):
+@pytest.mark.parametrize("framed", [False, True])
+def test_smooth_signals_matches_oracle(ctx, orc, taps, n_tr, framed):
     from paper_1506_05393_amd import api
     rng = np.random.default_rng(n_tr * 10 + taps)
     x = (rng.standard_normal((7, n_tr)) + 1j * rng.standard_normal((7, n_tr))).astype(np.complex64)
-    ref = orc.smooth(x, taps)
+    seq = _phase_seq(1000, 3) if framed else None
+    sq = api.Sequence(ctx, seq) if framed else None
+    ref = orc.smooth(x, taps, seq)
     tol = 1e-6 * np.abs(x).max()
-    out = api.smooth_signals(ctx, to_dev(x), taps).cpu().numpy()
+    out = api.smooth_signals(ctx, to_dev(x), taps, seq=sq).cpu().numpy()
     assert np.abs(out - ref).max() < tol
     # in place, on rows of a wider buffer (row stride n_tr + 3)
     wide = to_dev(np.concatenate([x, np.full((7, 3), 9 + 9j, np.complex64)], axis=1))
     view = wide[:, :n_tr]
-    api.smooth_signals(ctx, view, taps, out=view)
+    api.smooth_signals(ctx, view, taps, out=view, seq=sq)
     w = wide.cpu().numpy()
     assert np.array_equal(w[:, :n_tr], out)
     assert np.all(w[:, n_tr:] == 9 + 9j)
@@ -78,6 +93,8 @@ def test_smooth_signals_copy_and_errors(ctx):
         api.smooth_signals(ctx, x, 4)
     with pytest.raises(Exception):  # rows that overlap without being the same rows
         api.smooth_signals(ctx, x[:, :9], 3, out=x.view(-1)[1:37].view(4, 9))
+    with pytest.raises(Exception):  # longer than the sequence
+        api.smooth_signals(ctx, x, 3, seq=api.Sequence(ctx, I.make_sequence(8, 1)))
 
 
 def test_sequence_rejects_other_lengths(ctx):
@@ -111,11 +128,14 @@ def test_smoothed_dictionary_f32_bf16(ctx, orc, taps):
 
 
 @pytest.mark.parametrize("n_tr", [1, 2, 3, 5, 53])
-def test_smoothed_dictionary_ragged(ctx, orc, n_tr):
+@pytest.mark.parametrize("phases", ["alternating", "general"])
+def test_smoothed_dictionary_ragged(ctx, orc, n_tr, phases):
     """Short sequences (both ends of the window cut), an entry range off the
-    block size, row padding and a B1 axis (per-lane pulses)."""
+    block size, row padding and a B1 axis (per-lane pulses); RF phases 0/180
+    or arbitrary (general pulses, rounded demodulation)."""
     from paper_1506_05393_amd import api
-    seq = dataclasses.replace(I.make_sequence(77, 5), smooth=5)
+    base = I.make_sequence(77, 5) if phases == "alternating" else _phase_seq(77, 5)
+    seq = dataclasses.replace(base, smooth=5)
     grid = I.make_grid([300.0, 800.0, 1500.0], [25.0, 60.0, 200.0], I.grid_arange(-30, 30, 3),
                        [0.85, 1.0, 1.15])
     sq = api.Sequence(ctx, seq)
@@ -138,7 +158,7 @@ def test_smoothed_signals_equal_smoothed_entries(ctx):
     ks = np.array([0, 5, 777, 4321, w.grid.size - 1])
     params = np.stack([np.array(w.grid.values(int(k)), np.float64) for k in ks])
     raw = api.simulate_signals(ctx, sq, to_dev(params))
-    sm = api.smooth_signals(ctx, raw, 3).cpu().numpy()
+    sm = api.smooth_signals(ctx, raw, 3, seq=sq).cpu().numpy()
     torch.cuda.synchronize()
     ent = _entries(d, w.grid.size)[ks]
     assert np.array_equal(sm.astype(np.complex128), ent)
@@ -147,10 +167,10 @@ def test_smoothed_signals_equal_smoothed_entries(ctx):
 def test_smoothed_cc_map(ctx, orc):
     from paper_1506_05393_amd import api
     w = _small(3)
-    V = orc.smooth(oracle_fingerprints(orc, w.seq, w.phantom, voxels=[0, 77, 200]), 3)
-    Vg = api.smooth_signals(ctx, to_dev(oracle_fingerprints(orc, w.seq, w.phantom,
-                                                            voxels=[0, 77, 200])), 3)
+    V = orc.smooth(oracle_fingerprints(orc, w.seq, w.phantom, voxels=[0, 77, 200]), 3, w.seq)
     sq = api.Sequence(ctx, w.seq)
+    Vg = api.smooth_signals(ctx, to_dev(oracle_fingerprints(orc, w.seq, w.phantom,
+                                                            voxels=[0, 77, 200])), 3, seq=sq)
     k0, cnt = 1000, 20000
     ref = orc.cc_map(w.seq, w.grid, V, k0=k0, count=cnt, threads=8)
     got = api.cc_map(ctx, sq, w.grid, Vg, entry_begin=k0, entry_count=cnt).cpu().numpy()
@@ -178,10 +198,10 @@ def test_smoothed_bruteforce_f32_and_bf16(ctx, orc, taps):
     from paper_1506_05393_amd import api
     w = _small(taps)
     V = oracle_fingerprints(orc, w.seq, w.phantom)
-    Vs = orc.smooth(V, taps)
+    Vs = orc.smooth(V, taps, w.seq)
     ref = orc.bruteforce(w.seq, w.grid, Vs, top_k=8, threads=8)
     sq = api.Sequence(ctx, w.seq)
-    Vg = api.smooth_signals(ctx, to_dev(V), taps)
+    Vg = api.smooth_signals(ctx, to_dev(V), taps, seq=sq)
     d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
     res = api.match_bruteforce(ctx, d, Vg, top_k=4)
     torch.cuda.synchronize()
@@ -201,11 +221,11 @@ def test_smoothed_zoom(ctx, orc, taps):
     from paper_1506_05393_amd import api
     w = _small(taps)
     V = oracle_fingerprints(orc, w.seq, w.phantom)
-    Vs = orc.smooth(V, taps)
+    Vs = orc.smooth(V, taps, w.seq)
     sched = orc.schedule_paper(w.seq, w.grid)
     ref = orc.zoom(w.seq, w.grid, sched, Vs, threads=8)
     sq = api.Sequence(ctx, w.seq)
-    Vg = api.smooth_signals(ctx, to_dev(V), taps)
+    Vg = api.smooth_signals(ctx, to_dev(V), taps, seq=sq)
     res = api.zoom_search(ctx, sq, w.grid, Vg, sched=sched)
     torch.cuda.synchronize()
     idx = res["idx"].cpu().numpy()
@@ -222,7 +242,8 @@ def test_smoothed_zoom(ctx, orc, taps):
     # wherever the paths differ, the GPU's CC is the CC of the smoothed entry it returns
     for v in np.flatnonzero(~agree)[:16]:
         t1, t2, df, b1 = w.grid.values(int(idx[v]))
-        dv = orc.smooth(orc.simulate(w.seq, float(t1), float(t2), float(df), float(b1)), taps)
+        dv = orc.smooth(orc.simulate(w.seq, float(t1), float(t2), float(df), float(b1)), taps,
+                        w.seq)
         assert abs(orc.cc(Vs[v], dv) - cc[v]) < CC_TOL
 
 
