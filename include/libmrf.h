@@ -49,7 +49,7 @@ enum {
   MRF_ERR_CANCELLED = 7
 };
 
-typedef enum { MRF_F32 = 0, MRF_BF16 = 1 } mrf_dtype;
+typedef enum { MRF_F32 = 0, MRF_BF16 = 1, MRF_F32_ROWS = 2 } mrf_dtype;
 
 const char* mrf_status_str(int status);
 const char* mrf_last_error(void);
@@ -120,6 +120,10 @@ int64_t mrf_grid_size(const mrf_grid* grid);
  *              element ((b*ld + e)*4 + q)*2 + {0: Re, 1: Im} of readout
  *              j = 4b + q, bf16 round-to-nearest-even; im must be NULL.
  *              n_tr must be a multiple of 4.
+ *   MRF_F32_ROWS: entry-major complex64 rows (the layout the resident-
+ *              dictionary ZOOM gathers from): re[(e*ld + j)*2 + {0: Re, 1: Im}],
+ *              j < n_tr; ld >= n_tr and even, re 16-byte aligned, im NULL.
+ *              (Brute-force matching does not take this layout.)
  * Values are the raw signal (M0 = 1) unless unit_norm = 1, in which case each
  * entry is divided by its norm (two passes). norm (device, FP64
  * [entry_count], or NULL) receives, for MRF_F32, the raw norm ||d||; for
@@ -310,6 +314,22 @@ int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* g
                     const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
                     int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                     mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
+
+/* MRF-ZOOM over a resident dictionary (Results: the MZfulldict variant, the
+ * fastest of the paper's timings): the same search as mrf_zoom_search, but
+ * each visited entry is read from `dict` instead of simulated. dict: an
+ * MRF_F32_ROWS dictionary of the whole grid (entry_base 0, n_entries = grid
+ * size, n_tr >= the n_tr searched, ld even), as mrf_simulate_dictionary
+ * writes it; its norm may be NULL (norms are computed from the rows). A
+ * group of lanes reads each entry's row together (coalesced 16-byte loads),
+ * so the search is bound by HBM reads of ~8 B per readout per visited entry
+ * instead of the simulation's ALU work. Outputs and errors as
+ * mrf_zoom_search, plus MRF_ERR_INVALID for a dictionary of another layout,
+ * another extent or a misaligned base. */
+int mrf_zoom_search_dict(mrf_context* ctx, const mrf_dict_view* dict, const mrf_grid* grid,
+                         const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                         int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
+                         mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
 
 /* As mrf_zoom_search, with each voxel's prior centre given as a flat grid
  * index (device int64 [n_vox], e.g. the idx output of mrf_match_bruteforce;

@@ -12,7 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmrf.so")
 
 MRF_OK = 0
-MRF_F32, MRF_BF16 = 0, 1
+MRF_F32, MRF_BF16, MRF_F32_ROWS = 0, 1, 2
 STATUS = {0: "MRF_OK", 1: "MRF_ERR_INVALID", 2: "MRF_ERR_OOM", 3: "MRF_ERR_DEVICE",
           4: "MRF_ERR_NOT_READY", 5: "MRF_ERR_REJECTED", 6: "MRF_ERR_UNSUPPORTED",
           7: "MRF_ERR_CANCELLED"}
@@ -141,6 +141,10 @@ _SIGS += [
      [C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     ("mrf_zoom_search", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
+      C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
+    ("mrf_zoom_search_dict", C.c_int,
+     [C.c_void_p, C.POINTER(DictView), C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
       C.c_void_p]),
     ("mrf_zoom_search_lattice", C.c_int,

@@ -103,6 +103,8 @@ class Dictionary:
 
     f32 : re, im float32 [n_tr, ld] (planar, time-major)
     bf16: packed bfloat16 blocks viewed as int16 [n_tr/4, ld, 4, 2]
+    f32rows: entry-major complex64 rows, re float32 [n_entries, ld, 2] (ld even
+          and >= n_tr; the layout the resident-dictionary ZOOM reads)
     norm: float64 [n_entries] raw norms (None when the entries are unit-norm)
     """
     dtype: str
@@ -116,7 +118,7 @@ class Dictionary:
 
     def view(self, n_tr: Optional[int] = None) -> L.DictView:
         n = self.n_tr if n_tr is None else int(n_tr)
-        return L.DictView(L.MRF_F32 if self.dtype == "f32" else L.MRF_BF16, n, self.n_entries,
+        return L.DictView(_DTYPES[self.dtype], n, self.n_entries,
                           self.ld, self.re.data_ptr(),
                           self.im.data_ptr() if self.im is not None else None,
                           self.norm.data_ptr() if self.norm is not None else None,
@@ -134,8 +136,16 @@ def _round_up(x: int, m: int) -> int:
     return (x + m - 1) // m * m
 
 
+_DTYPES = {"f32": L.MRF_F32, "bf16": L.MRF_BF16, "f32rows": L.MRF_F32_ROWS}
+
+
 def alloc_dictionary(n_tr: int, n_entries: int, dtype: str = "f32", device="cuda",
                      ld: Optional[int] = None, with_norm: bool = True) -> Dictionary:
+    if dtype == "f32rows":
+        ld = _round_up(n_tr, 2) if ld is None else int(ld)
+        re = torch.empty((max(n_entries, 1), ld, 2), dtype=torch.float32, device=device)
+        norm = torch.empty(n_entries, dtype=torch.float64, device=device) if with_norm else None
+        return Dictionary(dtype, n_tr, n_entries, ld, re, None, norm)
     ld = _round_up(max(n_entries, 1), 256) if ld is None else int(ld)
     if dtype == "f32":
         re = torch.empty((n_tr, ld), dtype=torch.float32, device=device)
@@ -163,7 +173,7 @@ def simulate_dictionary(ctx: Context, seq: Sequence, grid, n_tr: Optional[int] =
     d.entry_base = int(entry_begin)
     L.check(ctx._lib.mrf_simulate_dictionary(
         ctx.handle, seq.handle, g.ptr, n_tr, int(entry_begin), count,
-        L.MRF_F32 if dtype == "f32" else L.MRF_BF16, d.re.data_ptr(),
+        _DTYPES[d.dtype], d.re.data_ptr(),
         d.im.data_ptr() if d.im is not None else None, d.ld,
         d.norm.data_ptr() if d.norm is not None else None, int(bool(unit_norm)),
         _stream_ptr(stream)))
@@ -405,6 +415,36 @@ def zoom_search(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, sched: Opt
         r["_init"] = init
     L.check(ctx._lib.mrf_zoom_search(
         ctx.handle, seq.handle, g.ptr, C.byref(s), vox.data_ptr(), n_vox, vox.stride(0), n_tr,
+        init.data_ptr() if init is not None else None, _result_view(r), buf.data_ptr(),
+        buf.numel(), _stream_ptr(stream)))
+    return r
+
+
+def zoom_search_dict(ctx: Context, d: Dictionary, grid, vox: torch.Tensor, sched: dict,
+                     n_tr: Optional[int] = None, init: Optional[torch.Tensor] = None,
+                     workspace: Optional[Workspace] = None, out: Optional[dict] = None,
+                     stream=None) -> dict:
+    """MRF-ZOOM reading visited entries from a resident f32rows dictionary of
+    the whole grid (mrf_zoom_search_dict). Outputs as zoom_search."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda or vox.stride(1) != 1:
+        raise ValueError("vox must be a complex64 CUDA tensor with contiguous rows")
+    if d.dtype != "f32rows":
+        raise ValueError("the resident dictionary must be f32rows")
+    n_tr = d.n_tr if n_tr is None else int(n_tr)
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    s = schedule_from_dict(sched)
+    n_vox = vox.shape[0]
+    nb = C.c_size_t()
+    L.check(ctx._lib.mrf_zoom_workspace(ctx.handle, g.ptr, n_vox, n_tr, C.byref(nb)))
+    ws = workspace if workspace is not None else Workspace(ctx.device)
+    buf = ws.get(int(nb.value))
+    r = out if out is not None else _result_tensors(n_vox, ctx.device, with_nsim=True)
+    if init is not None:
+        init = init.to(device=ctx.device, dtype=torch.int32).contiguous()
+        r["_init"] = init
+    v = d.view()  # the stored readout count; the search uses the first n_tr
+    L.check(ctx._lib.mrf_zoom_search_dict(
+        ctx.handle, C.byref(v), g.ptr, C.byref(s), vox.data_ptr(), n_vox, vox.stride(0), n_tr,
         init.data_ptr() if init is not None else None, _result_view(r), buf.data_ptr(),
         buf.numel(), _stream_ptr(stream)))
     return r

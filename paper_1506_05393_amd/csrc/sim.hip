@@ -77,6 +77,7 @@ __device__ __forceinline__ void lds_barrier() {
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // Round-to-nearest-even to BF16, two values per instruction (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
@@ -137,7 +138,8 @@ struct Dots {
 };
 
 // One pass over all readouts for the thread's kQ entries. MODE 0 accumulates
-// the norm only, MODE 1 stores FP32 planes, MODE 2 stores BF16 blocks and
+// the norm only, MODE 1 stores FP32 planes, MODE 4 stores FP32 entry-major
+// rows (two readouts per 16-byte store), MODE 2 stores BF16 blocks and
 // also accumulates the norm of the stored (scaled, rounded) values into nb,
 // MODE 3 stores nothing and accumulates v conj(d) against the fingerprint
 // `vox` (one value per readout, the same for every thread) into dt.
@@ -170,6 +172,10 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
   // FP32 partial sums over (up to) four outputs, added into FP64
   float part[kQ], partb[kQ], pre[kQ], pim[kQ], pv = 0.f;
   uint32_t w[kQ][4];  // one BF16 block of four outputs
+  f32x2_t w4[kQ];     // MODE 4: the even output waiting for its odd neighbour
+  bool live[kQ];      // MODE 4: the entry exists (tail lanes recompute the last one)
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) live[q] = blk0 + tid + kThreads * q < a.count;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) part[q] = partb[q] = pre[q] = pim[q] = 0.f;
   auto flush = [&]() {
@@ -196,7 +202,16 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
     part[q] = fmaf(sy, sy, part[q]);
     const float ox = SCALED ? sx * scale[q] : sx;
     const float oy = SCALED ? sy * scale[q] : sy;
-    if (MODE == 1) {
+    if (MODE == 4) {
+      // row e = blk0 + tid + kThreads q; outputs 2p and 2p + 1 share one store
+      float2* row = (float2*)a.re + (blk0 + tid + kThreads * q) * a.ld;
+      if (o & 1) {
+        const f32x4_t v = {w4[q].x, w4[q].y, ox, oy};
+        if (live[q]) __builtin_nontemporal_store(v, (f32x4_t*)(row + (o - 1)));
+      } else {
+        w4[q] = f32x2_t{ox, oy};
+      }
+    } else if (MODE == 1) {
       const rsrc_t wr = make_rsrc(a.re + (int64_t)o * a.ld + blk0, nrec);
       const rsrc_t wi = make_rsrc(a.im + (int64_t)o * a.ld + blk0, nrec);
       store1(ox, wr, 4u * (tid + kThreads * q));
@@ -295,7 +310,7 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
   }
   if (SM) {
     // the last two outputs (BF16 entries have n_tr % 4 == 0: they fill
-    // positions 2 and 3 of the last block)
+    // positions 2 and 3 of the last block; MODE 4 takes the parity of o)
 #pragma unroll
     for (int t = 0; t < kSmoothLag; ++t) {
       const int32_t o = n_tr - kSmoothLag + t;
@@ -315,6 +330,14 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       }
     }
     flush();
+  }
+  if (MODE == 4 && (n_tr & 1)) {
+    // an odd readout count leaves the last output without a partner
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      float2* row = (float2*)a.re + (blk0 + tid + kThreads * q) * a.ld;
+      if (live[q]) __builtin_nontemporal_store(w4[q], (f32x2_t*)(row + (n_tr - 1)));
+    }
   }
 }
 
@@ -573,6 +596,8 @@ int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count
   ProfScope prof(ctx, "k_sim_dict", stream);
   if (dtype == MRF_F32)
     launch_sim_mode<1>(a, t, blocks, stream);
+  else if (dtype == MRF_F32_ROWS)
+    launch_sim_mode<4>(a, t, blocks, stream);
   else
     launch_sim_mode<2>(a, t, blocks, stream);
   MRF_HIP(hipGetLastError());
@@ -608,16 +633,25 @@ extern "C" int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq
   int rc = check_grid(grid);
   if (rc) return rc;
   MRF_CHECK_ARG(n_tr >= 1 && n_tr <= seq->n, "n_tr %d must be in [1, %d]", n_tr, seq->n);
-  MRF_CHECK_ARG(dtype == MRF_F32 || dtype == MRF_BF16, "unknown dtype %d", (int)dtype);
+  MRF_CHECK_ARG(dtype == MRF_F32 || dtype == MRF_BF16 || dtype == MRF_F32_ROWS,
+                "unknown dtype %d", (int)dtype);
   const int64_t E = grid_size_checked(grid);
   MRF_CHECK_ARG(entry_begin >= 0 && entry_count >= 0 && entry_begin + entry_count <= E,
                 "entry range [%lld, %lld) outside the grid of %lld entries",
                 (long long)entry_begin, (long long)(entry_begin + entry_count), (long long)E);
-  MRF_CHECK_ARG(ld >= entry_count, "ld (%lld) must be >= entry_count (%lld)", (long long)ld,
-                (long long)entry_count);
+  if (dtype == MRF_F32_ROWS) {
+    MRF_CHECK_ARG(ld >= n_tr && ld % 2 == 0, "entry-major rows need an even ld >= n_tr (got %lld)",
+                  (long long)ld);
+    MRF_CHECK_ARG(entry_count == 0 || re, "re must not be NULL");
+    MRF_CHECK_ARG(im == nullptr, "im must be NULL for entry-major rows");
+    MRF_CHECK_ARG(((uintptr_t)re & 15) == 0, "entry-major rows must be 16-byte aligned");
+  } else {
+    MRF_CHECK_ARG(ld >= entry_count, "ld (%lld) must be >= entry_count (%lld)", (long long)ld,
+                  (long long)entry_count);
+  }
   if (dtype == MRF_F32) {
     MRF_CHECK_ARG(entry_count == 0 || (re && im), "re and im must not be NULL");
-  } else {
+  } else if (dtype == MRF_BF16) {
     MRF_CHECK_ARG(entry_count == 0 || re, "re must not be NULL");
     MRF_CHECK_ARG(im == nullptr, "im must be NULL for the packed BF16 layout");
     MRF_CHECK_ARG(n_tr % 4 == 0, "BF16 dictionaries need n_tr %% 4 == 0 (got %d)", n_tr);

@@ -53,6 +53,16 @@ struct ZoomArgs {
   const mrf_zoom_schedule* sch;  // device copy (workspace)
   SmoothW sm;  // temporal smoothing of the entries (SM kernels)
   const float2* demod;  // [n_tr] (cos, sin) of the RF phases (SM kernels)
+  // resident dictionary (GA kernels): entry k's readouts 2t, 2t + 1 at
+  // dict[k * dict_ld4 + t], complex64 entry-major rows
+  const float4* dict;
+  int64_t dict_ld4;
+};
+
+// A resident entry-major dictionary, as the gathering engine reads it.
+struct DictRows {
+  const float4* base;
+  int64_t ld4;
 };
 
 __device__ __forceinline__ int32_t round_half_away(double x) {
@@ -118,7 +128,7 @@ struct EngineParams {
   int32_t dims[4];
 };
 
-template <int G, bool SM>
+template <int G, bool SM, bool GA>
 struct Engine {
   EngineParams pa;
 
@@ -142,6 +152,7 @@ struct Engine {
   // smoothing weights (SM only; the plain kernel carries no copy)
   std::conditional_t<SM, SmoothW, char> sw;
   std::conditional_t<SM, const float2*, char> dm;  // (cos, sin) of the RF phases
+  std::conditional_t<GA, DictRows, char> dict;      // resident dictionary (GA)
 
   __device__ int64_t key(const int32_t* i) const {
     return (((int64_t)i[0] * pa.dims[1] + i[1]) * pa.dims[2] + i[2]) * pa.dims[3] + i[3];
@@ -302,6 +313,57 @@ struct Engine {
     if (!(n2 > 0.0)) return 0.0f;
     return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
   }
+  // GA: CC of resident entry k against the voxel, read by the whole group:
+  // lane l takes readout pairs l, l + G, ... of the entry's row (so each load
+  // instruction covers G x 16 contiguous bytes of one row), then the partial
+  // sums are reduced over the group. Every lane returns the result.
+  __device__ float gather_cc(int64_t k, float* pdr = nullptr, float* pdi = nullptr,
+                             double* pn2 = nullptr) const {
+    float dr = 0.0f, di = 0.0f;
+    double n2 = 0.0;
+    if constexpr (GA) {
+      typedef float v4 __attribute__((ext_vector_type(4)));
+      typedef float v2 __attribute__((ext_vector_type(2)));
+      typedef const __attribute__((address_space(1))) v4 gf4;
+      typedef const __attribute__((address_space(1))) v2 gf2;
+      const int32_t n = pa.n_tr, nq = (n + 1) >> 1;
+      gf4* row = (gf4*)(dict.base + k * dict.ld4);
+      gf2* vl = (gf2*)vx;
+#pragma unroll 4
+      for (int32_t t = lane; t < nq; t += G) {
+        v4 d = row[t];
+        const v2 v0 = vl[2 * t];
+        v2 v1 = {0.0f, 0.0f};
+        if (2 * t + 1 < n) {
+          v1 = vl[2 * t + 1];
+        } else {
+          d.z = 0.0f;  // an odd readout count: the row's padding
+          d.w = 0.0f;
+        }
+        const float vr0 = v0.x * vinv, vi0 = v0.y * vinv;
+        const float vr1 = v1.x * vinv, vi1 = v1.y * vinv;
+        dr = fmaf(vr0, d.x, fmaf(vi0, d.y, dr));
+        di = fmaf(vi0, d.x, fmaf(-vr0, d.y, di));
+        dr = fmaf(vr1, d.z, fmaf(vi1, d.w, dr));
+        di = fmaf(vi1, d.z, fmaf(-vr1, d.w, di));
+        n2 = fma((double)d.x, (double)d.x, n2);
+        n2 = fma((double)d.y, (double)d.y, n2);
+        n2 = fma((double)d.z, (double)d.z, n2);
+        n2 = fma((double)d.w, (double)d.w, n2);
+      }
+      for (int o = G / 2; o > 0; o >>= 1) {
+        dr += __shfl_xor(dr, o, G);
+        di += __shfl_xor(di, o, G);
+        n2 += __shfl_xor(n2, o, G);
+      }
+    }
+    if (pdr) *pdr = dr;
+    if (pdi) *pdi = di;
+    if (pn2) *pn2 = n2;
+    if (!(n2 > 0.0)) return 0.0f;
+    return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
+  }
+
   __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
                                double* pn2 = nullptr) const {
     if (pa.dims[3] > 1)
@@ -344,7 +406,18 @@ struct Engine {
         s = (s + 1) & (cap - 1);
       }
     }
-    if (need) val = simulate_cc(i);
+    if constexpr (GA) {
+      // the group reads each needed entry together, one after another
+      uint64_t nm = grp_ballot<G>(need, gbase);
+      while (nm) {
+        const int src = __ffsll((unsigned long long)nm) - 1;
+        nm &= nm - 1;
+        const float cv = gather_cc(__shfl(k, src, G));
+        if (lane == src) val = cv;
+      }
+    } else {
+      if (need) val = simulate_cc(i);
+    }
     uint64_t m = grp_ballot<G>(need, gbase);
     n_sim += __popcll(m);
     while (m) {
@@ -665,7 +738,7 @@ __host__ __device__ inline size_t zoom_group_lds() {
 // One wave per block, 64 / G voxels per wave: each group of G lanes runs its
 // own voxel's stage machine and pulls its own voxels from the queue, so the
 // lanes that a decision leaves idle in one group work for the others.
-template <int G, bool SM>
+template <int G, bool SM, bool GA>
 __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   constexpr int NG = 64 / G;
   extern __shared__ __align__(16) unsigned char sm[];
@@ -728,7 +801,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
     ++serial;
 
-    Engine<G, SM> e;
+    Engine<G, SM, GA> e;
     e.pa.t1T = a.t1T;
     e.pa.t1ti = a.t1ti;
     e.pa.t2T = a.t2T;
@@ -741,6 +814,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       e.sw = a.sm;
       e.dm = a.demod;
     }
+    if constexpr (GA) e.dict = DictRows{a.dict, a.dict_ld4};
     e.pa.memo_cap = a.memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
@@ -811,7 +885,11 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     // proton density of the found entry: <v, d> / ||d||^2
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
-    if (glane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
+    if constexpr (GA) {
+      if (a.pd_re || a.pd_im) e.gather_cc(bk, &dr, &di, &n2);
+    } else {
+      if (glane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
+    }
     if (glane == 0) {
       a.idx[v] = bk;
       if (a.cc) a.cc[v] = bv;
@@ -827,17 +905,17 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-template <bool SM>
+template <bool SM, bool GA>
 static void launch_zoom_groups(int group, int blocks, size_t lds, hipStream_t st,
                                const ZoomArgs& a) {
   if (group == 8)
-    hipLaunchKernelGGL((k_zoom<8, SM>), dim3(blocks), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((k_zoom<8, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
   else if (group == 16)
-    hipLaunchKernelGGL((k_zoom<16, SM>), dim3(blocks), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((k_zoom<16, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
   else if (group == 32)
-    hipLaunchKernelGGL((k_zoom<32, SM>), dim3(blocks), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((k_zoom<32, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
   else
-    hipLaunchKernelGGL((k_zoom<64, SM>), dim3(blocks), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((k_zoom<64, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
 }
 
 static int32_t h_round_half_away(double x) {
@@ -1028,19 +1106,35 @@ extern "C" int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_
   return MRF_OK;
 }
 
+// dict == NULL: candidates are simulated (seq required); otherwise they are
+// read from the resident entry-major dictionary (seq unused).
 static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
                        const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
                        int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                        const int64_t* init_flat, mrf_result_view out, void* workspace,
-                       size_t ws_bytes, void* stream, const int32_t* lattice = nullptr) {
-  MRF_CHECK_ARG(ctx && seq, "context and sequence must not be NULL");
+                       size_t ws_bytes, void* stream, const int32_t* lattice = nullptr,
+                       const mrf_dict_view* dict = nullptr) {
+  MRF_CHECK_ARG(ctx && (seq || dict), "context and sequence (or dictionary) must not be NULL");
   int rc = check_grid(grid);
   if (rc) return rc;
   const int32_t dims[4] = {grid->t1_ms.n, grid->t2_ms.n, grid->df_hz.n,
                            grid->b1.n > 0 ? grid->b1.n : 1};
   rc = check_schedule(sched, dims);
   if (rc) return rc;
-  MRF_CHECK_ARG(n_tr >= 1 && n_tr <= seq->n, "n_tr %d must be in [1, %d]", n_tr, seq->n);
+  if (dict) {
+    MRF_CHECK_ARG(dict->dtype == MRF_F32_ROWS,
+                  "the resident dictionary must be MRF_F32_ROWS (entry-major rows)");
+    MRF_CHECK_ARG(dict->entry_base == 0 && dict->n_entries == grid_size_checked(grid),
+                  "the resident dictionary must hold the whole grid (entries 0..%lld)",
+                  (long long)grid_size_checked(grid) - 1);
+    MRF_CHECK_ARG(n_tr >= 1 && n_tr <= dict->n_tr, "n_tr %d must be in [1, %d]", n_tr,
+                  dict->n_tr);
+    MRF_CHECK_ARG(dict->ld >= dict->n_tr && dict->ld % 2 == 0, "dictionary ld must be even and >= n_tr");
+    MRF_CHECK_ARG(dict->re && ((uintptr_t)dict->re & 15) == 0,
+                  "dictionary rows must be a 16-byte aligned device pointer");
+  } else {
+    MRF_CHECK_ARG(n_tr >= 1 && n_tr <= seq->n, "n_tr %d must be in [1, %d]", n_tr, seq->n);
+  }
   MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
   if (n_vox == 0) return MRF_OK;
   MRF_CHECK_ARG(vox != nullptr && out.idx != nullptr, "vox and out.idx must not be NULL");
@@ -1049,9 +1143,12 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   MRF_CHECK_ARG(workspace != nullptr && ws_bytes >= plan.total,
                 "workspace too small (%zu < %zu bytes)", ws_bytes, plan.total);
   hipStream_t st = (hipStream_t)stream;
-  const Tables* t = nullptr;
-  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, st, &t);
-  if (rc) return rc;
+  static const Tables no_tables;
+  const Tables* t = &no_tables;
+  if (!dict) {
+    rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, st, &t);
+    if (rc) return rc;
+  }
 
   ZoomArgs a;
   a.t1T = t->t1T;
@@ -1064,6 +1161,8 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.x_axis = t->x_axis_pulses;
   a.sm = smooth_weights(t->smooth ? t->smooth : 3, n_tr);
   a.demod = t->demod;
+  a.dict = dict ? (const float4*)dict->re : nullptr;
+  a.dict_ld4 = dict ? dict->ld / 2 : 0;
   for (int q = 0; q < 4; ++q) a.dims[q] = dims[q];
   a.vox = (const float2*)vox;
   a.ld_vox = ld_vox;
@@ -1094,10 +1193,12 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   MRF_HIP(hipGetLastError());
   auto launch = [&]() {
     ProfScope prof(ctx, "k_zoom", st);
-    if (t->smooth)
-      launch_zoom_groups<true>(plan.group, blocks, lds, st, a);
+    if (dict)
+      launch_zoom_groups<false, true>(plan.group, blocks, lds, st, a);
+    else if (t->smooth)
+      launch_zoom_groups<true, false>(plan.group, blocks, lds, st, a);
     else
-      launch_zoom_groups<false>(plan.group, blocks, lds, st, a);
+      launch_zoom_groups<false, false>(plan.group, blocks, lds, st, a);
   };
   if (!lattice) {
     launch();
@@ -1126,6 +1227,16 @@ extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const 
                                void* stream) {
   return zoom_search(ctx, seq, grid, sched, vox, n_vox, ld_vox, n_tr, init_idx, nullptr, out,
                      workspace, ws_bytes, stream);
+}
+
+extern "C" int mrf_zoom_search_dict(mrf_context* ctx, const mrf_dict_view* dict,
+                                    const mrf_grid* grid, const mrf_zoom_schedule* sched,
+                                    const void* vox, int32_t n_vox, int64_t ld_vox, int32_t n_tr,
+                                    const int32_t* init_idx, mrf_result_view out,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  MRF_CHECK_ARG(dict != nullptr, "dict must not be NULL");
+  return zoom_search(ctx, nullptr, grid, sched, vox, n_vox, ld_vox, n_tr, init_idx, nullptr, out,
+                     workspace, ws_bytes, stream, nullptr, dict);
 }
 
 extern "C" int mrf_zoom_search_from(mrf_context* ctx, const mrf_sequence* seq,
