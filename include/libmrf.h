@@ -122,8 +122,11 @@ int64_t mrf_grid_size(const mrf_grid* grid);
  *              n_tr must be a multiple of 4.
  *   MRF_F32_ROWS: entry-major complex64 rows (the layout the resident-
  *              dictionary ZOOM gathers from): re[(e*ld + j)*2 + {0: Re, 1: Im}],
- *              j < n_tr; ld >= n_tr and even, re 16-byte aligned, im NULL.
- *              (Brute-force matching does not take this layout.)
+ *              j < n_tr; ld >= n_tr and even, re 16-byte aligned, im NULL;
+ *              rows start on 128-byte lines when ld is a multiple of 16 and
+ *              re is 128-byte aligned (each entry's readouts are written 16
+ *              at a time, one line per burst). (Brute-force matching does
+ *              not take this layout.)
  * Values are the raw signal (M0 = 1) unless unit_norm = 1, in which case each
  * entry is divided by its norm (two passes). norm (device, FP64
  * [entry_count], or NULL) receives, for MRF_F32, the raw norm ||d||; for

@@ -142,7 +142,7 @@ _DTYPES = {"f32": L.MRF_F32, "bf16": L.MRF_BF16, "f32rows": L.MRF_F32_ROWS}
 def alloc_dictionary(n_tr: int, n_entries: int, dtype: str = "f32", device="cuda",
                      ld: Optional[int] = None, with_norm: bool = True) -> Dictionary:
     if dtype == "f32rows":
-        ld = _round_up(n_tr, 2) if ld is None else int(ld)
+        ld = _round_up(n_tr, 16) if ld is None else int(ld)  # 128-byte aligned rows
         re = torch.empty((max(n_entries, 1), ld, 2), dtype=torch.float32, device=device)
         norm = torch.empty(n_entries, dtype=torch.float64, device=device) if with_norm else None
         return Dictionary(dtype, n_tr, n_entries, ld, re, None, norm)

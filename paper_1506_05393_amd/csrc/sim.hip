@@ -34,8 +34,11 @@ constexpr int kThreads = 512;
 constexpr int kQ = 2;                              // entries per thread
 constexpr int kBlockEntries = kThreads * kQ;
 constexpr int kChunk = 8;                          // readouts per staged df chunk
+constexpr int kChunkRows = 16;                     // MODE 4: one 128-byte line per entry
 constexpr int kLdsMaxN3 = 128;                     // longest df axis staged through LDS
-constexpr int kPrefetch = kChunk * kLdsMaxN3 / kThreads;  // float4 per thread per chunk
+// readouts per chunk: MODE 4 stages 16 outputs per entry (a full line of its row)
+template <int MODE>
+constexpr int chunk_of() { return MODE == 4 ? kChunkRows : kChunk; }
 constexpr int kRsrcWord3 = 0x00020000;             // raw 32-bit buffer format
 
 // pulse kinds: general 3x3 or x-axis rotation, one matrix per wavefront
@@ -154,9 +157,11 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
                                          const float (&scale)[kQ], double (&n2)[kQ],
                                          double (&nb)[kQ], const float2* __restrict__ vox,
                                          Dots& dt) {
+  constexpr int CH = chunk_of<MODE>();
+  constexpr int kPrefetch = CH * kLdsMaxN3 / kThreads;  // float4 per thread per chunk
   const uint32_t tid = threadIdx.x;
   const int32_t n_tr = a.n_tr, n3 = a.n3;
-  const int32_t per = kChunk * n3;  // staged float4 per chunk
+  const int32_t per = CH * n3;  // staged float4 per chunk
   Spin m[kQ];
   float hx[kQ][kSmoothLen], hy[kQ][kSmoothLen];
 #pragma unroll
@@ -172,7 +177,8 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
   // FP32 partial sums over (up to) four outputs, added into FP64
   float part[kQ], partb[kQ], pre[kQ], pim[kQ], pv = 0.f;
   uint32_t w[kQ][4];  // one BF16 block of four outputs
-  f32x2_t w4[kQ];     // MODE 4: the even output waiting for its odd neighbour
+  // MODE 4: 16 outputs of each entry, stored as one 128-byte burst of its row
+  f32x4_t w16[kQ][kChunkRows / 2];
   bool live[kQ];      // MODE 4: the entry exists (tail lanes recompute the last one)
 #pragma unroll
   for (int q = 0; q < kQ; ++q) live[q] = blk0 + tid + kThreads * q < a.count;
@@ -195,22 +201,46 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       pv = 0.f;
     }
   };
-  // output sample o of entry q (ol = o & 3, a compile-time constant at every
-  // call): norm, store or fingerprint product
+  // MODE 4: outputs [o0, o0 + count) of the staging buffer to the entry's row
+  auto store_rows = [&](int q, int32_t o0, int32_t count) {
+    float2* row = (float2*)a.re + (blk0 + tid + kThreads * q) * a.ld + o0;
+#pragma unroll
+    for (int p = 0; p < kChunkRows / 2; ++p) {
+      if (!live[q]) break;
+      if (2 * p + 1 < count) {
+        *(f32x4_t*)(row + 2 * p) = w16[q][p];
+      } else if (2 * p < count) {
+        *(f32x2_t*)(row + 2 * p) = f32x2_t{w16[q][p].x, w16[q][p].y};
+      }
+    }
+  };
+  // output sample o of entry q (ol = o & (CH - 1), a compile-time constant in
+  // the readout loop): norm, store or fingerprint product
   auto emit = [&](int q, int ol, int32_t o, float sx, float sy, float2 vo) {
     part[q] = fmaf(sx, sx, part[q]);
     part[q] = fmaf(sy, sy, part[q]);
     const float ox = SCALED ? sx * scale[q] : sx;
     const float oy = SCALED ? sy * scale[q] : sy;
-    if (MODE == 4) {
-      // row e = blk0 + tid + kThreads q; outputs 2p and 2p + 1 share one store
+    if (MODE == 4 && ol < 0) {
+      // the two outputs after the last readout (smoothing): stored directly
       float2* row = (float2*)a.re + (blk0 + tid + kThreads * q) * a.ld;
-      if (o & 1) {
-        const f32x4_t v = {w4[q].x, w4[q].y, ox, oy};
-        if (live[q]) __builtin_nontemporal_store(v, (f32x4_t*)(row + (o - 1)));
-      } else {
-        w4[q] = f32x2_t{ox, oy};
+      if (live[q]) *(f32x2_t*)(row + o) = f32x2_t{ox, oy};
+    } else if (MODE == 4) {
+      // staged at position ol (known at compile time); a full group of 16
+      // goes out as one burst
+#pragma unroll
+      for (int p = 0; p < kChunkRows / 2; ++p) {
+        if (p == (ol >> 1)) {
+          if (ol & 1) {
+            w16[q][p].z = ox;
+            w16[q][p].w = oy;
+          } else {
+            w16[q][p].x = ox;
+            w16[q][p].y = oy;
+          }
+        }
       }
+      if (ol == kChunkRows - 1) store_rows(q, o - (kChunkRows - 1), kChunkRows);
     } else if (MODE == 1) {
       const rsrc_t wr = make_rsrc(a.re + (int64_t)o * a.ld + blk0, nrec);
       const rsrc_t wi = make_rsrc(a.im + (int64_t)o * a.ld + blk0, nrec);
@@ -218,11 +248,11 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       store1(oy, wi, 4u * (tid + kThreads * q));
     } else if (MODE == 2) {
       const uint32_t v = pack_bf16x2(ox, oy);
-      w[q][ol] = v;
+      w[q][ol & 3] = v;
       // |stored value|^2: BF16 products are exact in FP32 (v_dot2_f32_bf16)
       const bf16x2_t b = __builtin_bit_cast(bf16x2_t, v);
       partb[q] = __builtin_amdgcn_fdot2_f32_bf16(b, b, partb[q], false);
-      if (ol == 3) {
+      if ((ol & 3) == 3) {
         const rsrc_t wr = make_rsrc(a.packed + (int64_t)(o >> 2) * a.ld + blk0, nrec);
         store4(w[q], wr, 16u * (tid + kThreads * q));
       }
@@ -240,27 +270,27 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       if ((int32_t)(tid + kThreads * p) < per) sdf[tid + kThreads * p] = pf[p];
     lds_barrier();
   }
-  const int32_t nch = (n_tr + kChunk - 1) / kChunk;
+  const int32_t nch = (n_tr + CH - 1) / CH;
   for (int32_t c = 0; c < nch; ++c) {
-    const int32_t j0 = c * kChunk;
+    const int32_t j0 = c * CH;
     const float4* sd = sdf + (c & 1) * per;
     if (DF_LDS && c + 1 < nch) {
       // rows j0+8.. of the step-major table are contiguous. The whole offset
       // goes in the vector operand, which the buffer range check covers:
       // reads past the table end return zero and are never used.
-      const uint32_t row = (uint32_t)(j0 + kChunk) * (uint32_t)n3 * 16u;
+      const uint32_t row = (uint32_t)(j0 + CH) * (uint32_t)n3 * 16u;
 #pragma unroll
       for (int p = 0; p < kPrefetch; ++p)
         pf[p] = load4(rds, row + 16u * (tid + kThreads * p), 0);
     }
 #pragma unroll
-    for (int jj = 0; jj < kChunk; ++jj) {
+    for (int jj = 0; jj < CH; ++jj) {
       const int32_t j = j0 + jj;
       if (j < n_tr) {
-        // the output of this readout (j0 is a multiple of 4, so o & 3 is
-        // known at compile time)
+        // the output of this readout (j0 is a multiple of CH, so o & (CH - 1)
+        // is known at compile time)
         const int32_t o = SM ? j - kSmoothLag : j;
-        const int ol = SM ? ((jj - kSmoothLag) & 3) : (jj & 3);
+        const int ol = SM ? ((jj - kSmoothLag) & (CH - 1)) : (jj & (CH - 1));
         const bool out = !SM || o >= 0;
         float sc = 1.f;
         float2 dmj = make_float2(1.f, 0.f), dmo = make_float2(1.f, 0.f);
@@ -310,7 +340,7 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
   }
   if (SM) {
     // the last two outputs (BF16 entries have n_tr % 4 == 0: they fill
-    // positions 2 and 3 of the last block; MODE 4 takes the parity of o)
+    // positions 2 and 3 of the last block; MODE 4 stores them directly)
 #pragma unroll
     for (int t = 0; t < kSmoothLag; ++t) {
       const int32_t o = n_tr - kSmoothLag + t;
@@ -326,17 +356,19 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
         smooth_push(hx[q], hy[q], 0.f, 0.f);
         smooth_out(a.sm, hx[q], hy[q], a.sm.tail[t], sx, sy);
         smooth_remod(dmo, sx, sy);
-        if (o >= 0) emit(q, 2 + t, o, sx, sy, vo);
+        if (o >= 0) emit(q, MODE == 4 ? -1 : 2 + t, o, sx, sy, vo);
       }
     }
     flush();
   }
-  if (MODE == 4 && (n_tr & 1)) {
-    // an odd readout count leaves the last output without a partner
+  if (MODE == 4) {
+    // the staged outputs after the last full group of 16 (with smoothing the
+    // readout loop stages outputs up to n_tr - 3)
+    const int32_t end = SM ? max(n_tr - kSmoothLag, 0) : n_tr;
+    const int32_t r = end & (kChunkRows - 1);
+    if (r) {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      float2* row = (float2*)a.re + (blk0 + tid + kThreads * q) * a.ld;
-      if (live[q]) __builtin_nontemporal_store(w4[q], (f32x2_t*)(row + (n_tr - 1)));
+      for (int q = 0; q < kQ; ++q) store_rows(q, end - r, r);
     }
   }
 }
@@ -413,7 +445,7 @@ template <int MODE, int PK, bool SM>
 static void launch_sim_smooth(const SimArgs& a, const Tables& t, bool df_lds, int64_t blocks,
                               hipStream_t stream, const float2* vox) {
   const dim3 g((unsigned)blocks), b(kThreads);
-  const size_t lds = df_lds ? 2 * sizeof(float4) * kChunk * (size_t)a.n3 : 0;
+  const size_t lds = df_lds ? 2 * sizeof(float4) * chunk_of<MODE>() * (size_t)a.n3 : 0;
   if (df_lds)
     hipLaunchKernelGGL((k_sim_dict<MODE, PK, true, SM>), g, b, lds, stream, a, t.t1, t.t2, t.df,
                        t.rf, t.t1ti, vox);
