@@ -313,55 +313,83 @@ struct Engine {
     if (!(n2 > 0.0)) return 0.0f;
     return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
   }
-  // GA: CC of resident entry k against the voxel, read by the whole group:
-  // lane l takes readout pairs l, l + G, ... of the entry's row (so each load
-  // instruction covers G x 16 contiguous bytes of one row), then the partial
-  // sums are reduced over the group. Every lane returns the result.
-  __device__ float gather_cc(int64_t k, float* pdr = nullptr, float* pdi = nullptr,
-                             double* pn2 = nullptr) const {
-    float dr = 0.0f, di = 0.0f;
-    double n2 = 0.0;
+  // GA: CC of up to kGather resident entries against the voxel, read by the
+  // whole group: lane l takes readout pairs l, l + G, ... of every entry's
+  // row (each load instruction covers G x 16 contiguous bytes of a row) and
+  // of the voxel (shared by the entries), then the partial sums are reduced
+  // over the group. Entries at or beyond `cnt` are skipped. Every lane
+  // returns every result.
+  static constexpr int kGather = 4;
+  __device__ void gather_cc(const int64_t (&ks)[kGather], int cnt, float (&cv)[kGather],
+                            float* pdr = nullptr, float* pdi = nullptr,
+                            double* pn2 = nullptr) const {
+    float dr[kGather], di[kGather];
+    double n2[kGather];
+#pragma unroll
+    for (int e = 0; e < kGather; ++e) {
+      dr[e] = di[e] = 0.0f;
+      n2[e] = 0.0;
+    }
     if constexpr (GA) {
       typedef float v4 __attribute__((ext_vector_type(4)));
       typedef float v2 __attribute__((ext_vector_type(2)));
       typedef const __attribute__((address_space(1))) v4 gf4;
       typedef const __attribute__((address_space(1))) v2 gf2;
       const int32_t n = pa.n_tr, nq = (n + 1) >> 1;
-      gf4* row = (gf4*)(dict.base + k * dict.ld4);
+      gf4* row[kGather];
+#pragma unroll
+      for (int e = 0; e < kGather; ++e) row[e] = (gf4*)(dict.base + ks[e] * dict.ld4);
       gf2* vl = (gf2*)vx;
-#pragma unroll 4
+#pragma unroll 2
       for (int32_t t = lane; t < nq; t += G) {
-        v4 d = row[t];
+        v4 d[kGather];
+#pragma unroll
+        for (int e = 0; e < kGather; ++e)
+          if (e < cnt) d[e] = row[e][t];
         const v2 v0 = vl[2 * t];
+        const bool pair = 2 * t + 1 < n;  // an odd readout count: the row's padding
         v2 v1 = {0.0f, 0.0f};
-        if (2 * t + 1 < n) {
-          v1 = vl[2 * t + 1];
-        } else {
-          d.z = 0.0f;  // an odd readout count: the row's padding
-          d.w = 0.0f;
-        }
+        if (pair) v1 = vl[2 * t + 1];
         const float vr0 = v0.x * vinv, vi0 = v0.y * vinv;
         const float vr1 = v1.x * vinv, vi1 = v1.y * vinv;
-        dr = fmaf(vr0, d.x, fmaf(vi0, d.y, dr));
-        di = fmaf(vi0, d.x, fmaf(-vr0, d.y, di));
-        dr = fmaf(vr1, d.z, fmaf(vi1, d.w, dr));
-        di = fmaf(vi1, d.z, fmaf(-vr1, d.w, di));
-        n2 = fma((double)d.x, (double)d.x, n2);
-        n2 = fma((double)d.y, (double)d.y, n2);
-        n2 = fma((double)d.z, (double)d.z, n2);
-        n2 = fma((double)d.w, (double)d.w, n2);
+#pragma unroll
+        for (int e = 0; e < kGather; ++e) {
+          if (e < cnt) {
+            v4 x = d[e];
+            if (!pair) {
+              x.z = 0.0f;
+              x.w = 0.0f;
+            }
+            dr[e] = fmaf(vr0, x.x, fmaf(vi0, x.y, dr[e]));
+            di[e] = fmaf(vi0, x.x, fmaf(-vr0, x.y, di[e]));
+            dr[e] = fmaf(vr1, x.z, fmaf(vi1, x.w, dr[e]));
+            di[e] = fmaf(vi1, x.z, fmaf(-vr1, x.w, di[e]));
+            n2[e] = fma((double)x.x, (double)x.x, n2[e]);
+            n2[e] = fma((double)x.y, (double)x.y, n2[e]);
+            n2[e] = fma((double)x.z, (double)x.z, n2[e]);
+            n2[e] = fma((double)x.w, (double)x.w, n2[e]);
+          }
+        }
       }
-      for (int o = G / 2; o > 0; o >>= 1) {
-        dr += __shfl_xor(dr, o, G);
-        di += __shfl_xor(di, o, G);
-        n2 += __shfl_xor(n2, o, G);
+#pragma unroll
+      for (int e = 0; e < kGather; ++e) {
+        if (e < cnt) {
+          for (int o = G / 2; o > 0; o >>= 1) {
+            dr[e] += __shfl_xor(dr[e], o, G);
+            di[e] += __shfl_xor(di[e], o, G);
+            n2[e] += __shfl_xor(n2[e], o, G);
+          }
+        }
       }
     }
-    if (pdr) *pdr = dr;
-    if (pdi) *pdi = di;
-    if (pn2) *pn2 = n2;
-    if (!(n2 > 0.0)) return 0.0f;
-    return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
+#pragma unroll
+    for (int e = 0; e < kGather; ++e)
+      cv[e] = n2[e] > 0.0
+                  ? (float)(sqrt((double)dr[e] * dr[e] + (double)di[e] * di[e]) / sqrt(n2[e]))
+                  : 0.0f;
+    if (pdr) *pdr = dr[0];
+    if (pdi) *pdi = di[0];
+    if (pn2) *pn2 = n2[0];
   }
 
   __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
@@ -407,13 +435,28 @@ struct Engine {
       }
     }
     if constexpr (GA) {
-      // the group reads each needed entry together, one after another
+      // the group reads the needed entries together, kGather at a time
       uint64_t nm = grp_ballot<G>(need, gbase);
       while (nm) {
-        const int src = __ffsll((unsigned long long)nm) - 1;
-        nm &= nm - 1;
-        const float cv = gather_cc(__shfl(k, src, G));
-        if (lane == src) val = cv;
+        int64_t ks[kGather];
+        int srcs[kGather];
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < kGather; ++e) {
+          srcs[e] = -1;
+          if (nm) {
+            srcs[e] = __ffsll((unsigned long long)nm) - 1;
+            nm &= nm - 1;
+            cnt = e + 1;
+          }
+          // unused slots repeat the first entry (a valid row, never read)
+          ks[e] = __shfl(k, srcs[e] >= 0 ? srcs[e] : srcs[0], G);
+        }
+        float cv[kGather];
+        gather_cc(ks, cnt, cv);
+#pragma unroll
+        for (int e = 0; e < kGather; ++e)
+          if (lane == srcs[e]) val = cv[e];
       }
     } else {
       if (need) val = simulate_cc(i);
@@ -886,7 +929,13 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
     if constexpr (GA) {
-      if (a.pd_re || a.pd_im) e.gather_cc(bk, &dr, &di, &n2);
+      if (a.pd_re || a.pd_im) {
+        constexpr int KG = Engine<G, SM, GA>::kGather;
+        int64_t ks[KG];
+        for (int q = 0; q < KG; ++q) ks[q] = bk;
+        float cv[KG];
+        e.gather_cc(ks, 1, cv, &dr, &di, &n2);
+      }
     } else {
       if (glane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
     }
@@ -966,14 +1015,16 @@ struct ZoomPlan {
 // wave per SIMD, beat 8 lanes, half a wave per SIMD).
 constexpr int kZoomGroups[] = {8, 16, 32, 64};
 
-static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_entries) {
+static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_entries,
+                          bool gather = false) {
   ZoomPlan p;
   // memo slots per voxel group: fine 4-parameter grids make long unit-step walks
   p.cap = grid_entries > ((int64_t)1 << 26) ? 32768 : 4096;
   (void)n_tr;
   p.group = 64;
+  // gathering: whole waves per voxel (each row read 1 KB per instruction)
   for (int g : kZoomGroups)
-    if (((int64_t)n_vox + 64 / g - 1) / (64 / g) >= 4 * (int64_t)n_cu) {
+    if (!gather && ((int64_t)n_vox + 64 / g - 1) / (64 / g) >= 4 * (int64_t)n_cu) {
       p.group = g;
       break;
     }
@@ -1102,7 +1153,10 @@ extern "C" int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_
   int rc = check_grid(grid);
   if (rc) return rc;
   MRF_CHECK_ARG(n_vox >= 0 && n_tr >= 1, "bad sizes");
-  *bytes = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid)).total;
+  // enough for the simulating and the gathering engine
+  const int64_t E = grid_size_checked(grid);
+  *bytes = std::max(zoom_plan(ctx->n_cu, n_vox, n_tr, E).total,
+                    zoom_plan(ctx->n_cu, n_vox, n_tr, E, true).total);
   return MRF_OK;
 }
 
@@ -1139,7 +1193,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   if (n_vox == 0) return MRF_OK;
   MRF_CHECK_ARG(vox != nullptr && out.idx != nullptr, "vox and out.idx must not be NULL");
   MRF_CHECK_ARG(ld_vox >= n_tr, "ld_vox must be >= n_tr");
-  const ZoomPlan plan = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid));
+  const ZoomPlan plan = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid), dict != nullptr);
   MRF_CHECK_ARG(workspace != nullptr && ws_bytes >= plan.total,
                 "workspace too small (%zu < %zu bytes)", ws_bytes, plan.total);
   hipStream_t st = (hipStream_t)stream;
