@@ -691,7 +691,7 @@ def main():
                      "f32_frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"],
                      "f32_frac_write_measured": (dict_bytes / (sim_avg * 1e-3) / 1e9 /
                                                  peaks["write_GB_per_s"] if peaks else None),
-                     "f32_traffic": counted_traffic("mrf::k_sim_dict<1, 1, true>", "sim.hip"),
+                     "f32_traffic": counted_traffic("mrf::k_sim_dict<1, 1, true, false>", "sim.hip"),
                      "bf16_ms": float(np.median(per_row["dict_bf16"])),
                      "bf16_GB_per_s": (E * N * 4 + E * 8) /
                                       (float(np.median(per_row["dict_bf16"])) * 1e-3) / 1e9},

@@ -319,7 +319,7 @@ struct Engine {
   // of the voxel (shared by the entries), then the partial sums are reduced
   // over the group. Entries at or beyond `cnt` are skipped. Every lane
   // returns every result.
-  static constexpr int kGather = 4;
+  static constexpr int kGather = 8;
   __device__ void gather_cc(const int64_t (&ks)[kGather], int cnt, float (&cv)[kGather],
                             float* pdr = nullptr, float* pdi = nullptr,
                             double* pn2 = nullptr) const {
