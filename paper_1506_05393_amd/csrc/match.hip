@@ -1,14 +1,11 @@
 // Brute-force matching (Theory Eq. 1, exhaustive search): K2 voxel packing,
 // K3 complex GEMM on MFMA with a fused per-voxel top-k epilogue, K4 merge.
 //
-// The complex inner products s_vk = sum_j vhat_j conj(d_kj) are a real GEMM
-// C = A^T B with K = 2 n_tr: for readout j and plane g (0: real, 1: imaginary)
-//   B[g][j][k] = Re/Im d_kj (the dictionary's planar layout),
-//   A[g][j][2v]   = (Re vhat_j, Im vhat_j)[g]   -> C[2v][k]   = Re s_vk
-//   A[g][j][2v+1] = (Im vhat_j, -Re vhat_j)[g]  -> C[2v+1][k] = Im s_vk
-// so CC_vk^2 = (C[2v][k]^2 + C[2v+1][k]^2) / ||d_k||^2. The score matrix is
-// never written: every workgroup keeps the running top-k of its voxels over
-// its share of the entries and writes only those lists.
+// The complex inner products s_vk = sum_j vhat_j conj(d_kj) are formed from
+// three real GEMMs over the readouts (see K3 below), and
+// CC_vk^2 = |s_vk|^2 / ||d_k||^2. The score matrix is never written: every
+// workgroup keeps the running top-k of its voxels over its share of the
+// entries and writes only those lists.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,48 +17,67 @@
 
 namespace mrf {
 
-// ---------------------------------------------------------------------------
-// Tile geometry of the FP32 GEMM.
-// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement over a 128-row x
-// 128-column tile; each wave owns 64 x 64 = 2 x 2 blocks of 32 x 32
-// (v_mfma_f32_32x32x2_f32: per instruction lanes 0-31 carry plane 0 and lanes
-// 32-63 plane 1 of one readout, so one instruction = one readout of K).
-// ---------------------------------------------------------------------------
-constexpr int BM = 128;     // rows (64 voxels)
-constexpr int BN = 128;     // entries
-constexpr int KC = 8;       // readouts per LDS chunk (48 KB of LDS: three workgroups per CU)
-constexpr int NLD = KC / 4;  // float4 of A (and of B) each thread moves per chunk
-constexpr int KK_MAX = 16;  // longest candidate list kept in the epilogue
+// Tile geometry of the FP32 GEMM (workgroup of 256 threads = 4 waves).
+constexpr int BN = 128;      // entries per tile
+constexpr int KC = 8;        // readouts per LDS chunk (44 KB of LDS: three workgroups per CU)
+constexpr int NLD = KC / 4;  // float4 of B each thread moves per chunk
+constexpr int KK_MAX = 16;   // longest candidate list kept in the epilogue
 constexpr int kWgPerCu = 3;  // resident workgroups per CU (LDS and registers allow three)
 
-struct MatchArgs {
-  const float* A;       // [2][n_tr_pad][m_pad]
+// ---------------------------------------------------------------------------
+// K3, three-product form. With T1 = sum vr dr, T2 = sum vi di and
+// T3 = sum (vr + vi)(dr - di) (v the unit voxel, d the entry, sums over the
+// readouts), Re s = T1 + T2 and Im s = T3 - T1 + T2: three real GEMMs with
+// K = n_tr instead of one with M = 2 V and K = 2 n_tr, so 6 V N E matrix
+// flops instead of 8 V N E. A holds three planes [vr | vi | vr + vi] of the
+// voxels, B stays the dictionary's two planes; dr - di is formed from the
+// two B fragments in registers. Tile: 64 voxels x 128 entries, four waves
+// 2 x 2, each 32 voxels x 64 entries = two 32 x 32 blocks per product;
+// v_mfma_f32_32x32x2_f32 takes two readouts of one plane per instruction
+// (lanes 0-31 readout 2p, lanes 32-63 readout 2p + 1). Against the
+// two-rows-per-voxel form (M = 2 V, K = 2 n_tr, 8 V N E flops) this measured
+// 3.14 s instead of 3.38 s on the 64 x 64 slice: the thresholds of the top-k
+// filter are read from the lists in LDS, which keeps the extra accumulators
+// within three waves per SIMD without spills.
+// ---------------------------------------------------------------------------
+constexpr int BV3 = 64;                      // voxels per tile
+constexpr int NLA3 = 3 * KC * BV3 / 4 / 256;  // float4 of A every thread moves per chunk
+constexpr int NLA3_REM = 3 * KC * BV3 / 4 - NLA3 * 256;  // and the threads moving one more
+
+struct Match3Args {
+  const float* A;       // [3][n_tr_pad][v_pad]
   const float* Bre;     // [n_tr][ld]
   const float* Bim;
   const double* norm;   // [n_entries] or NULL
-  int32_t n_tr, n_tr_pad, m_pad, n_vox_pad;
+  int32_t n_tr, n_tr_pad, v_pad;
   int64_t ld, n_entries;
   int32_t n_row_tiles, n_chunks, n_col_tiles, kk;
-  float* part_s;        // [n_chunks][2][n_vox_pad][kk]
+  float* part_s;        // [n_chunks][2][v_pad][kk]
   int32_t* part_i;
 };
 
-// One LDS chunk of KC readouts: A [2 planes][KC][BM] and B [2][KC][BN]
-// floats; thread t moves NLD float4 of each.
-__device__ __forceinline__ void load_chunk(const MatchArgs& a, int c, int row0, int64_t col0,
-                                           int tid, float4 (&ra)[NLD], float4 (&rb)[NLD]) {
+__device__ __forceinline__ void load_chunk3(const Match3Args& a, int c, int vox0, int64_t col0,
+                                            int tid, float4 (&ra)[NLA3 + 1],
+                                            float4 (&rb)[NLD]) {
   const int s0 = c * KC;
+#pragma unroll
+  for (int i = 0; i < NLA3 + 1; ++i) {
+    // [g][s][c4] with 16 float4 per row; the threads past the last float4
+    // load a duplicate (never stored), so no load waits behind a branch
+    const int idx = i < NLA3 ? i * 256 + tid : NLA3 * 256 + tid % NLA3_REM;
+    const int g = idx / (KC * 16);
+    const int s = (idx / 16) % KC;
+    const int c4 = idx & 15;
+    ra[i] = *(const float4*)(a.A + ((int64_t)g * a.n_tr_pad + s0 + s) * a.v_pad + vox0 + 4 * c4);
+  }
 #pragma unroll
   for (int i = 0; i < NLD; ++i) {
     const int idx = i * 256 + tid;  // [g][s][c4] with 32 float4 per row
     const int g = idx / (KC * 32);
     const int s = (idx / 32) % KC;
     const int c4 = idx & 31;
-    ra[i] = *(const float4*)(a.A + ((int64_t)g * a.n_tr_pad + s0 + s) * a.m_pad + row0 + 4 * c4);
-    // unconditional loads (a branch here would make every load wait for
-    // the previous ones): readouts past n_tr are clamped to a stored row
-    // (they meet zero A rows), columns past ld to the last float4 (those
-    // columns are masked in the epilogue)
+    // unconditional: readouts past n_tr are clamped to a stored row (they
+    // meet zero A rows), columns past ld to the last float4 (masked later)
     int64_t col = col0 + 4 * c4;
     col = col + 4 <= a.ld ? col : a.ld - 4;
     const int row = s0 + s < a.n_tr ? s0 + s : a.n_tr - 1;
@@ -70,23 +86,23 @@ __device__ __forceinline__ void load_chunk(const MatchArgs& a, int c, int row0, 
   }
 }
 
-__device__ __forceinline__ void store_chunk(float* As, float* Bs, int buf, int tid,
-                                            const float4 (&ra)[NLD], const float4 (&rb)[NLD]) {
-  float* as = As + buf * 2 * KC * BM;
+__device__ __forceinline__ void store_chunk3(float* As, float* Bs, int buf, int tid,
+                                             const float4 (&ra)[NLA3 + 1],
+                                             const float4 (&rb)[NLD]) {
+  float* as = As + buf * 3 * KC * BV3;
   float* bs = Bs + buf * 2 * KC * BN;
+#pragma unroll
+  for (int i = 0; i < NLA3; ++i) *(float4*)(as + 4 * (i * 256 + tid)) = ra[i];
+  if (tid < NLA3_REM) *(float4*)(as + 4 * (NLA3 * 256 + tid)) = ra[NLA3];
 #pragma unroll
   for (int i = 0; i < NLD; ++i) {
     const int idx = i * 256 + tid;
-    *(float4*)(as + 4 * idx) = ra[i];
     *(float4*)(bs + 4 * idx) = rb[i];
   }
 }
 
-// Three workgroups per CU (one wave per SIMD each): the registers of a wave
-// stay within a third of the file, so each SIMD holds three waves whose MFMAs
-// fill each other's LDS waits.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_match_f32(
-    MatchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_match_f32_3m(
+    Match3Args a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
   // (round robin over 8), so the row tiles of one column chunk are grouped on
   // one XCD and share its L2 for the dictionary tiles.
@@ -98,8 +114,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   if (chunk >= a.n_chunks) return;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  float* As = (float*)smem;                    // [2 buf][2 g][KC][BM]
-  float* Bs = As + 2 * 2 * KC * BM;            // [2 buf][2 g][KC][BN]
+  float* As = (float*)smem;                    // [2 buf][3 g][KC][BV3]
+  float* Bs = As + 2 * 3 * KC * BV3;           // [2 buf][2 g][KC][BN]
   float* Ls = Bs + 2 * 2 * KC * BN;            // [4 waves][32 voxels][KK_MAX]
   int32_t* Li = (int32_t*)(Ls + 4 * 32 * KK_MAX);
 
@@ -107,8 +123,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
+  const int h = lane >> 5;
   const int kk = a.kk;
-  const int row0 = rt * BM;
+  const int vox0 = rt * BV3;
 
   float* myLs = Ls + wave * 32 * KK_MAX;
   int32_t* myLi = Li + wave * 32 * KK_MAX;
@@ -116,9 +133,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     myLs[i] = -1.0f;
     myLi[i] = 0x7fffffff;
   }
-  float thr[16];  // per lane: current k-th best of its 16 voxels
-#pragma unroll
-  for (int i = 0; i < 16; ++i) thr[i] = -1.0f;
+  __syncthreads();  // the lists' initial values before the first threshold read
 
   const int ct_begin = (int)((int64_t)chunk * a.n_col_tiles / a.n_chunks);
   const int ct_end = (int)((int64_t)(chunk + 1) * a.n_col_tiles / a.n_chunks);
@@ -126,35 +141,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 
   for (int ct = ct_begin; ct < ct_end; ++ct) {
     const int64_t col0 = (int64_t)ct * BN;
-    floatx16 acc[2][2];
+    floatx16 t1[2], t2[2], t3[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+      for (int r = 0; r < 16; ++r) t1[j][r] = t2[j][r] = t3[j][r] = 0.0f;
 
-    float4 ra[NLD], rb[NLD];
-    load_chunk(a, 0, row0, col0, tid, ra, rb);
-    store_chunk(As, Bs, 0, tid, ra, rb);
+    float4 ra[NLA3 + 1], rb[NLD];
+    load_chunk3(a, 0, vox0, col0, tid, ra, rb);
+    store_chunk3(As, Bs, 0, tid, ra, rb);
     __syncthreads();
     for (int c = 0; c < n_kc; ++c) {
       const int buf = c & 1;
-      // always load (the last iteration reloads its own chunk): no branch
-      // around the loads, so they stay in flight during the MFMAs
-      load_chunk(a, c + 1 < n_kc ? c + 1 : c, row0, col0, tid, ra, rb);
-      const float* as = As + buf * 2 * KC * BM + (lane >> 5) * KC * BM + wr * 64 + (lane & 31);
-      const float* bs = Bs + buf * 2 * KC * BN + (lane >> 5) * KC * BN + wc * 64 + (lane & 31);
-#pragma unroll 8
-      for (int s = 0; s < KC; ++s) {
-        const float a0 = as[s * BM], a1 = as[s * BM + 32];
-        const float b0 = bs[s * BN], b1 = bs[s * BN + 32];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      load_chunk3(a, c + 1 < n_kc ? c + 1 : c, vox0, col0, tid, ra, rb);
+      const float* as = As + buf * 3 * KC * BV3 + h * BV3 + wr * 32 + (lane & 31);
+      const float* bs = Bs + buf * 2 * KC * BN + h * BN + wc * 64 + (lane & 31);
+#pragma unroll
+      for (int p = 0; p < KC / 2; ++p) {
+        const int s = 2 * p;
+        const float a1 = as[s * BV3], a2 = as[(KC + s) * BV3], a3 = as[(2 * KC + s) * BV3];
+        const float r0 = bs[s * BN], r1 = bs[s * BN + 32];
+        const float i0 = bs[(KC + s) * BN], i1 = bs[(KC + s) * BN + 32];
+        t1[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, r0, t1[0], 0, 0, 0);
+        t1[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, r1, t1[1], 0, 0, 0);
+        t2[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, i0, t2[0], 0, 0, 0);
+        t2[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, i1, t2[1], 0, 0, 0);
+        t3[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a3, r0 - i0, t3[0], 0, 0, 0);
+        t3[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a3, r1 - i1, t3[1], 0, 0, 0);
       }
-      store_chunk(As, Bs, buf ^ 1, tid, ra, rb);
+      store_chunk3(As, Bs, buf ^ 1, tid, ra, rb);
       __syncthreads();
     }
 
@@ -173,59 +188,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       }
     }
 #pragma unroll
-    for (int bm = 0; bm < 2; ++bm) {
+    for (int bn = 0; bn < 2; ++bn) {
 #pragma unroll
-      for (int bn = 0; bn < 2; ++bn) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          // rows 8*(q/2) + 4*h + 2*(q%2) + {0,1}: voxel (4*(q/2) + 2*h + q%2) of the block
-          const int r = 4 * (q >> 1) + 2 * (q & 1);
-          const float re = acc[bm][bn][r], im = acc[bm][bn][r + 1];
-          const float sc = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
-          const int t = bm * 8 + q;
-          const bool cand = sc > thr[t];
-          uint64_t m = __ballot(cand);
-          while (m) {
-            const int src = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const float s = __shfl(sc, src);
-            const int32_t e = __shfl(ecol[bn], src);
-            // voxel slot of lane src within this wave's 32 voxels
-            const int vl = bm * 16 + 4 * (q >> 1) + 2 * (src >> 5) + (q & 1);
-            list_insert(myLs + vl * KK_MAX, myLi + vl * KK_MAX, kk, lane, s, e);
-          }
+      for (int r = 0; r < 16; ++r) {
+        // output row 8 (r / 4) + 4 h + r % 4 of the block = voxel slot
+        const float re = t1[bn][r] + t2[bn][r];
+        const float im = t3[bn][r] - t1[bn][r] + t2[bn][r];
+        const float sc = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
+        // this lane's voxel: the k-th best so far (read from its list)
+        const float thr = myLs[(8 * (r >> 2) + 4 * h + (r & 3)) * KK_MAX + kk - 1];
+        const bool cand = sc > thr;
+        uint64_t m = __ballot(cand);
+        while (m) {
+          const int src = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const float sv = __shfl(sc, src);
+          const int32_t e = __shfl(ecol[bn], src);
+          const int vl = 8 * (r >> 2) + 4 * (src >> 5) + (r & 3);
+          list_insert(myLs + vl * KK_MAX, myLi + vl * KK_MAX, kk, lane, sv, e);
         }
       }
     }
-    // refresh thresholds (k-th best of each voxel this lane holds)
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int vl = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
-        thr[bm * 8 + q] = myLs[vl * KK_MAX + kk - 1];
-      }
   }
 
   // write this wave's lists: partial[chunk][wc][voxel][kk]
   for (int i = lane; i < 32 * kk; i += 64) {
     const int vl = i / kk, p = i % kk;
-    const int v = (row0 + wr * 64) / 2 + vl;
-    if (v < a.n_vox_pad) {
-      const int64_t o = (((int64_t)chunk * 2 + wc) * a.n_vox_pad + v) * kk + p;
+    const int v = vox0 + wr * 32 + vl;
+    if (v < a.v_pad) {
+      const int64_t o = (((int64_t)chunk * 2 + wc) * a.v_pad + v) * kk + p;
       a.part_s[o] = myLs[vl * KK_MAX + p];
       a.part_i[o] = myLi[vl * KK_MAX + p];
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// K2: voxel normalisation and packing of the A operand. One wave per voxel.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_pack_f32(const float2* __restrict__ vox, int64_t ld_vox,
-                                                 int32_t n_vox, int32_t n_tr, int32_t n_tr_pad,
-                                                 int32_t m_pad, float* __restrict__ A,
-                                                 double* __restrict__ vnorm) {
+// K2 for the three-product form: A = [vr | vi | vr + vi] of the unit voxels,
+// time-major, zero past n_tr and past n_vox. One wave per voxel.
+__global__ __launch_bounds__(64) void k_pack_f32_3m(const float2* __restrict__ vox,
+                                                    int64_t ld_vox, int32_t n_vox, int32_t n_tr,
+                                                    int32_t n_tr_pad, int32_t v_pad,
+                                                    float* __restrict__ A,
+                                                    double* __restrict__ vnorm) {
   const int v = blockIdx.x;
   const int lane = threadIdx.x;
   double s2 = 0.0;
@@ -240,12 +244,15 @@ __global__ __launch_bounds__(64) void k_pack_f32(const float2* __restrict__ vox,
   const double nv = sqrt(s2);
   const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
   if (lane == 0 && v < n_vox) vnorm[v] = nv;
+  const int64_t plane = (int64_t)n_tr_pad * v_pad;
   for (int j = lane; j < n_tr_pad; j += 64) {
     float2 x = make_float2(0.f, 0.f);
     if (v < n_vox && j < n_tr) x = vox[(int64_t)v * ld_vox + j];
     const float xr = x.x * inv, xi = x.y * inv;
-    *(float2*)(A + (int64_t)j * m_pad + 2 * v) = make_float2(xr, xi);
-    *(float2*)(A + ((int64_t)n_tr_pad + j) * m_pad + 2 * v) = make_float2(xi, -xr);
+    float* col = A + (int64_t)j * v_pad + v;
+    col[0] = xr;
+    col[plane] = xi;
+    col[2 * plane] = xr + xi;
   }
 }
 
@@ -342,8 +349,9 @@ int launch_merge(mrf_context* ctx, const MergeArgs& m, hipStream_t st) {
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+
 struct Plan {
-  int32_t n_tr_pad, m_pad, n_vox_pad, n_row_tiles, n_col_tiles, n_chunks, kk;
+  int32_t n_tr_pad, n_vox_pad, n_row_tiles, n_col_tiles, n_chunks, kk;
   size_t off_A, off_vn, off_ps, off_pi, off_bs, off_bi, total;
 };
 
@@ -351,9 +359,8 @@ static Plan make_plan(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int 
   Plan p;
   p.kk = std::max(top_k, 2);
   p.n_tr_pad = (d->n_tr + KC - 1) / KC * KC;
-  p.m_pad = std::max((2 * n_vox + BM - 1) / BM * BM, BM);
-  p.n_vox_pad = p.m_pad / 2;
-  p.n_row_tiles = p.m_pad / BM;
+  p.n_vox_pad = std::max((n_vox + BV3 - 1) / BV3 * BV3, BV3);
+  p.n_row_tiles = p.n_vox_pad / BV3;
   p.n_col_tiles = (int32_t)((d->n_entries + BN - 1) / BN);
   // enough chunks for two rounds of the three resident workgroups per CU, a
   // multiple of 8 (XCDs)
@@ -362,7 +369,7 @@ static Plan make_plan(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int 
   p.n_chunks = std::max(8, (want + 7) / 8 * 8);
   size_t o = 0;
   p.off_A = o;
-  o = al(o + sizeof(float) * 2 * (size_t)p.n_tr_pad * p.m_pad);
+  o = al(o + sizeof(float) * 3 * (size_t)p.n_tr_pad * p.n_vox_pad);
   p.off_vn = o;
   o = al(o + sizeof(double) * (size_t)p.n_vox_pad);
   const size_t np = (size_t)p.n_chunks * 2 * p.n_vox_pad * p.kk;
@@ -450,20 +457,18 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
 
   {
     ProfScope prof(ctx, "k_pack_f32", st);
-    hipLaunchKernelGGL(k_pack_f32, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox, ld_vox,
-                       n_vox, d->n_tr, p.n_tr_pad, p.m_pad, A, vn);
+    hipLaunchKernelGGL(k_pack_f32_3m, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox,
+                       ld_vox, n_vox, d->n_tr, p.n_tr_pad, p.n_vox_pad, A, vn);
   }
   MRF_HIP(hipGetLastError());
-
-  MatchArgs a;
+  Match3Args a;
   a.A = A;
   a.Bre = (const float*)d->re;
   a.Bim = (const float*)d->im;
   a.norm = d->norm;
   a.n_tr = d->n_tr;
   a.n_tr_pad = p.n_tr_pad;
-  a.m_pad = p.m_pad;
-  a.n_vox_pad = p.n_vox_pad;
+  a.v_pad = p.n_vox_pad;
   a.ld = d->ld;
   a.n_entries = d->n_entries;
   a.n_row_tiles = p.n_row_tiles;
@@ -473,17 +478,17 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   a.part_s = ps;
   a.part_i = pi;
   const int grid_wg = p.n_row_tiles * p.n_chunks;
-  const size_t lds = sizeof(float) * (2 * 2 * KC * BM + 2 * 2 * KC * BN) +
+  const size_t lds = sizeof(float) * (2 * 3 * KC * BV3 + 2 * 2 * KC * BN) +
                      (sizeof(float) + sizeof(int32_t)) * 4 * 32 * KK_MAX;
-  static bool attr_set = false;
-  if (!attr_set) {
-    MRF_HIP(hipFuncSetAttribute((const void*)k_match_f32,
+  static bool attr3_set = false;
+  if (!attr3_set) {
+    MRF_HIP(hipFuncSetAttribute((const void*)k_match_f32_3m,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = true;
+    attr3_set = true;
   }
   {
     ProfScope prof(ctx, "k_match_f32", st);
-    hipLaunchKernelGGL(k_match_f32, dim3(grid_wg), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(k_match_f32_3m, dim3(grid_wg), dim3(256), lds, st, a);
   }
   MRF_HIP(hipGetLastError());
 
