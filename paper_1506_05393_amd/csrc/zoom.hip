@@ -175,8 +175,10 @@ struct Engine {
   // as the full 3 x 3 one does.
   // six readouts ahead: on the slice each SIMD holds one wave (4096 voxels in
   // groups of 16), so nothing else hides the table reads' latency; deeper
-  // rings spill more than they gain (measured 3: 11.1 ms, 6: 10.2 ms, 8: 10.6)
-  static constexpr int kAhead = 6;
+  // rings spill more than they gain (measured 3: 11.1 ms, 6: 10.2 ms, 8: 10.6).
+  // The smoothing kernel, whose delay line already fills the registers, keeps
+  // three (six made it slower: 22-24 -> 27 ms).
+  static constexpr int kAhead = SM ? 3 : 6;
   template <bool LANE_R, bool X_AXIS>
   __device__ float simulate_cc_t(const int32_t* i, float* pdr, float* pdi, double* pn2) const {
     typedef float v2 __attribute__((ext_vector_type(2)));
