@@ -413,8 +413,24 @@ struct Engine {
   __device__ uint32_t memo_home(int64_t k) const {
     return (uint32_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(pa.memo_cap - 1);
   }
+  // GA: the memo lives in LDS (one voxel group per wave), so a probe or a
+  // store costs an LDS access instead of an L2 round trip.
   __device__ int64_t memo_ld_key(uint32_t s) const {
+    if constexpr (GA) return mkey[s];
     return __hip_atomic_load(mkey + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ float memo_ld_val(uint32_t s) const {
+    if constexpr (GA) return mval[s];
+    return __hip_atomic_load(mval + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ void memo_st(uint32_t s, int64_t kv, float v) const {
+    if constexpr (GA) {
+      mval[s] = v;
+      mkey[s] = kv;
+    } else {
+      __hip_atomic_store(mval + s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(mkey + s, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 
   // Wave-level evaluation: every lane with `valid` asks for the value at i.
@@ -431,7 +447,7 @@ struct Engine {
       for (int32_t probe = 0; probe < cap; ++probe) {
         const int64_t mk = memo_ld_key(s);
         if (mk == tagged) {
-          val = __hip_atomic_load(mval + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          val = memo_ld_val(s);
           need = false;
           break;
         }
@@ -477,8 +493,7 @@ struct Engine {
         if (lane == 0) {
           uint32_t s = memo_home(ks);
           while ((memo_ld_key(s) & ~kIndexMask) == tag) s = (s + 1) & (cap - 1);
-          __hip_atomic_store(mval + s, vv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(mkey + s, tag | ks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          memo_st(s, tag | ks, vv);
         }
         ++memo_count;
       } else {
@@ -783,6 +798,14 @@ __host__ __device__ inline size_t zoom_group_lds() {
   return MRF_ZOOM_MAX_STARTS * (sizeof(int64_t) + sizeof(float)) + 8 * sizeof(float);
 }
 
+// The gathering engine's memo: slots per wave, in LDS (a slice voxel visits
+// ~150 entries; past 3/4 of the slots values are no longer kept and n_sim
+// is reported negative, as with the global memo).
+constexpr int32_t kGatherMemo = 1024;
+__host__ __device__ inline size_t zoom_gather_memo_lds() {
+  return (size_t)kGatherMemo * (sizeof(int64_t) + sizeof(float));
+}
+
 // One wave per block, 64 / G voxels per wave: each group of G lanes runs its
 // own voxel's stage machine and pulls its own voxels from the queue, so the
 // lanes that a decision leaves idle in one group work for the others.
@@ -799,11 +822,24 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   float* nbv = fin_v + MRF_ZOOM_MAX_STARTS;                                        // [8]
   const mrf_zoom_schedule* __restrict__ S = a.sch;
   // this group's memo; serial 0 marks never-used slots
-  int64_t* mkey = a.memo_keys + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
-  float* mval = a.memo_vals + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
-  for (int32_t i = lane; i < NG * a.memo_cap; i += 64)
-    __hip_atomic_store(a.memo_keys + (int64_t)blockIdx.x * NG * a.memo_cap + i, (int64_t)0,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int64_t* mkey;
+  float* mval;
+  int32_t memo_cap;
+  if constexpr (GA) {
+    // one group per wave: the memo follows the group's LDS (8-byte aligned)
+    static_assert(G == 64 || !GA, "the gathering engine runs one voxel group per wave");
+    mkey = (int64_t*)(sm + ((NG * zoom_group_lds() + 7) & ~(size_t)7));
+    mval = (float*)(mkey + kGatherMemo);
+    memo_cap = kGatherMemo;
+    for (int32_t i = lane; i < kGatherMemo; i += 64) mkey[i] = 0;
+  } else {
+    mkey = a.memo_keys + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
+    mval = a.memo_vals + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
+    memo_cap = a.memo_cap;
+    for (int32_t i = lane; i < NG * a.memo_cap; i += 64)
+      __hip_atomic_store(a.memo_keys + (int64_t)blockIdx.x * NG * a.memo_cap + i, (int64_t)0,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();
   int64_t serial = 0;
 
@@ -863,7 +899,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       e.dm = a.demod;
     }
     if constexpr (GA) e.dict = DictRows{a.dict, a.dict_ld4};
-    e.pa.memo_cap = a.memo_cap;
+    e.pa.memo_cap = memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
     e.vx = src;
@@ -962,14 +998,19 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
 template <bool SM, bool GA>
 static void launch_zoom_groups(int group, int blocks, size_t lds, hipStream_t st,
                                const ZoomArgs& a) {
-  if (group == 8)
-    hipLaunchKernelGGL((k_zoom<8, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
-  else if (group == 16)
-    hipLaunchKernelGGL((k_zoom<16, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
-  else if (group == 32)
-    hipLaunchKernelGGL((k_zoom<32, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
-  else
+  if constexpr (GA) {
+    (void)group;  // whole-wave groups (zoom_plan)
     hipLaunchKernelGGL((k_zoom<64, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+  } else {
+    if (group == 8)
+      hipLaunchKernelGGL((k_zoom<8, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+    else if (group == 16)
+      hipLaunchKernelGGL((k_zoom<16, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+    else if (group == 32)
+      hipLaunchKernelGGL((k_zoom<32, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+    else
+      hipLaunchKernelGGL((k_zoom<64, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+  }
 }
 
 static int32_t h_round_half_away(double x) {
@@ -1035,6 +1076,7 @@ static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_en
     }
   const int ng = 64 / p.group;
   p.lds = (size_t)ng * zoom_group_lds() + 16;
+  if (gather) p.lds = ((p.lds + 7) & ~(size_t)7) + zoom_gather_memo_lds();
   const int per_cu = std::max(1, std::min(16, (int)((160 * 1024) / p.lds)));
   const int64_t waves_needed = ((int64_t)n_vox + ng - 1) / ng;
   p.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(waves_needed, (int64_t)n_cu * per_cu));
