@@ -490,7 +490,8 @@ int mrf_probe_write(mrf_context* ctx, void* dst, int64_t bytes, uint32_t pattern
 
 /* ------------------------------------------------------------------------
  * Kernel timing. When enabled, every launch of a named kernel
- * ("k_sim_dict", "k_match_f32", "k_match_bf16", "k_rescore", "k_zoom", ...)
+ * ("k_sim_dict", "k_match_f32" (the three-product FP32 GEMM), "k_match_bf16",
+ * "k_rescore", "k_zoom", ...)
  * is bracketed by HIP events recorded on the stream it is launched on.
  * mrf_profile_read waits for those events and returns the summed elapsed
  * time and launch count since the last reset (reset = 1 clears them).
