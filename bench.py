@@ -389,7 +389,7 @@ def smoothing_bench(api, ctx, torch, w, vox, d32, ws, wsz, base, repeats: int = 
             "mean_abs_error_zoom_unsmoothed": err(base["idx_zoom"])}
 
 
-def zoom_dict_bench(api, ctx, torch, w, sq, vox, sched, base, repeats: int = 20):
+def zoom_dict_bench(api, ctx, torch, w, sq, vox, sched, base, repeats: int = 50):
     """MRF-ZOOM over a resident dictionary (the paper's MZfulldict): the slice's
     whole grid as entry-major FP32 rows (K1), then the gathering engine; its
     time per slice beside the simulating engine's (`base`)."""
@@ -594,9 +594,9 @@ def main():
     ctx.profile(False)
     log(f"timed {args.steps} steps in {wall:.2f} s")
 
-    # single-slice ZOOM latency over repeated calls
+    # single-slice ZOOM latency over 50 repeated calls
     zl = []
-    for _ in range(20):
+    for _ in range(50):
         a_, b_ = ev(), ev()
         a_.record()
         api.zoom_search(ctx, sq, ga, vox, sched=sched, workspace=wsz, out=outz)
