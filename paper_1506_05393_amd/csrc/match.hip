@@ -19,10 +19,13 @@ namespace mrf {
 
 // Tile geometry of the FP32 GEMM (workgroup of 256 threads = 4 waves).
 constexpr int BN = 128;      // entries per tile
-constexpr int KC = 8;        // readouts per LDS chunk (44 KB of LDS: three workgroups per CU)
+// readouts per LDS chunk: 72 KB of LDS, two workgroups per CU. With 8
+// readouts (44 KB, three workgroups per CU) the chunk's barrier and refill
+// took a larger share: 3.15 s instead of 2.85 s on the slice.
+constexpr int KC = 16;
 constexpr int NLD = KC / 4;  // float4 of B each thread moves per chunk
 constexpr int KK_MAX = 16;   // longest candidate list kept in the epilogue
-constexpr int kWgPerCu = 3;  // resident workgroups per CU (LDS and registers allow three)
+constexpr int kWgPerCu = 2;  // resident workgroups per CU (LDS allows two)
 
 // ---------------------------------------------------------------------------
 // K3, three-product form. With T1 = sum vr dr, T2 = sum vi di and
@@ -36,13 +39,15 @@ constexpr int kWgPerCu = 3;  // resident workgroups per CU (LDS and registers al
 // v_mfma_f32_32x32x2_f32 takes two readouts of one plane per instruction
 // (lanes 0-31 readout 2p, lanes 32-63 readout 2p + 1). Against the
 // two-rows-per-voxel form (M = 2 V, K = 2 n_tr, 8 V N E flops) this measured
-// 3.14 s instead of 3.38 s on the 64 x 64 slice: the thresholds of the top-k
-// filter are read from the lists in LDS, which keeps the extra accumulators
-// within three waves per SIMD without spills.
+// 3.14 s instead of 3.38 s on the 64 x 64 slice with 8-readout chunks (the
+// thresholds of the top-k filter read from the lists in LDS keep the extra
+// accumulators within three waves per SIMD without spills), 2.85 s with
+// 16-readout chunks at two waves per SIMD.
 // ---------------------------------------------------------------------------
 constexpr int BV3 = 64;                      // voxels per tile
 constexpr int NLA3 = 3 * KC * BV3 / 4 / 256;  // float4 of A every thread moves per chunk
 constexpr int NLA3_REM = 3 * KC * BV3 / 4 - NLA3 * 256;  // and the threads moving one more
+constexpr int NLA3X = NLA3 + (NLA3_REM > 0 ? 1 : 0);      // A registers per thread
 
 struct Match3Args {
   const float* A;       // [3][n_tr_pad][v_pad]
@@ -57,14 +62,14 @@ struct Match3Args {
 };
 
 __device__ __forceinline__ void load_chunk3(const Match3Args& a, int c, int vox0, int64_t col0,
-                                            int tid, float4 (&ra)[NLA3 + 1],
+                                            int tid, float4 (&ra)[NLA3X],
                                             float4 (&rb)[NLD]) {
   const int s0 = c * KC;
 #pragma unroll
-  for (int i = 0; i < NLA3 + 1; ++i) {
+  for (int i = 0; i < NLA3X; ++i) {
     // [g][s][c4] with 16 float4 per row; the threads past the last float4
     // load a duplicate (never stored), so no load waits behind a branch
-    const int idx = i < NLA3 ? i * 256 + tid : NLA3 * 256 + tid % NLA3_REM;
+    const int idx = i < NLA3 ? i * 256 + tid : NLA3 * 256 + tid % (NLA3_REM > 0 ? NLA3_REM : 1);
     const int g = idx / (KC * 16);
     const int s = (idx / 16) % KC;
     const int c4 = idx & 15;
@@ -87,13 +92,14 @@ __device__ __forceinline__ void load_chunk3(const Match3Args& a, int c, int vox0
 }
 
 __device__ __forceinline__ void store_chunk3(float* As, float* Bs, int buf, int tid,
-                                             const float4 (&ra)[NLA3 + 1],
+                                             const float4 (&ra)[NLA3X],
                                              const float4 (&rb)[NLD]) {
   float* as = As + buf * 3 * KC * BV3;
   float* bs = Bs + buf * 2 * KC * BN;
 #pragma unroll
   for (int i = 0; i < NLA3; ++i) *(float4*)(as + 4 * (i * 256 + tid)) = ra[i];
-  if (tid < NLA3_REM) *(float4*)(as + 4 * (NLA3 * 256 + tid)) = ra[NLA3];
+  if constexpr (NLA3_REM > 0)
+    if (tid < NLA3_REM) *(float4*)(as + 4 * (NLA3 * 256 + tid)) = ra[NLA3X - 1];
 #pragma unroll
   for (int i = 0; i < NLD; ++i) {
     const int idx = i * 256 + tid;
@@ -101,7 +107,7 @@ __device__ __forceinline__ void store_chunk3(float* As, float* Bs, int buf, int 
   }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_match_f32_3m(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_match_f32_3m(
     Match3Args a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
   // (round robin over 8), so the row tiles of one column chunk are grouped on
@@ -147,7 +153,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 #pragma unroll
       for (int r = 0; r < 16; ++r) t1[j][r] = t2[j][r] = t3[j][r] = 0.0f;
 
-    float4 ra[NLA3 + 1], rb[NLD];
+    float4 ra[NLA3X], rb[NLD];
     load_chunk3(a, 0, vox0, col0, tid, ra, rb);
     store_chunk3(As, Bs, 0, tid, ra, rb);
     __syncthreads();
