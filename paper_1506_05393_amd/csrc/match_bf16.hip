@@ -39,6 +39,7 @@ struct MatchB16Args {
   int32_t nblk, nblk_pad, m_pad, n_vox_pad;
   int64_t ld, n_entries;
   int32_t n_row_tiles, n_chunks, n_col_tiles, kk;
+  int32_t grp_rows, grp_chunks;  // workgroups resident on one XCD: grp_rows x grp_chunks
   float* part_s;        // [n_chunks][2][n_vox_pad][kk]
   int32_t* part_i;
 };
@@ -106,12 +107,20 @@ __device__ __forceinline__ void mfma_group(floatx16 (&acc)[4][4], const bf16x8 (
 }
 
 __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
+  // Workgroups are dealt to the 8 XCDs in turn (w & 7), and each XCD starts
+  // its slots in order, one workgroup per CU. The slots that run together on
+  // an XCD form a grp_rows x grp_chunks block: every voxel tile is then read
+  // into that XCD's L2 once for grp_chunks workgroups, and every dictionary
+  // tile once for grp_rows (rather than all row tiles against one chunk,
+  // which re-reads the whole voxel operand for every dictionary tile).
   const int w = blockIdx.x;
   const int xcd = w & 7;
   const int slot = w >> 3;
-  const int rt = slot % a.n_row_tiles;
-  const int chunk = xcd + 8 * (slot / a.n_row_tiles);
-  if (chunk >= a.n_chunks) return;
+  const int per = a.grp_rows * a.grp_chunks;
+  const int within = slot % per;
+  const int rt = (slot / per) * a.grp_rows + within % a.grp_rows;
+  const int chunk = xcd + 8 * (within / a.grp_rows);
+  if (rt >= a.n_row_tiles || chunk >= a.n_chunks) return;
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* As = (uint4*)smem;                  // [NSTAGE][BKB][BBM]
@@ -477,6 +486,7 @@ static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PlanB {
   int32_t nblk, nblk_pad, m_pad, n_vox_pad, n_row_tiles, n_col_tiles, n_chunks, kk;
+  int32_t grp_rows, grp_chunks, n_wg;
   size_t off_A, off_vn, off_ps, off_pi, off_bs, off_bi, total;
 };
 
@@ -489,9 +499,15 @@ static PlanB plan_bf16(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int
   p.n_vox_pad = p.m_pad / 2;
   p.n_row_tiles = p.m_pad / BBM;
   p.n_col_tiles = (int32_t)((d->n_entries + BBN - 1) / BBN);
-  int want = (2 * n_cu + p.n_row_tiles - 1) / p.n_row_tiles;
-  want = std::min(want, std::max(p.n_col_tiles, 1));
-  p.n_chunks = std::max(8, (want + 7) / 8 * 8);
+  // one workgroup per CU (the LDS ring takes most of it), n_cu / 8 per XCD:
+  // up to 8 row tiles x the rest in chunks resident together on an XCD
+  const int per_xcd = std::max(n_cu / 8, 1);
+  p.grp_rows = std::min(p.n_row_tiles, 8);
+  p.grp_chunks = std::max(per_xcd / p.grp_rows, 1);
+  p.grp_chunks = std::min(p.grp_chunks, std::max((p.n_col_tiles + 7) / 8, 1));
+  p.n_chunks = 8 * p.grp_chunks;
+  const int n_groups = (p.n_row_tiles + p.grp_rows - 1) / p.grp_rows;
+  p.n_wg = 8 * n_groups * p.grp_rows * p.grp_chunks;
   size_t o = 0;
   p.off_A = o;
   o = al(o + sizeof(uint4) * (size_t)p.nblk_pad * p.m_pad);
@@ -558,6 +574,8 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   a.n_chunks = p.n_chunks;
   a.n_col_tiles = p.n_col_tiles;
   a.kk = p.kk;
+  a.grp_rows = p.grp_rows;
+  a.grp_chunks = p.grp_chunks;
   a.part_s = ps;
   a.part_i = pi;
   const size_t lds = sizeof(uint4) * NSTAGE * BKB * (BBM + BBN) +
@@ -570,7 +588,7 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   }
   {
     ProfScope prof(ctx, "k_match_bf16", st);
-    hipLaunchKernelGGL(k_match_bf16, dim3(p.n_row_tiles * p.n_chunks), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(k_match_bf16, dim3(p.n_wg), dim3(256), lds, st, a);
   }
   MRF_HIP(hipGetLastError());
   MergeArgs m;
