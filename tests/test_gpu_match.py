@@ -208,6 +208,40 @@ def test_bruteforce_bf16_ragged(ctx, orc):
     _check(sub, {k: v[recall] for k, v in ref.items()}, "bf16 ragged")
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_bruteforce_tiling_invariance(ctx, orc, dtype):
+    """1100 voxels (9 row tiles of the BF16 GEMM, a ragged second group of row
+    tiles on each XCD; 18 of the FP32 one) give, voxel by voxel, the same
+    top-k lists bit for bit as the same voxels matched 128 at a time (one or
+    two row tiles, other entry chunks); sampled voxels meet the oracle bar."""
+    from paper_1506_05393_amd import api, workloads
+    w = workloads.small_dgs(False)
+    V0 = oracle_fingerprints(orc, w.seq, w.phantom)
+    rng = np.random.default_rng(11)
+    reps = -(-1100 // len(V0))
+    V = np.concatenate([V0 * np.exp(1j * rng.uniform(0, 2 * np.pi, (len(V0), 1)))
+                        for _ in range(reps)])[:1100].astype(np.complex64)
+    sq = api.Sequence(ctx, w.seq)
+    d = (_bf16_dict(api, ctx, sq, w.grid) if dtype == "bf16"
+         else api.simulate_dictionary(ctx, sq, w.grid))
+    kw = dict(top_k=8, seq=sq, grid=w.grid, with_topk=True)
+    Vd = to_dev(V)
+    full = api.match_bruteforce(ctx, d, Vd, **kw)
+    parts = [api.match_bruteforce(ctx, d, Vd[i:i + 128].contiguous(), **kw)
+             for i in range(0, len(V), 128)]
+    torch.cuda.synchronize()
+    for key in ("idx", "cc", "topk_idx", "topk_cc"):
+        assert torch.equal(full[key], torch.cat([p[key] for p in parts])), key
+    sample = np.sort(rng.choice(len(V), 24, replace=False))
+    ref = orc.bruteforce(w.seq, w.grid, V[sample], top_k=8, threads=8)
+    tk = full["topk_idx"].cpu().numpy()[sample]
+    recall = np.array([ref["idx"][i] in tk[i] for i in range(len(sample))])
+    assert recall.mean() >= 0.9
+    sub = {k: v[sample][recall] for k, v in full.items()
+           if isinstance(v, torch.Tensor) and v.dim() == 1}
+    _check(sub, {k: v[recall] for k, v in ref.items()}, f"{dtype} 1100 voxels")
+
+
 def test_bf16_requires_sequence_and_grid(ctx):
     from paper_1506_05393_amd import api, _lib
     seq = I.make_sequence(40, 1)
