@@ -297,6 +297,19 @@ typedef struct {
 int mrf_zoom_schedule_paper(const mrf_grid* grid, const mrf_sequence* seq,
                             mrf_zoom_schedule* out);
 
+/* Neighbour-prior ranges (Methods, Experiment 3: a neighbour's result
+ * T1p/T2p/dfp opens the ranges T1p +- 3000 ms, T2p +- 800 ms, dfp +- 150 Hz,
+ * intersected with the search ranges). Sets sched->prior_half (the only
+ * field written) from physical half widths half[4] = (T1 ms, T2 ms, df Hz,
+ * B1 scale), host memory, or NULL for the paper's ranges with +- 0.3 for a
+ * B1 axis. Each becomes index steps like the schedule's other physical
+ * steps, max(1, round_half_away(half / ((max - min)/(n - 1)))); an axis of
+ * fewer than two values or a negative half width gets -1 (the whole axis).
+ * The ranges apply to searches started from prior centres (init_idx,
+ * mrf_zoom_search_from, the second lattice pass). Host only.
+ * Errors: invalid grid, NULL sched, a NaN half width -> MRF_ERR_INVALID. */
+int mrf_zoom_schedule_prior(const mrf_grid* grid, const double* half, mrf_zoom_schedule* sched);
+
 /* Local refinement (not a schedule of the paper: its finest-resolution
  * steps, Methods Experiment 2 step 5, used alone): unit-step 2-D zoom on
  * (T1, T2), unit-step 1-D zoom on df (and on B1 with a B1 axis), repeated

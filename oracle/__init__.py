@@ -86,6 +86,9 @@ def lib():
                                  C.c_int32, C.c_int64, C.c_int64, dp, C.c_int32]
         L.orc_schedule_paper.argtypes = [C.POINTER(GridS), C.POINTER(Seq),
                                          C.POINTER(Schedule)]
+        L.orc_cc_at.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp, C.c_int32,
+                                C.c_int32, lp, dp, C.c_int32]
+        L.orc_prior_half.argtypes = [C.POINTER(GridS), dp, ip]
         L.orc_zoom_generic.argtypes = [C.POINTER(Schedule), ip, ip, OBJECTIVE, C.c_void_p,
                                        ip, dp, ip, dp, ip, C.c_int32, ip]
         L.orc_zoom.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32,
@@ -203,6 +206,27 @@ def cc(v, d) -> float:
     return float(lib().orc_cc(len(v), _dp(vr), _dp(vi), _dp(dr), _dp(di)))
 
 
+def cc_at(seq, grid, vox, idx, n_tr=None, threads=0) -> np.ndarray:
+    """CC (Eq. 1) of each voxel against listed entries: vox complex [n_vox,
+    n_tr], idx int [n_vox, m] grid indices (negative: 0). float64 [n_vox, m]."""
+    vox = np.atleast_2d(np.asarray(vox, np.complex128))
+    n_vox = vox.shape[0]
+    n_tr = vox.shape[1] if n_tr is None else n_tr
+    vox = vox[:, :n_tr]
+    idx = np.ascontiguousarray(np.asarray(idx, np.int64).reshape(n_vox, -1))
+    m = idx.shape[1]
+    s, ks = make_seq(seq)
+    g, kg = make_grid(grid)
+    vr = np.ascontiguousarray(vox.real)
+    vi = np.ascontiguousarray(vox.imag)
+    out = np.zeros((n_vox, m))
+    rc = lib().orc_cc_at(C.byref(s), C.byref(g), n_tr, _dp(vr), _dp(vi), n_vox, m,
+                         idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(out), _threads(threads))
+    if rc:
+        raise ValueError(f"orc_cc_at failed ({rc})")
+    return out
+
+
 def bruteforce(seq, grid, vox, top_k=1, n_tr=None, threads=0) -> dict:
     """vox: complex [n_vox, n_tr]. Returns idx, cc, margin, pd, topk_idx, topk_cc."""
     vox = np.asarray(vox, np.complex128)
@@ -289,6 +313,21 @@ def schedule_paper(seq, grid) -> dict:
     if rc:
         raise ValueError("orc_schedule_paper failed")
     return schedule_to_dict(out)
+
+
+def prior_half(grid, half=None) -> list:
+    """Neighbour-prior half widths (Experiment 3) in index steps for physical
+    half widths (T1 ms, T2 ms, df Hz, B1); None: 3000, 800, 150, 0.3."""
+    g, kg = make_grid(grid)
+    out = (C.c_int32 * 4)()
+    h = None
+    if half is not None:
+        kg.half = np.ascontiguousarray(half, np.float64)
+        h = _dp(kg.half)
+    rc = lib().orc_prior_half(C.byref(g), h, out)
+    if rc:
+        raise ValueError("orc_prior_half failed")
+    return [int(out[a]) for a in range(4)]
 
 
 def zoom_generic(sched: dict, dims, objective: Callable, init=None) -> dict:

@@ -540,6 +540,51 @@ int orc_cc_map(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
   return 0;
 }
 
+/* CC (Eq. 1) of voxel v against the listed entries idx[v*m + i] (a
+ * negative index gives 0): the plain definition at chosen points, used to
+ * check a search's answer where several answers are within tolerance. */
+int orc_cc_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr, const double* vr,
+              const double* vi, int32_t n_vox, int32_t m, const int64_t* idx, double* out,
+              int32_t n_threads) {
+  if (!grid || n_vox < 0 || m < 0 || (n_vox > 0 && m > 0 && (!vr || !vi || !idx || !out)))
+    return 1;
+  tables t;
+  int rc = tables_build(seq, grid, n_tr, &t);
+  if (rc) return rc;
+  const int64_t E = grid_size(grid);
+  for (int64_t q = 0; q < (int64_t)n_vox * m; ++q)
+    if (idx[q] >= E) {
+      tables_free(&t);
+      return 1;
+    }
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+  {
+    double* re = (double*)malloc(sizeof(double) * (size_t)(n_tr + 1));
+    double* im = (double*)malloc(sizeof(double) * (size_t)(n_tr + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+    for (int64_t q = 0; q < (int64_t)n_vox * m; ++q) {
+      const int64_t v = q / m;
+      if (idx[q] < 0) {
+        out[q] = 0.0;
+        continue;
+      }
+      entry_factors f;
+      tables_view(&t, idx[q], &f);
+      entry_samples(&t, &f, re, im);
+      out[q] = orc_cc(n_tr, vr + (size_t)v * n_tr, vi + (size_t)v * n_tr, re, im);
+    }
+    free(re);
+    free(im);
+  }
+  tables_free(&t);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* ZOOM (Theory: MRF ZOOM; Methods: Experiment 2 procedure).                 */
 /* ------------------------------------------------------------------------ */
@@ -626,6 +671,29 @@ int orc_schedule_paper(const orc_grid* g, const orc_seq* seq, orc_schedule* o) {
   o->starts[0][3] = g->n4 > 1 ? nearest(g->b1, g->n4, 1.0) : 0;
   o->pruned = 0;
   for (int a = 0; a < 4; ++a) o->prior_half[a] = -1;
+  return 0;
+}
+
+/* Neighbour prior (Methods, Experiment 3): the ranges T1p +- 3000 ms,
+ * T2p +- 800 ms and dfp +- 150 Hz around a neighbour's result, intersected
+ * with the search ranges. Here the half widths are given physically (B1 is
+ * an extension; its default is +- 0.3) and converted to index steps like
+ * every other physical step of the schedule: max(1, round_half_away(r /
+ * ((max - min)/(n - 1)))). An axis of fewer than two values, or a negative
+ * half width, gets -1 (the whole axis). */
+int orc_prior_half(const orc_grid* g, const double* half, int32_t* out) {
+  if (!g || !out) return 1;
+  static const double dflt[4] = {3000.0, 800.0, 150.0, 0.3};
+  const double* h = half ? half : dflt;
+  const double* ax[4] = {g->t1, g->t2, g->df, g->b1};
+  const int32_t n[4] = {g->n1, g->n2, g->n3, g->n4};
+  for (int a = 0; a < 4; ++a) {
+    if (n[a] < 2 || !(h[a] >= 0.0) || !ax[a]) {
+      out[a] = -1;
+      continue;
+    }
+    out[a] = idx_step(h[a], ax[a], n[a]);
+  }
   return 0;
 }
 

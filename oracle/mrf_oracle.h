@@ -108,9 +108,18 @@ int orc_cc_map(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
                const double* vr, const double* vi, int32_t n_vox, int64_t k0,
                int64_t count, double* out, int32_t n_threads);
 
+/* ---- Eq. 1 at listed entries: out[v*m + i] = CC(v, entry idx[v*m + i]),
+ * 0 for a negative index ---- */
+int orc_cc_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr, const double* vr,
+              const double* vi, int32_t n_vox, int32_t m, const int64_t* idx, double* out,
+              int32_t n_threads);
+
 /* ---- ZOOM ---- */
 int orc_schedule_paper(const orc_grid* grid, const orc_seq* seq,
                        orc_schedule* out);
+/* neighbour-prior half widths (Experiment 3) in index steps from physical
+ * half widths half[4] (T1 ms, T2 ms, df Hz, B1; NULL: 3000, 800, 150, 0.3) */
+int orc_prior_half(const orc_grid* grid, const double* half, int32_t* out);
 /* generic engine on a caller objective; the memo is per call. path (optional):
  * 5 ints per hill-climb move or scan update = new centre and the number of
  * evaluations made when it was reached */

@@ -137,6 +137,8 @@ _SIGS += [
      [C.POINTER(GridDesc), C.c_void_p, C.POINTER(ZoomSchedule)]),
     ("mrf_zoom_schedule_local", C.c_int,
      [C.POINTER(GridDesc), C.c_int32, C.POINTER(ZoomSchedule)]),
+    ("mrf_zoom_schedule_prior", C.c_int,
+     [C.POINTER(GridDesc), C.POINTER(C.c_double), C.POINTER(ZoomSchedule)]),
     ("mrf_zoom_workspace", C.c_int,
      [C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     ("mrf_zoom_search", C.c_int,

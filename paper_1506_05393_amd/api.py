@@ -556,19 +556,28 @@ class Server:
 
 
 def prior_half_widths(grid, t1_ms=3000.0, t2_ms=800.0, df_hz=150.0, b1=0.3) -> list:
-    """Neighbour-prior half-widths in index steps for physical ranges (the
-    Methods' Experiment 3 ranges by default; B1 +-0.3 for a B1 axis): per axis
-    max(1, round(r / ((max - min)/(n - 1)))), -1 for an axis of one value."""
-    gr = grid.grid if isinstance(grid, GridArg) else grid
-    out = []
-    for ax, r in ((gr.t1_ms, t1_ms), (gr.t2_ms, t2_ms), (gr.df_hz, df_hz), (gr.b1, b1)):
-        n = len(ax)
-        if n <= 1:
-            out.append(-1)
-            continue
-        step = (float(ax[-1]) - float(ax[0])) / (n - 1)
-        out.append(max(1, int(np.floor(r / step + 0.5))))
-    return out
+    """Neighbour-prior half widths in index steps for physical ranges (the
+    Methods' Experiment 3 ranges by default; B1 +-0.3 for a B1 axis), as
+    libmrf's mrf_zoom_schedule_prior converts them; -1 for an axis of one
+    value."""
+    lib = L.load()
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    half = (C.c_double * 4)(float(t1_ms), float(t2_ms), float(df_hz), float(b1))
+    s = L.ZoomSchedule()
+    L.check(lib.mrf_zoom_schedule_prior(g.ptr, half, C.byref(s)))
+    return [int(s.prior_half[a]) for a in range(4)]
+
+
+def schedule_with_prior(sched: dict, grid, half=None) -> dict:
+    """A copy of `sched` whose prior_half is set by mrf_zoom_schedule_prior
+    from physical half widths (T1 ms, T2 ms, df Hz, B1); None: the paper's
+    Experiment 3 ranges."""
+    lib = L.load()
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    s = schedule_from_dict(sched)
+    h = None if half is None else (C.c_double * 4)(*[float(x) for x in half])
+    L.check(lib.mrf_zoom_schedule_prior(g.ptr, h, C.byref(s)))
+    return schedule_to_dict(s)
 
 
 def zoom_search_lattice(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, width: int,

@@ -1143,6 +1143,25 @@ extern "C" int mrf_zoom_schedule_paper(const mrf_grid* g, const mrf_sequence* se
   return MRF_OK;
 }
 
+extern "C" int mrf_zoom_schedule_prior(const mrf_grid* g, const double* half,
+                                       mrf_zoom_schedule* o) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  MRF_CHECK_ARG(o, "NULL argument");
+  // Experiment 3: T1p +- 3000 ms, T2p +- 800 ms, dfp +- 150 Hz (B1 +- 0.3)
+  static const double kPaper[4] = {3000.0, 800.0, 150.0, 0.3};
+  const double* h = half ? half : kPaper;
+  const mrf_axis* ax[4] = {&g->t1_ms, &g->t2_ms, &g->df_hz, &g->b1};
+  int32_t out[4];
+  for (int a = 0; a < 4; ++a) {
+    MRF_CHECK_ARG(!std::isnan(h[a]), "half width %d is NaN", a);
+    // an axis of one value (or none) is searched whole; so is a negative width
+    out[a] = (ax[a]->n < 2 || h[a] < 0.0) ? -1 : h_idx_step(h[a], *ax[a]);
+  }
+  for (int a = 0; a < 4; ++a) o->prior_half[a] = out[a];
+  return MRF_OK;
+}
+
 extern "C" int mrf_zoom_schedule_local(const mrf_grid* g, int32_t outer_max,
                                        mrf_zoom_schedule* o) {
   int rc = check_grid(g);

@@ -72,3 +72,27 @@ def test_local_refine_schedule_builder():
     g4 = I.make_grid([300.0, 700.0], [30.0, 60.0], [0.0], [0.9, 1.0, 1.1])
     s4 = api.schedule_local(g4)
     assert [(x["kind"], x["axis0"]) for x in s4["stages"]] == [(4, 0), (3, 2), (3, 3)]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmrf.so not built")
+def test_prior_schedule_builder_matches_hand_worked_and_oracle(orc):
+    """mrf_zoom_schedule_prior (host only) gives the neighbour-prior half
+    widths of Experiment 3 worked by hand in the oracle pins, and the oracle's
+    conversion on random grids."""
+    import numpy as np
+    from paper_1506_05393_amd import api, workloads
+    from paper_1506_05393_amd import inputs as I
+    assert api.prior_half_widths(workloads.slice64().grid) == [300, 160, 150, -1]
+    assert api.prior_half_widths(workloads.volume(1, 8).grid) == [3000, 800, 300, 60]
+    assert api.prior_half_widths(workloads.small_dgs().grid) == [93, 82, 38, -1]
+    g = I.make_grid([100.0, 160.0, 220.0], [10.0, 20.0], [-60.0, 0.0, 60.0])
+    assert api.prior_half_widths(g, 150.0, 25.0, 150.0) == [3, 3, 3, -1]
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        ax = [np.cumsum(rng.uniform(0.5, 30.0, int(rng.integers(1, 12)))) for _ in range(3)]
+        b1 = np.cumsum(rng.uniform(0.001, 0.05, int(rng.integers(0, 6))))
+        g = I.make_grid(ax[0], ax[1], ax[2] - 50.0, b1 if len(b1) else None)
+        half = list(rng.uniform(-5.0, 400.0, 3)) + [float(rng.uniform(0.0, 0.3))]
+        assert api.prior_half_widths(g, *half) == orc.prior_half(g, half)
+    s = api.schedule_with_prior(dict(stages=[], starts=[[0, 0, 0, 0]]), workloads.slice64().grid)
+    assert s["prior_half"] == [300, 160, 150, -1]

@@ -46,6 +46,26 @@ def test_bruteforce_equals_numpy_reduction(orc):
     assert np.max(np.abs(res["pd"] - pd)) < 1e-12
 
 
+def test_cc_at_listed_entries_equals_numpy(orc):
+    """CC at listed entries (Eq. 1) = NumPy |Vn Dn^H| on the expm dictionary,
+    read at the listed columns; a negative index gives 0."""
+    seq, grid = _tiny()
+    D = np.stack([bloch_ref.simulate(seq, *map(float, grid.values(k))) for k in range(grid.size)])
+    rng = np.random.default_rng(15)
+    V = rng.normal(size=(5, 24)) + 1j * rng.normal(size=(5, 24))
+    V[:3] += 3.0 * D[rng.integers(0, grid.size, 3)]
+    idx = rng.integers(0, grid.size, (5, 7))
+    idx[1, 2] = -1
+    got = orc.cc_at(seq, grid, V, idx, threads=2)
+    S = np.abs((V / np.linalg.norm(V, axis=1, keepdims=True))
+               @ (D / np.linalg.norm(D, axis=1, keepdims=True)).conj().T)
+    want = np.take_along_axis(S, np.maximum(idx, 0), axis=1)
+    want[1, 2] = 0.0
+    assert np.max(np.abs(got - want)) < 1e-13
+    with pytest.raises(ValueError):
+        orc.cc_at(seq, grid, V, np.full((5, 1), grid.size))
+
+
 def test_bruteforce_noise_free_on_grid_is_exact(orc):
     """On-grid noise-free fingerprints return the truth with CC = 1 (Experiment 2)."""
     seq, grid = _tiny()
@@ -374,3 +394,70 @@ def test_lattice_prior_pass_structure(orc):
     again = orc.zoom(seq, grid, sched, V[rest], init=init)
     assert np.array_equal(res["idx"][rest], again["idx"])
     assert np.array_equal(res["n_sim"][rest], again["n_sim"])
+
+
+def _calls_of_one_scan(orc, stage, n, centre):
+    sched = dict(stages=[stage], starts=[[0, 0, centre, 0]])
+    r = orc.zoom_generic(sched, (1, 1, n, 1), lambda a, b, c, d: -abs(c - centre))
+    return [c[2] for c in r["calls"]]
+
+
+def test_scan_hops_non_integer_hop_hand_listed(orc):
+    """Methods, Experiment 2 step 1(c): the +-k omega hops land on
+    c + round(k * hop) with halves rounded away from zero. Hand-worked point
+    lists (the centre is evaluated first, then the targets in increasing
+    index order): a floor, a truncation or round-half-even would list other
+    points."""
+    # hop 23.8 about 50 on 101 values: +-23.8 -> +-24, +-47.6 -> +-48, +-71.4 out
+    assert _calls_of_one_scan(orc, dict(kind=orc.SCAN_HOPS, axis0=2, hop=23.8), 101, 50) == \
+        [50, 2, 26, 74, 98]
+    # hop 2.5 about 10 on 21 values: 2.5 -> 3, 5, 7.5 -> 8, 10, 12.5 -> 13 (out)
+    assert _calls_of_one_scan(orc, dict(kind=orc.SCAN_HOPS, axis0=2, hop=2.5), 21, 10) == \
+        [10, 0, 2, 5, 7, 13, 15, 18, 20]
+    # the targets are offsets from the centre, clipped at each end separately
+    assert _calls_of_one_scan(orc, dict(kind=orc.SCAN_HOPS, axis0=2, hop=1.5), 9, 2) == \
+        [2, 0, 4, 5, 7, 8]
+    # hops below one index step are taken as one step (every index in range)
+    assert _calls_of_one_scan(orc, dict(kind=orc.SCAN_HOPS, axis0=2, hop=0.4), 5, 1) == \
+        [1, 0, 2, 3, 4]
+
+
+def test_scan_window_truncation_and_ties(orc):
+    """Methods, Experiment 2 step 1(b)/3: a window scan visits c + m s for
+    0 < |m s| <= w, so a window of 7 at step 3 reaches +-6 and not +-9; the
+    centre is kept on ties, and among equal candidates the lowest index
+    wins."""
+    st = dict(kind=orc.SCAN_WINDOW, axis0=2, step0=3, window=7)
+    assert _calls_of_one_scan(orc, st, 40, 20) == [20, 14, 17, 23, 26]
+    # clipped at the low end: 2 - 3 and 2 - 6 are outside
+    assert _calls_of_one_scan(orc, st, 40, 2) == [2, 5, 8]
+    sched = dict(stages=[st], starts=[[0, 0, 20, 0]])
+    run = lambda vals: orc.zoom_generic(sched, (1, 1, 40, 1),
+                                        lambda a, b, c, d: vals.get(c, 0.0))["idx"][2]
+    assert run({20: 1.0, 23: 1.0}) == 20           # a tie with the centre keeps it
+    assert run({20: 0.5, 17: 1.0, 26: 1.0}) == 17  # equal candidates: lowest index
+    assert run({20: 0.5, 26: 1.0, 14: 0.9}) == 26
+    # a window narrower than the step scans nothing but the centre
+    assert _calls_of_one_scan(orc, dict(kind=orc.SCAN_WINDOW, axis0=2, step0=3, window=2),
+                              40, 20) == [20]
+
+
+def test_prior_half_widths_hand_worked(orc):
+    """Methods, Experiment 3: ranges T1p +- 3000 ms, T2p +- 800 ms,
+    dfp +- 150 Hz around the neighbour's result, in index steps of each
+    grid, worked by hand:
+      slice grid (T1 step 10, T2 step 5, df step 1): 300, 160, 150;
+      volume grid (T1 1, T2 1, df 0.5, B1 0.005 with +- 0.3): 3000, 800, 300, 60;
+      small grid (T1 1900/59 = 32.20 ms, T2 380/39 = 9.744 ms, df 4 Hz):
+        3000/32.20 = 93.2 -> 93, 800/9.744 = 82.1 -> 82, 150/4 = 37.5 -> 38;
+      halves round away from zero: 150 / 60 = 2.5 -> 3, 25 / 10 = 2.5 -> 3;
+      a width below half a step still opens one step."""
+    from paper_1506_05393_amd import workloads
+    assert orc.prior_half(workloads.slice64().grid) == [300, 160, 150, -1]
+    assert orc.prior_half(workloads.volume(1, 8).grid) == [3000, 800, 300, 60]
+    assert orc.prior_half(workloads.small_dgs().grid) == [93, 82, 38, -1]
+    g = I.make_grid([100.0, 160.0, 220.0], [10.0, 20.0], [-60.0, 0.0, 60.0])
+    assert orc.prior_half(g, [150.0, 25.0, 150.0, 0.3]) == [3, 3, 3, -1]
+    assert orc.prior_half(g, [1.0, -1.0, 0.0, 0.3]) == [1, -1, 1, -1]
+    g1 = I.make_grid([100.0], [10.0, 20.0], [0.0])
+    assert orc.prior_half(g1) == [-1, 80, -1, -1]
