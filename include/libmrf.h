@@ -233,6 +233,29 @@ int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* dict, const void
                          int64_t* topk_idx, float* topk_cc, void* workspace,
                          size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): FP32 brute
+ * force exactly as mrf_match_bruteforce with an MRF_F32 dictionary (same
+ * kernels, bitwise-equal outputs), with its workspace in a static device
+ * array of mrf_static_scratch_bytes() bytes (64 MiB) that the library holds
+ * on each GPU it runs on until the process ends. The call allocates nothing:
+ * no hipMalloc/hipFree, no library allocation, no profiling events.
+ * Arguments as mrf_match_bruteforce (vox, out, topk_idx/topk_cc device
+ * memory, caller-owned). Every call on one GPU shares that GPU's array and
+ * leaves its contents behind; nothing in it needs to start at zero (the
+ * packing kernel writes every operand slot and the GEMM every candidate list
+ * before they are read). Calls that overlap on one GPU (two streams, two
+ * threads) race on the array: serialise them.
+ * Errors: a BF16 or rows dictionary, or sizes whose workspace
+ * (mrf_match_workspace) exceeds the array -> MRF_ERR_INVALID with the bytes
+ * needed (a 64 x 64 slice at N = 1000 fits); otherwise as
+ * mrf_match_bruteforce. */
+size_t mrf_static_scratch_bytes(void);
+int mrf_match_bruteforce_noalloc(mrf_context* ctx, const mrf_dict_view* dict, const void* vox,
+                                 int32_t n_vox, int64_t ld_vox, int32_t top_k,
+                                 mrf_result_view out, int64_t* topk_idx, float* topk_cc,
+                                 void* stream);
+
 /* ------------------------------------------------------------------------
  * MRF-ZOOM (Theory: MRF ZOOM; Methods: Experiment 2 zooming steps 1-5;
  * Experiment 3 neighbour prior).

@@ -80,6 +80,10 @@ _SIGS = [
      [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
       C.POINTER(GridDesc), ResultView, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("mrf_static_scratch_bytes", C.c_size_t, []),
+    ("mrf_match_bruteforce_noalloc", C.c_int,
+     [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, ResultView,
+      C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mrf_probe_mfma", C.c_int,
      [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p]),
     ("mrf_probe_write", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]),

@@ -312,6 +312,30 @@ def match_bruteforce(ctx: Context, d: Dictionary, vox: torch.Tensor, top_k: int 
     return r
 
 
+def match_bruteforce_noalloc(ctx: Context, d: Dictionary, vox: torch.Tensor, top_k: int = 1,
+                             n_tr: Optional[int] = None, with_topk: bool = False,
+                             out: Optional[dict] = None, stream=None) -> dict:
+    """FP32 brute force through the allocation-free entry point (workspace in
+    the library's static device array). Outputs as match_bruteforce; pass
+    `out` (and preallocated topk tensors in it) to allocate nothing here."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda:
+        raise ValueError("vox must be a complex64 CUDA tensor")
+    if vox.stride(1) != 1:
+        raise ValueError("vox rows must be contiguous")
+    n_vox = vox.shape[0]
+    v = d.view(n_tr)
+    r = out if out is not None else _result_tensors(n_vox, ctx.device)
+    if with_topk and "topk_idx" not in r:
+        r["topk_idx"] = torch.empty((n_vox, top_k), dtype=torch.int64, device=ctx.device)
+        r["topk_cc"] = torch.empty((n_vox, top_k), dtype=torch.float32, device=ctx.device)
+    tk_i, tk_c = (r.get("topk_idx"), r.get("topk_cc")) if with_topk else (None, None)
+    L.check(ctx._lib.mrf_match_bruteforce_noalloc(
+        ctx.handle, C.byref(v), vox.data_ptr(), n_vox, vox.stride(0), int(top_k),
+        _result_view(r), tk_i.data_ptr() if tk_i is not None else None,
+        tk_c.data_ptr() if tk_c is not None else None, _stream_ptr(stream)))
+    return r
+
+
 # ---------------------------------------------------------------- ZOOM -----
 
 STAGE_KINDS = {"scan_stride": 0, "scan_window": 1, "scan_hops": 2, "zoom1": 3, "zoom2": 4}

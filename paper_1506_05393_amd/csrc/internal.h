@@ -111,4 +111,7 @@ int check_grid(const mrf_grid* g);
 int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t stream,
                const Tables** out);
 int64_t grid_size_checked(const mrf_grid* g);
+// Looks up the device address of this device's static scratch (scratch.hip);
+// called once per device with the device current.
+int scratch_setup(int device);
 }  // namespace mrf

@@ -431,26 +431,20 @@ extern "C" int mrf_match_workspace(mrf_context* ctx, const mrf_dict_view* d, int
   return MRF_OK;
 }
 
-extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, const void* vox,
-                                    int32_t n_vox, int64_t ld_vox, int32_t top_k,
-                                    const mrf_sequence* seq, const mrf_grid* grid,
-                                    mrf_result_view out, int64_t* topk_idx, float* topk_cc,
-                                    void* workspace, size_t ws_bytes, void* stream) {
-  MRF_CHECK_ARG(ctx != nullptr, "context is NULL");
-  int rc = check_view(d);
-  if (rc) return rc;
-  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
-  MRF_CHECK_ARG(top_k >= 1 && top_k <= KK_MAX, "top_k must be in [1, %d]", KK_MAX);
-  if (n_vox == 0) return MRF_OK;
-  MRF_CHECK_ARG(vox != nullptr, "vox is NULL");
-  MRF_CHECK_ARG(ld_vox >= d->n_tr, "ld_vox (%lld) must be >= n_tr (%d)", (long long)ld_vox, d->n_tr);
-  MRF_CHECK_ARG(out.idx != nullptr, "out.idx is NULL");
-  MRF_CHECK_ARG(workspace != nullptr, "workspace is NULL");
-  hipStream_t st = (hipStream_t)stream;
-  if (d->dtype == MRF_BF16) {
-    return match_bf16(ctx, d, vox, n_vox, ld_vox, top_k, seq, grid, out, topk_idx, topk_cc,
-                      workspace, ws_bytes, st);
-  }
+namespace mrf {
+
+size_t match_f32_workspace_bytes(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu) {
+  return make_plan(d, n_vox, top_k, n_cu).total;
+}
+
+// FP32 brute force (K2 packing, K3 GEMM with the fused top-k, K4 merge, PD of
+// the best entry) with the caller's workspace. The arguments have been
+// checked by the entry point (view, sizes, pointers). `profile` = false keeps
+// the launches free of event creation (the allocation-free entry point).
+int match_f32_run(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_t n_vox,
+                  int64_t ld_vox, int32_t top_k, mrf_result_view out, int64_t* topk_idx,
+                  float* topk_cc, void* workspace, size_t ws_bytes, hipStream_t st,
+                  bool profile) {
   const Plan p = make_plan(d, n_vox, top_k, ctx->n_cu);
   MRF_CHECK_ARG(ws_bytes >= p.total, "workspace too small (%zu < %zu bytes)", ws_bytes, p.total);
   char* ws = (char*)workspace;
@@ -460,9 +454,10 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   int32_t* pi = (int32_t*)(ws + p.off_pi);
   float* bs = (float*)(ws + p.off_bs);
   int32_t* bi = (int32_t*)(ws + p.off_bi);
+  mrf_context* pctx = profile ? ctx : nullptr;
 
   {
-    ProfScope prof(ctx, "k_pack_f32", st);
+    ProfScope prof(pctx, "k_pack_f32", st);
     hipLaunchKernelGGL(k_pack_f32_3m, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox,
                        ld_vox, n_vox, d->n_tr, p.n_tr_pad, p.n_vox_pad, A, vn);
   }
@@ -486,14 +481,15 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   const int grid_wg = p.n_row_tiles * p.n_chunks;
   const size_t lds = sizeof(float) * (2 * 3 * KC * BV3 + 2 * 2 * KC * BN) +
                      (sizeof(float) + sizeof(int32_t)) * 4 * 32 * KK_MAX;
-  static bool attr3_set = false;
-  if (!attr3_set) {
-    MRF_HIP(hipFuncSetAttribute((const void*)k_match_f32_3m,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr3_set = true;
-  }
+  static std::once_flag attr3_once;
+  hipError_t attr_rc = hipSuccess;
+  std::call_once(attr3_once, [&]() {
+    attr_rc = hipFuncSetAttribute((const void*)k_match_f32_3m,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  });
+  MRF_HIP(attr_rc);
   {
-    ProfScope prof(ctx, "k_match_f32", st);
+    ProfScope prof(pctx, "k_match_f32", st);
     hipLaunchKernelGGL(k_match_f32_3m, dim3(grid_wg), dim3(256), lds, st, a);
   }
   MRF_HIP(hipGetLastError());
@@ -514,7 +510,7 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
   m.margin = out.margin;
   m.topk_idx = topk_idx;
   m.topk_cc = topk_cc;
-  rc = launch_merge(ctx, m, st);
+  int rc = launch_merge(pctx, m, st);
   if (rc) return rc;
   if (out.pd_re || out.pd_im) {
     hipLaunchKernelGGL(k_pd_f32, dim3(n_vox), dim3(64), 0, st, (const float2*)vox, ld_vox, n_vox,
@@ -523,4 +519,55 @@ extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, co
     MRF_HIP(hipGetLastError());
   }
   return MRF_OK;
+}
+
+int match_f32_scratch(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_t n_vox,
+                      int64_t ld_vox, int32_t top_k, mrf_result_view out, int64_t* topk_idx,
+                      float* topk_cc, void* scratch, size_t scratch_bytes, hipStream_t st) {
+  MRF_CHECK_ARG(ctx != nullptr, "context is NULL");
+  int rc = check_view(d);
+  if (rc) return rc;
+  MRF_CHECK_ARG(d->dtype == MRF_F32,
+                "the allocation-free brute force takes FP32 dictionaries only (BF16 "
+                "re-scoring builds step tables on first use)");
+  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
+  MRF_CHECK_ARG(top_k >= 1 && top_k <= KK_MAX, "top_k must be in [1, %d]", KK_MAX);
+  if (n_vox == 0) return MRF_OK;
+  MRF_CHECK_ARG(vox != nullptr, "vox is NULL");
+  MRF_CHECK_ARG(ld_vox >= d->n_tr, "ld_vox (%lld) must be >= n_tr (%d)", (long long)ld_vox, d->n_tr);
+  MRF_CHECK_ARG(out.idx != nullptr, "out.idx is NULL");
+  MRF_CHECK_ARG(scratch != nullptr, "no static scratch on device %d", ctx->device);
+  const size_t need = match_f32_workspace_bytes(d, n_vox, top_k, ctx->n_cu);
+  MRF_CHECK_ARG(need <= scratch_bytes,
+                "%d voxels x %d readouts (top_k %d) need %zu bytes of scratch, the static "
+                "scratch holds %zu: match fewer voxels per call", n_vox, d->n_tr, top_k, need,
+                scratch_bytes);
+  return match_f32_run(ctx, d, vox, n_vox, ld_vox, top_k, out, topk_idx, topk_cc, scratch,
+                       scratch_bytes, st, false);
+}
+
+}  // namespace mrf
+
+extern "C" int mrf_match_bruteforce(mrf_context* ctx, const mrf_dict_view* d, const void* vox,
+                                    int32_t n_vox, int64_t ld_vox, int32_t top_k,
+                                    const mrf_sequence* seq, const mrf_grid* grid,
+                                    mrf_result_view out, int64_t* topk_idx, float* topk_cc,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  MRF_CHECK_ARG(ctx != nullptr, "context is NULL");
+  int rc = check_view(d);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_vox >= 0, "n_vox must be >= 0");
+  MRF_CHECK_ARG(top_k >= 1 && top_k <= KK_MAX, "top_k must be in [1, %d]", KK_MAX);
+  if (n_vox == 0) return MRF_OK;
+  MRF_CHECK_ARG(vox != nullptr, "vox is NULL");
+  MRF_CHECK_ARG(ld_vox >= d->n_tr, "ld_vox (%lld) must be >= n_tr (%d)", (long long)ld_vox, d->n_tr);
+  MRF_CHECK_ARG(out.idx != nullptr, "out.idx is NULL");
+  MRF_CHECK_ARG(workspace != nullptr, "workspace is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (d->dtype == MRF_BF16) {
+    return match_bf16(ctx, d, vox, n_vox, ld_vox, top_k, seq, grid, out, topk_idx, topk_cc,
+                      workspace, ws_bytes, st);
+  }
+  return match_f32_run(ctx, d, vox, n_vox, ld_vox, top_k, out, topk_idx, topk_cc, workspace,
+                       ws_bytes, st, true);
 }

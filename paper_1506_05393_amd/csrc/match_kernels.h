@@ -29,3 +29,18 @@ struct MergeArgs {
 };
 int launch_merge(mrf_context* ctx, const MergeArgs& m, hipStream_t st);
 }  // namespace mrf
+
+namespace mrf {
+// FP32 brute force on a caller-provided buffer (the pieces of
+// mrf_match_bruteforce's FP32 path). match_f32_run expects checked
+// arguments; match_f32_scratch checks them itself (FP32 views only) and
+// refuses a buffer smaller than the plan needs.
+size_t match_f32_workspace_bytes(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu);
+int match_f32_run(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_t n_vox,
+                  int64_t ld_vox, int32_t top_k, mrf_result_view out, int64_t* topk_idx,
+                  float* topk_cc, void* workspace, size_t ws_bytes, hipStream_t st,
+                  bool profile);
+int match_f32_scratch(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_t n_vox,
+                      int64_t ld_vox, int32_t top_k, mrf_result_view out, int64_t* topk_idx,
+                      float* topk_cc, void* scratch, size_t scratch_bytes, hipStream_t st);
+}  // namespace mrf

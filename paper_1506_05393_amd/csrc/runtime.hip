@@ -372,6 +372,8 @@ int mrf_context_create(int device, mrf_context** out) {
   MRF_HIP(hipSetDevice(device));
   hipDeviceProp_t prop;
   MRF_HIP(hipGetDeviceProperties(&prop, device));
+  int rc = scratch_setup(device);
+  if (rc) return rc;
   mrf_context* c = new (std::nothrow) mrf_context();
   if (!c) {
     set_error("out of host memory");
