@@ -8,7 +8,11 @@
  * Ownership: the caller owns every device array passed in (voxels,
  * dictionaries, outputs, workspaces) and libmrf never frees them. libmrf owns
  * the opaque handles (context, sequence with its resident step tables,
- * schedule, server). Device pointers are plain hipMalloc'ed (or torch) device
+ * server). A ZOOM schedule is a plain struct (mrf_zoom_schedule) that the
+ * caller allocates and the schedule builders fill in place: it holds no
+ * pointers or resources, so there is no destroy call for it (a deviation
+ * from an opaque-handle design with mrf_zoom_schedule_destroy). Device
+ * pointers are plain hipMalloc'ed (or torch) device
  * memory on the context's device; host pointers are ordinary host memory.
  *
  * Streams: `void* stream` is a hipStream_t (NULL = the default stream). All
@@ -219,9 +223,12 @@ typedef struct {
 int mrf_match_workspace(mrf_context* ctx, const mrf_dict_view* dict, int32_t n_vox,
                         int32_t top_k, size_t* bytes);
 
-/* top_k in [1, 64]: the kept candidate list per voxel (at least 2 internally
- * for the margin). With a BF16 dictionary top_k must be >= 2 and seq/grid
- * are required: the top_k BF16 candidates of each voxel are re-simulated in
+/* top_k: the kept candidate list per voxel (at least 2 internally for the
+ * margin). FP32 dictionaries: top_k in [1, 64] (lists longer than 16 run a
+ * GEMM instance with 64-entry lists in LDS, one workgroup per CU instead of
+ * two). BF16 dictionaries: top_k in [2, 8] (the GEMM's four-stage LDS ring
+ * leaves room for lists of 8) and seq/grid are required: the top_k BF16
+ * candidates of each voxel are re-simulated in
  * FP32 (the values an FP32 dictionary stores) and re-scored with an FP32 dot
  * product under compensated summation (error ~1 FP32 ulp of the sum), and the
  * best of them is returned. topk_idx /

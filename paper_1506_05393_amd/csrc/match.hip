@@ -24,7 +24,11 @@ constexpr int BN = 128;      // entries per tile
 // took a larger share: 3.15 s instead of 2.85 s on the slice.
 constexpr int KC = 16;
 constexpr int NLD = KC / 4;  // float4 of B each thread moves per chunk
-constexpr int KK_MAX = 16;   // longest candidate list kept in the epilogue
+// Candidate lists kept in the epilogue: up to 16 in the default kernel (72 KB
+// of LDS, two workgroups per CU); longer lists (up to 64, the boundary's
+// limit) take a kernel instance with 64-entry lists (120 KB, one per CU).
+constexpr int KK_SHORT = 16;
+constexpr int KK_MAX = 64;
 constexpr int kWgPerCu = 2;  // resident workgroups per CU (LDS allows two)
 
 // ---------------------------------------------------------------------------
@@ -107,6 +111,7 @@ __device__ __forceinline__ void store_chunk3(float* As, float* Bs, int buf, int 
   }
 }
 
+template <int KL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_match_f32_3m(
     Match3Args a) {
   // XCD-aware mapping: consecutive workgroup ids go to different XCDs
@@ -122,8 +127,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   extern __shared__ __align__(16) unsigned char smem[];
   float* As = (float*)smem;                    // [2 buf][3 g][KC][BV3]
   float* Bs = As + 2 * 3 * KC * BV3;           // [2 buf][2 g][KC][BN]
-  float* Ls = Bs + 2 * 2 * KC * BN;            // [4 waves][32 voxels][KK_MAX]
-  int32_t* Li = (int32_t*)(Ls + 4 * 32 * KK_MAX);
+  float* Ls = Bs + 2 * 2 * KC * BN;            // [4 waves][32 voxels][KL]
+  int32_t* Li = (int32_t*)(Ls + 4 * 32 * KL);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -133,9 +138,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int kk = a.kk;
   const int vox0 = rt * BV3;
 
-  float* myLs = Ls + wave * 32 * KK_MAX;
-  int32_t* myLi = Li + wave * 32 * KK_MAX;
-  for (int i = lane; i < 32 * KK_MAX; i += 64) {
+  float* myLs = Ls + wave * 32 * KL;
+  int32_t* myLi = Li + wave * 32 * KL;
+  for (int i = lane; i < 32 * KL; i += 64) {
     myLs[i] = -1.0f;
     myLi[i] = 0x7fffffff;
   }
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const float im = t3[bn][r] - t1[bn][r] + t2[bn][r];
         const float sc = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
         // this lane's voxel: the k-th best so far (read from its list)
-        const float thr = myLs[(8 * (r >> 2) + 4 * h + (r & 3)) * KK_MAX + kk - 1];
+        const float thr = myLs[(8 * (r >> 2) + 4 * h + (r & 3)) * KL + kk - 1];
         const bool cand = sc > thr;
         uint64_t m = __ballot(cand);
         while (m) {
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           const float sv = __shfl(sc, src);
           const int32_t e = __shfl(ecol[bn], src);
           const int vl = 8 * (r >> 2) + 4 * (src >> 5) + (r & 3);
-          list_insert(myLs + vl * KK_MAX, myLi + vl * KK_MAX, kk, lane, sv, e);
+          list_insert(myLs + vl * KL, myLi + vl * KL, kk, lane, sv, e);
         }
       }
     }
@@ -223,8 +228,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int v = vox0 + wr * 32 + vl;
     if (v < a.v_pad) {
       const int64_t o = (((int64_t)chunk * 2 + wc) * a.v_pad + v) * kk + p;
-      a.part_s[o] = myLs[vl * KK_MAX + p];
-      a.part_i[o] = myLi[vl * KK_MAX + p];
+      a.part_s[o] = myLs[vl * KL + p];
+      a.part_i[o] = myLi[vl * KL + p];
     }
   }
 }
@@ -268,9 +273,9 @@ __global__ __launch_bounds__(64) void k_pack_f32_3m(const float2* __restrict__ v
 __global__ __launch_bounds__(64) void k_merge(MergeArgs a) {
   const int v = blockIdx.x * 64 + threadIdx.x;
   if (v >= a.n_vox) return;
-  float ls[KK_MAX];
-  int32_t li[KK_MAX];
-  for (int p = 0; p < KK_MAX; ++p) {
+  float ls[KK_SHORT];
+  int32_t li[KK_SHORT];
+  for (int p = 0; p < KK_SHORT; ++p) {
     ls[p] = -1.0f;
     li[p] = 0x7fffffff;
   }
@@ -303,6 +308,67 @@ __global__ __launch_bounds__(64) void k_merge(MergeArgs a) {
     if (a.topk_idx)
       a.topk_idx[(int64_t)v * a.top_k + p] = li[p] == 0x7fffffff ? -1 : a.entry_base + li[p];
     if (a.topk_cc) a.topk_cc[(int64_t)v * a.top_k + p] = sqrtf(fmaxf(ls[p], 0.0f));
+  }
+}
+
+// K4 for lists longer than 16: one wave per voxel, lane p holding entry p of
+// the running list. Each chunk's sorted list is read by the wave at once and
+// its entries are inserted in order with the wave-parallel shift of
+// list_insert, stopping at the first one that cannot enter. The result, the
+// best kk by (score desc, index asc), is the same as k_merge's.
+__global__ __launch_bounds__(64) void k_merge_wave(MergeArgs a) {
+  const int v = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (v >= a.n_vox) return;
+  const int kk = a.kk;
+  float cs = -1.0f;
+  int32_t ci = 0x7fffffff;
+  for (int l = 0; l < a.n_lists; ++l) {
+    const int64_t o = ((int64_t)l * a.n_vox_pad + v) * kk;
+    float s = -1.0f;
+    int32_t e = 0x7fffffff;
+    if (lane < kk) {
+      s = a.part_s[o + lane];
+      e = a.part_i[o + lane];
+    }
+    for (int p = 0; p < kk; ++p) {
+      const float sp = __shfl(s, p);
+      const int32_t ep = __shfl(e, p);
+      if (ep == 0x7fffffff) break;
+      const float ls_last = __shfl(cs, kk - 1);
+      const int32_t li_last = __shfl(ci, kk - 1);
+      if (!beats(sp, ep, ls_last, li_last)) break;  // the chunk's list is sorted
+      const bool ahead = lane < kk && beats(cs, ci, sp, ep);
+      const int q = __popcll(__ballot(ahead));
+      const float ps = __shfl_up(cs, 1);
+      const int32_t pi = __shfl_up(ci, 1);
+      if (lane < kk) {
+        if (lane == q) {
+          cs = sp;
+          ci = ep;
+        } else if (lane > q) {
+          cs = ps;
+          ci = pi;
+        }
+      }
+    }
+  }
+  if (lane < kk) {
+    a.best_s[(int64_t)v * kk + lane] = cs;
+    a.best_i[(int64_t)v * kk + lane] = ci;
+  }
+  const float s0 = __shfl(cs, 0), s1 = __shfl(cs, 1);
+  const int32_t i0 = __shfl(ci, 0), i1 = __shfl(ci, 1);
+  if (lane == 0) {
+    const float c1 = sqrtf(fmaxf(s0, 0.0f));
+    if (a.idx) a.idx[v] = i0 == 0x7fffffff ? -1 : a.entry_base + i0;
+    if (a.cc) a.cc[v] = c1;
+    if (a.margin) a.margin[v] = i1 == 0x7fffffff ? INFINITY : c1 - sqrtf(fmaxf(s1, 0.0f));
+  }
+  if (lane < a.top_k) {
+    if (a.topk_idx)
+      a.topk_idx[(int64_t)v * a.top_k + lane] = ci == 0x7fffffff ? -1 : a.entry_base + ci;
+    if (a.topk_cc) a.topk_cc[(int64_t)v * a.top_k + lane] = sqrtf(fmaxf(cs, 0.0f));
   }
 }
 
@@ -347,7 +413,10 @@ __global__ __launch_bounds__(64) void k_pd_f32(const float2* __restrict__ vox, i
 int launch_merge(mrf_context* ctx, const MergeArgs& m, hipStream_t st) {
   {
     ProfScope prof(ctx, "k_merge", st);
-    hipLaunchKernelGGL(k_merge, dim3((m.n_vox + 63) / 64), dim3(64), 0, st, m);
+    if (m.kk <= KK_SHORT)
+      hipLaunchKernelGGL(k_merge, dim3((m.n_vox + 63) / 64), dim3(64), 0, st, m);
+    else
+      hipLaunchKernelGGL(k_merge_wave, dim3(m.n_vox), dim3(64), 0, st, m);
   }
   MRF_HIP(hipGetLastError());
   return MRF_OK;
@@ -479,18 +548,22 @@ int match_f32_run(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int
   a.part_s = ps;
   a.part_i = pi;
   const int grid_wg = p.n_row_tiles * p.n_chunks;
+  const bool longl = p.kk > KK_SHORT;
   const size_t lds = sizeof(float) * (2 * 3 * KC * BV3 + 2 * 2 * KC * BN) +
-                     (sizeof(float) + sizeof(int32_t)) * 4 * 32 * KK_MAX;
-  static std::once_flag attr3_once;
+                     (sizeof(float) + sizeof(int32_t)) * 4 * 32 * (longl ? KK_MAX : KK_SHORT);
+  const void* kfn = longl ? (const void*)k_match_f32_3m<KK_MAX> : (const void*)k_match_f32_3m<KK_SHORT>;
+  static std::once_flag attr_once[2];
   hipError_t attr_rc = hipSuccess;
-  std::call_once(attr3_once, [&]() {
-    attr_rc = hipFuncSetAttribute((const void*)k_match_f32_3m,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  std::call_once(attr_once[longl ? 1 : 0], [&]() {
+    attr_rc = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   });
   MRF_HIP(attr_rc);
   {
     ProfScope prof(pctx, "k_match_f32", st);
-    hipLaunchKernelGGL(k_match_f32_3m, dim3(grid_wg), dim3(256), lds, st, a);
+    if (longl)
+      hipLaunchKernelGGL(k_match_f32_3m<KK_MAX>, dim3(grid_wg), dim3(256), lds, st, a);
+    else
+      hipLaunchKernelGGL(k_match_f32_3m<KK_SHORT>, dim3(grid_wg), dim3(256), lds, st, a);
   }
   MRF_HIP(hipGetLastError());
 

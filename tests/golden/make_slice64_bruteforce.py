@@ -40,13 +40,15 @@ def main():
                    "workload's grid (T1 100:10:4000, T2 10:5:2000, df -40:1:40; N = 1000, "
                    "sequence seed 1). Rows 0-63: the noisy subset (phantom seed 101, SNR 30, "
                    "voxels drawn with PCG64(2024)); rows 64-79: noise-free fingerprints at the "
-                   "grid values nearest to 16 phantom voxels (PCG64(2025)). Written by "
+                   "grid values nearest to 16 phantom voxels (PCG64(2025)); rows 80-95: "
+                   "noise-free fingerprints at grid points of the short-relaxation corner "
+                   "T1 100-500 ms, T2 10-60 ms (PCG64(2026)). Written by "
                    "tests/golden/make_slice64_bruteforce.py from the oracle only."),
         "workload": w.name,
         "inputs_sha256": S.digest(V),
         "noisy_voxels": [int(x) for x in S.noisy_voxels(w.phantom.n_vox)],
         "ongrid_voxels": [int(x) for x in S.ongrid_truths(w)[0]],
-        "ongrid_truth_idx": [int(x) for x in truth],
+        "truth_idx": [int(x) for x in truth],
         "top_k": TOP_K,
         "idx": [int(x) for x in r["idx"]],
         "cc": [float(x) for x in r["cc"]],

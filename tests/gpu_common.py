@@ -24,3 +24,34 @@ def oracle_fingerprints(orc, seq, ph, voxels=None, n_tr=None, noise=True):
 
 def to_dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def check_cc_at_index(orc, seq, grid, V, idx, cc, tol, label):
+    """Every voxel: the oracle's CC (Eq. 1, FP64) of the entry the GPU
+    returned equals the CC the GPU reported, within tol. Returns the oracle
+    values."""
+    at = orc.cc_at(seq, grid, V, np.asarray(idx, np.int64)[:, None])[:, 0]
+    d = np.abs(at - np.asarray(cc, np.float64))
+    print(f"{label}: oracle CC at the GPU index vs GPU CC, max |d| {d.max():.2e} "
+          f"over {len(d)} voxels")
+    assert float(d.max()) < tol, (float(d.max()), int(np.argmax(d)))
+    return at
+
+
+def unit_stencil(grid, idx, axes_steps):
+    """Grid indices of the neighbours of each entry along the given
+    (axis, step) moves, one column per move; -1 outside the grid."""
+    dims = grid.shape
+    u = np.stack(grid.unravel(np.asarray(idx, np.int64)), axis=1)
+    cols = []
+    for move in axes_steps:
+        n = u.copy()
+        for ax, st in move:
+            n[:, ax] += st
+        ok = np.all((n >= 0) & (n < np.array(dims)), axis=1)
+        cols.append(np.where(ok, grid.ravel(n[:, 0], n[:, 1], n[:, 2], n[:, 3]), -1))
+    return np.stack(cols, axis=1)
+
+
+# the 8 unit neighbours of a 2-D zoom on (T1, T2)
+UNIT_T1T2 = [[(0, a), (1, b)] for a in (-1, 0, 1) for b in (-1, 0, 1) if (a, b) != (0, 0)]

@@ -3,11 +3,15 @@
 Bar: on voxels whose oracle top-2 CC margin exceeds 1e-5 the GPU returns the
 oracle's argmax index, and |CC| agrees within 1e-5 on every voxel.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_1506_05393_amd import inputs as I
-from tests.gpu_common import need_gpu, oracle_fingerprints, to_dev, torch
+from tests.gpu_common import (check_cc_at_index, need_gpu, oracle_fingerprints, to_dev, torch,
+                              unit_stencil)
 
 pytestmark = pytest.mark.gpu
 CC_TOL = 1e-5
@@ -63,6 +67,32 @@ def test_bruteforce_f32_small_workload(ctx, orc, on_grid):
     assert bool(np.all(np.diff(tkc, axis=1) <= 0))
     tk_err = float(np.abs(tkc - ref["topk_cc"]).max())
     assert tk_err < CC_TOL, tk_err
+
+
+def test_bruteforce_f32_long_candidate_lists(ctx, orc):
+    """top_k up to 64 (a GEMM instance with 64-entry lists, merged one wave
+    per voxel): the list's CCs rank by rank and the oracle's CC of every
+    listed entry within 1e-5, the argmax bar, and its first 16 entries equal
+    bit for bit to the 16-entry instance's list."""
+    from paper_1506_05393_amd import api, workloads
+    w = workloads.small_dgs(False)
+    V = oracle_fingerprints(orc, w.seq, w.phantom)[:96]
+    sq = api.Sequence(ctx, w.seq)
+    d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+    r64 = api.match_bruteforce(ctx, d, to_dev(V), top_k=64, with_topk=True)
+    r16 = api.match_bruteforce(ctx, d, to_dev(V), top_k=16, with_topk=True)
+    torch.cuda.synchronize()
+    ref = orc.bruteforce(w.seq, w.grid, V, top_k=64, threads=8)
+    _check(r64, ref, "fp32 top_k 64")
+    tki, tkc = r64["topk_idx"].cpu().numpy(), r64["topk_cc"].cpu().numpy().astype(np.float64)
+    assert float(np.abs(tkc - ref["topk_cc"]).max()) < CC_TOL
+    at = orc.cc_at(w.seq, w.grid, V, tki)
+    assert float(np.abs(at - tkc).max()) < CC_TOL
+    assert bool(np.all(np.diff(tkc, axis=1) <= 0))
+    assert torch.equal(r64["topk_idx"][:, :16], r16["topk_idx"])
+    assert torch.equal(r64["topk_cc"][:, :16], r16["topk_cc"])
+    for k in ("idx", "cc", "margin", "pd_re", "pd_im"):
+        assert torch.equal(r64[k], r16[k]), k
 
 
 def test_bruteforce_ragged_shapes(ctx, orc):
@@ -124,7 +154,7 @@ def test_invalid_match_arguments(ctx):
     with pytest.raises(_lib.MRFError, match="top_k"):
         api.match_bruteforce(ctx, d, v, top_k=0)
     with pytest.raises(_lib.MRFError, match="top_k"):
-        api.match_bruteforce(ctx, d, v, top_k=17)
+        api.match_bruteforce(ctx, d, v, top_k=65)
     with pytest.raises(_lib.MRFError, match="ld_vox"):
         api.match_bruteforce(ctx, d, torch.zeros((3, 30), dtype=torch.complex64, device="cuda"))
     ws = api.Workspace(ctx.device)
@@ -138,24 +168,74 @@ def test_invalid_match_arguments(ctx):
     assert st == 1 and b"workspace too small" in ctx._lib.mrf_last_error()
 
 
-def test_full_size_bruteforce_sampled(ctx, orc):
-    """64x64 slice, N = 1000, 12,636,729 entries (FP32, resident): all 4096
-    voxels on the GPU; 8 sampled voxels by the streaming oracle."""
-    from paper_1506_05393_amd import api, workloads
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "slice64_bruteforce_oracle.json")
+
+
+def _slice64_inputs(orc):
+    """The slice workload, all 4096 fingerprints, the 96 subset fingerprints
+    of the stored oracle results and those results."""
+    from paper_1506_05393_amd import workloads
+    from tests import slice64_subsets as S
     w = workloads.slice64()
-    sample = np.random.default_rng(5).choice(w.phantom.n_vox, 8, replace=False)
-    sample.sort()
+    with open(GOLDEN) as f:
+        G = json.load(f)
+    Vsub, truth = S.fingerprints(orc, w)
+    assert S.digest(Vsub) == G["inputs_sha256"], "stored oracle results are for other inputs"
+    assert [int(x) for x in S.noisy_voxels(w.phantom.n_vox)] == G["noisy_voxels"]
     V = oracle_fingerprints(orc, w.seq, w.phantom)
-    Vs = V[sample]
+    nz = np.array(G["noisy_voxels"])
+    assert np.array_equal(V[nz], Vsub[:len(nz)])
+    ref = {k: np.array(G[k]) for k in ("idx", "cc", "margin", "topk_idx", "topk_cc")}
+    return w, V, Vsub, np.array(truth), nz, ref
+
+
+def _full_size_checks(orc, w, V, Vsub, truth, nz, ref, full, sub, label):
+    """full: GPU results on all 4096 voxels; sub: on the 32 on-grid
+    fingerprints. Index bar on pinned subset voxels, CC bar on all of them,
+    validity of every voxel's result under the oracle."""
+    n_noisy = len(nz)
+    res = {k: np.concatenate([full[k].cpu().numpy()[nz], sub[k].cpu().numpy()])
+           for k in ("idx", "cc")}
+    _check({k: torch.from_numpy(v) for k, v in res.items()}, ref, f"{label} 96-voxel subsets")
+    pinned = ref["margin"] > MARGIN
+    print(f"{label}: pinned noisy {pinned[:n_noisy].sum()}/{n_noisy}, on-grid "
+          f"{pinned[n_noisy:n_noisy + 16].sum()}/16, short-relaxation {pinned[n_noisy + 16:].sum()}/16")
+    assert pinned.sum() > 0
+    # noise-free on-grid fingerprints: the truth wherever the margin rule pins it, CC 1
+    ong = slice(n_noisy, len(ref["idx"]))
+    assert np.all(res["idx"][ong][pinned[ong]] == truth[pinned[ong]])
+    assert np.abs(res["cc"][ong] - 1.0).max() < CC_TOL
+    # every voxel of the slice: the CC reported is the oracle's CC of the entry
+    # returned, and no entry near the truth beats it by more than the tolerance
+    idx = full["idx"].cpu().numpy()
+    cc = full["cc"].cpu().numpy().astype(np.float64)
+    check_cc_at_index(orc, w.seq, w.grid, V, idx, cc, CC_TOL, f"{label} all 4096 voxels")
+    ph, g = w.phantom, w.grid
+    near = g.ravel(*[np.array([int(np.argmin(np.abs(ax - val))) for val in vals])
+                     for ax, vals in ((g.t1_ms, ph.t1), (g.t2_ms, ph.t2), (g.df_hz, ph.df))])
+    moves = [[(0, a), (1, b), (2, c)] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    around = orc.cc_at(w.seq, g, V, unit_stencil(g, near, moves))
+    short = around.max(axis=1) - cc
+    print(f"{label}: best oracle CC among the 27 entries around the truth minus the GPU CC: "
+          f"max {short.max():.2e}")
+    assert float(short.max()) <= CC_TOL
+
+
+def test_full_size_bruteforce_subsets(ctx, orc):
+    """64x64 slice, N = 1000, 12,636,729 entries (FP32, resident), all 4096
+    voxels in the benchmark's launch shape; the stored oracle brute force of
+    a seeded 64-voxel subset and of 32 noise-free on-grid fingerprints."""
+    from paper_1506_05393_amd import api
+    w, V, Vsub, truth, nz, ref = _slice64_inputs(orc)
     sq = api.Sequence(ctx, w.seq)
     d = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
-    res = api.match_bruteforce(ctx, d, to_dev(V), top_k=2)
+    full = api.match_bruteforce(ctx, d, to_dev(V), top_k=2)
+    sub = api.match_bruteforce(ctx, d, to_dev(Vsub[len(nz):]), top_k=2)
     torch.cuda.synchronize()
-    ref = orc.bruteforce(w.seq, w.grid, Vs, top_k=2, threads=0)
-    sub = {k: v[sample] for k, v in res.items() if isinstance(v, torch.Tensor)}
-    _check(sub, ref, "full-size sample")
     del d
     torch.cuda.empty_cache()
+    _full_size_checks(orc, w, V, Vsub, truth, nz, ref, full, sub, "fp32 slice")
 
 
 # ------------------------------------------------------------ BF16 + re-score
@@ -178,11 +258,9 @@ def test_bruteforce_bf16_rescored_small_workload(ctx, orc, on_grid):
     torch.cuda.synchronize()
     tk = res["topk_idx"].cpu().numpy()
     recall = np.array([ref["idx"][v] in tk[v] for v in range(len(V))])
-    print(f"bf16 top-8 recall of the oracle argmax: {recall.mean():.4f}")
-    assert recall.mean() >= 0.99
-    sub = {k: v[recall] for k, v in res.items() if isinstance(v, torch.Tensor) and v.dim() == 1}
-    rsub = {k: v[recall] for k, v in ref.items()}
-    _check(sub, rsub, f"bf16+rescore on_grid={on_grid}")
+    print(f"bf16 top-8 recall of the oracle argmax: {recall.mean():.4f} (reported)")
+    # every voxel is held to the margin rule, whether or not its argmax was kept
+    _check(res, ref, f"bf16+rescore on_grid={on_grid}")
     pd = (res["pd_re"] + 1j * res["pd_im"]).cpu().numpy()
     same = res["idx"].cpu().numpy() == ref["idx"]
     pd_err = float(np.abs(pd - ref["pd"])[same].max())
@@ -203,9 +281,8 @@ def test_bruteforce_bf16_ragged(ctx, orc):
     torch.cuda.synchronize()
     tk = res["topk_idx"].cpu().numpy()
     recall = np.array([ref["idx"][v] in tk[v] for v in range(len(V))])
-    assert recall.mean() >= 0.95
-    sub = {k: v[recall] for k, v in res.items() if isinstance(v, torch.Tensor) and v.dim() == 1}
-    _check(sub, {k: v[recall] for k, v in ref.items()}, "bf16 ragged")
+    print(f"bf16 ragged: top-4 recall {recall.mean():.4f} (reported)")
+    _check(res, ref, "bf16 ragged")
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f32"])
@@ -236,10 +313,9 @@ def test_bruteforce_tiling_invariance(ctx, orc, dtype):
     ref = orc.bruteforce(w.seq, w.grid, V[sample], top_k=8, threads=8)
     tk = full["topk_idx"].cpu().numpy()[sample]
     recall = np.array([ref["idx"][i] in tk[i] for i in range(len(sample))])
-    assert recall.mean() >= 0.9
-    sub = {k: v[sample][recall] for k, v in full.items()
-           if isinstance(v, torch.Tensor) and v.dim() == 1}
-    _check(sub, {k: v[recall] for k, v in ref.items()}, f"{dtype} 1100 voxels")
+    print(f"{dtype} 1100 voxels: top-8 recall of the sample {recall.mean():.3f} (reported)")
+    sub = {k: v[sample] for k, v in full.items() if isinstance(v, torch.Tensor) and v.dim() == 1}
+    _check(sub, ref, f"{dtype} 1100 voxels")
 
 
 def test_bf16_requires_sequence_and_grid(ctx):
@@ -255,30 +331,20 @@ def test_bf16_requires_sequence_and_grid(ctx):
         api.match_bruteforce(ctx, d, v, top_k=1, seq=sq, grid=grid)
 
 
-def test_full_size_bruteforce_bf16_sampled(ctx, orc):
+def test_full_size_bruteforce_bf16_subsets(ctx, orc):
     """64x64 slice, N = 1000, BF16 dictionary (50.5 GB resident) + top-8 FP32
-    re-scoring; 8 sampled voxels by the streaming oracle."""
-    from paper_1506_05393_amd import api, workloads
-    w = workloads.slice64()
-    sample = np.random.default_rng(6).choice(w.phantom.n_vox, 8, replace=False)
-    sample.sort()
-    V = oracle_fingerprints(orc, w.seq, w.phantom)
+    re-scoring, all 4096 voxels; the same oracle subsets and checks as FP32."""
+    from paper_1506_05393_amd import api
+    w, V, Vsub, truth, nz, ref = _slice64_inputs(orc)
     sq = api.Sequence(ctx, w.seq)
     d = _bf16_dict(api, ctx, sq, w.grid)
-    res = api.match_bruteforce(ctx, d, to_dev(V), top_k=8, seq=sq, grid=w.grid, with_topk=True)
+    kw = dict(top_k=8, seq=sq, grid=w.grid, with_topk=True)
+    full = api.match_bruteforce(ctx, d, to_dev(V), **kw)
+    sub = api.match_bruteforce(ctx, d, to_dev(Vsub[len(nz):]), **kw)
     torch.cuda.synchronize()
-    ref = orc.bruteforce(w.seq, w.grid, V[sample], top_k=8, threads=0)
-    tk = res["topk_idx"].cpu().numpy()[sample]
-    recall = np.array([ref["idx"][i] in tk[i] for i in range(len(sample))])
-    print(f"full-size bf16 top-8 recall {recall.mean():.3f}")
-    sub = {k: v[sample] for k, v in res.items() if isinstance(v, torch.Tensor) and v.dim() == 1}
-    cc = sub["cc"].cpu().numpy().astype(np.float64)
-    # the re-scored best is never worse than the oracle's best by more than the
-    # margin rule, and its CC is the exact CC of the entry returned
-    assert bool(np.all(ref["cc"] - cc <= MARGIN + CC_TOL)), float((ref["cc"] - cc).max())
-    idx = sub["idx"].cpu().numpy()
-    for i, v in enumerate(sample):
-        e = orc.simulate(w.seq, *map(float, w.grid.values(int(idx[i]))))
-        assert abs(orc.cc(V[v], e) - cc[i]) < CC_TOL
     del d
     torch.cuda.empty_cache()
+    tk = np.concatenate([full["topk_idx"].cpu().numpy()[nz], sub["topk_idx"].cpu().numpy()])
+    recall = np.array([ref["idx"][i] in tk[i] for i in range(len(tk))])
+    print(f"bf16 slice: top-8 recall of the oracle argmax {recall.mean():.3f} (reported)")
+    _full_size_checks(orc, w, V, Vsub, truth, nz, ref, full, sub, "bf16 slice")

@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 from paper_1506_05393_amd import inputs as I
-from tests.gpu_common import need_gpu, oracle_fingerprints, to_dev, torch
+from tests.gpu_common import (UNIT_T1T2, check_cc_at_index, need_gpu, oracle_fingerprints,
+                              to_dev, torch, unit_stencil)
 
 pytestmark = pytest.mark.gpu
 CC_TOL = 1e-5
@@ -26,7 +27,7 @@ def ctx():
 
 
 def _check(res, ref, label, min_pinned_frac=0.0, orc=None, seq=None, grid=None, V=None,
-           sample=16):
+           stencil=None):
     idx = res["idx"].cpu().numpy()
     cc = res["cc"].cpu().numpy().astype(np.float64)
     ns = res["n_sim"].cpu().numpy()
@@ -44,12 +45,18 @@ def _check(res, ref, label, min_pinned_frac=0.0, orc=None, seq=None, grid=None, 
     assert dcc < CC_TOL, dcc
     assert pinned.mean() >= min_pinned_frac
     if orc is not None:
-        # wherever the paths differ, the GPU's CC is still the CC of the entry it returns
-        rows = np.flatnonzero(~agree)[:sample]
-        for v in rows:
-            t1, t2, df, b1 = grid.values(int(idx[v]))
-            d = orc.simulate(seq, float(t1), float(t2), float(df), float(b1), n_tr=V.shape[1])
-            assert abs(orc.cc(V[v], d) - cc[v]) < CC_TOL
+        # every voxel, whether or not its path is the oracle's: the GPU's CC is
+        # the oracle's CC of the entry it returns
+        check_cc_at_index(orc, seq, grid, V, idx, cc, CC_TOL, label)
+        if stencil is not None:
+            # and the entry is a maximum of the last stage's stencil under the
+            # oracle (to within the tolerance of FP32 decisions)
+            nb = orc.cc_at(seq, grid, V, unit_stencil(grid, idx, stencil))
+            at = orc.cc_at(seq, grid, V, idx[:, None])[:, 0]
+            excess = nb.max(axis=1) - at
+            print(f"{label}: largest oracle CC gain over the endpoint within the final "
+                  f"stencil {excess.max():.2e}; unpinned voxels checked {int((~pinned).sum())}")
+            assert float(excess.max()) <= CC_TOL, (float(excess.max()), int(np.argmax(excess)))
     return agree
 
 
@@ -89,8 +96,11 @@ def test_zoom_small_workload(ctx, orc, variant):
     sq = api.Sequence(ctx, w.seq)
     res = api.zoom_search(ctx, sq, w.grid, to_dev(V), sched=sched)
     torch.cuda.synchronize()
+    # the endpoint is a maximum of the last 2-D zoom's stencil: all 8 unit
+    # neighbours, or with the evaluation-saving rules the 4 edge ones
+    edges = [[(0, -1)], [(0, 1)], [(1, -1)], [(1, 1)]]
     _check(res, ref, f"zoom {variant}", min_pinned_frac=0.25, orc=orc, seq=w.seq,
-           grid=w.grid, V=V)
+           grid=w.grid, V=V, stencil=edges if variant == "pruned" else UNIT_T1T2)
 
 
 def test_zoom_df_hops_equal_bruteforce_on_gpu(ctx, orc):
@@ -138,28 +148,50 @@ def test_zoom_full_size_slice(ctx, orc):
     sq = api.Sequence(ctx, w.seq)
     res = api.zoom_search(ctx, sq, w.grid, to_dev(V), sched=sched)
     torch.cuda.synchronize()
-    _check(res, ref, "zoom slice64", orc=orc, seq=w.seq, grid=w.grid, V=V)
+    _check(res, ref, "zoom slice64", orc=orc, seq=w.seq, grid=w.grid, V=V, stencil=UNIT_T1T2)
 
 
-def test_zoom_four_parameters_sampled(ctx, orc):
+def test_zoom_four_parameters_slice_subset(ctx, orc):
     """The 4-parameter volume grid (3901 x 1991 x 241 x 121, never stored):
-    a 16x16 block of one slice, GPU vs oracle."""
+    one 256 x 256 slice on the GPU (the volume's launch shape, 8-lane voxel
+    groups), a seeded 4096-voxel subset of it by the oracle's ZOOM, same
+    schedule. Index and n_sim on pinned voxels, and on every voxel: the CC
+    reported is the oracle's CC of the entry returned, and that entry is the
+    maximum of the fine df window the schedule ends with."""
     from paper_1506_05393_amd import api, workloads
-    w = workloads.volume(1, 16)
+    w = workloads.volume(1, 256)
+    sub = np.sort(np.random.default_rng(2027).choice(w.phantom.n_vox, 4096, replace=False))
     V = oracle_fingerprints(orc, w.seq, w.phantom)
     sched = orc.schedule_paper(w.seq, w.grid)
-    ref = orc.zoom(w.seq, w.grid, sched, V, threads=0)
     sq = api.Sequence(ctx, w.seq)
-    res = api.zoom_search(ctx, sq, w.grid, to_dev(V), sched=sched)
+    full = api.zoom_search(ctx, sq, w.grid, to_dev(V), sched=sched)
     torch.cuda.synchronize()
-    _check(res, ref, "zoom volume 16x16", orc=orc, seq=w.seq, grid=w.grid, V=V)
-    # at 1 ms / 0.5 Hz / 0.005 the CC differences along the final unit-step
-    # walks are far below FP32 rounding, so paths end at nearby but different
-    # entries (no voxel is pinned); their final CCs still agree closely
+    ref = orc.zoom(w.seq, w.grid, sched, V[sub], threads=0)
+    res = {k: v[torch.from_numpy(sub).to(v.device)] for k, v in full.items()
+           if isinstance(v, torch.Tensor)}
+    Vs = V[sub]
+    agree = _check(res, ref, "zoom volume slice, 4096-voxel subset", orc=orc, seq=w.seq,
+                   grid=w.grid, V=Vs)
+    # the outer rounds end with the unit-step df scan over +- omega / 2: its
+    # window is the one stencil every endpoint is the maximum of
+    last = sched["outer"][-1]
+    assert last["kind"] == 1 and last["axis0"] == 2 and last["step0"] == 1
+    half = last["window"]
+    idx = res["idx"].cpu().numpy()
+    win = [[(2, o)] for o in range(-half, half + 1) if o != 0]
+    nb = orc.cc_at(w.seq, w.grid, Vs, unit_stencil(w.grid, idx, win))
+    at = orc.cc_at(w.seq, w.grid, Vs, idx[:, None])[:, 0]
+    excess = nb.max(axis=1) - at
+    # reported: how many endpoints are also maxima of the unit (T1, T2) and
+    # B1 stencils (they are whenever the outer rounds converged)
+    nb2 = orc.cc_at(w.seq, w.grid, Vs, unit_stencil(w.grid, idx, UNIT_T1T2 + [[(3, -1)], [(3, 1)]]))
+    local = nb2.max(axis=1) - at <= CC_TOL
     cc = res["cc"].cpu().numpy().astype(np.float64)
     dcc = np.abs(cc - ref["cc"])
-    print(f"volume: median |dCC| {np.median(dcc):.2e}, max {dcc.max():.2e}")
-    assert np.median(dcc) < 1e-4
+    print(f"volume subset: index agreement {agree.mean():.4f}, endpoints that are unit "
+          f"(T1, T2, B1) maxima {local.mean():.4f}, |CC - oracle final CC| median "
+          f"{np.median(dcc):.2e} max {dcc.max():.2e}, df-window excess max {excess.max():.2e}")
+    assert float(excess.max()) <= CC_TOL, (float(excess.max()), int(np.argmax(excess)))
 
 
 def test_local_refine_from_brute_force(ctx, orc):

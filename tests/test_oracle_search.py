@@ -461,3 +461,41 @@ def test_prior_half_widths_hand_worked(orc):
     assert orc.prior_half(g, [1.0, -1.0, 0.0, 0.3]) == [1, -1, 1, -1]
     g1 = I.make_grid([100.0], [10.0, 20.0], [0.0])
     assert orc.prior_half(g1) == [-1, 80, -1, -1]
+
+
+def test_decision_margin_bounds_what_a_perturbation_can_change(orc):
+    """The pinning rule of the parity tests: a voxel whose smallest decision
+    margin along its path exceeds 2 delta takes the same path, entry for
+    entry, under any perturbation of its objective by at most delta (each
+    decision compares values at least 2 delta apart). Checked with a
+    deterministic per-entry perturbation on noisy small-workload voxels;
+    with a perturbation far above the margins some paths do change."""
+    from paper_1506_05393_amd import workloads
+    w = workloads.small_dgs(False)
+    g = w.grid
+    sched = orc.schedule_paper(w.seq, g)
+    voxels = np.arange(0, w.phantom.n_vox, 23)
+    V = []
+    for v in voxels:
+        d = orc.simulate(w.seq, float(w.phantom.t1[v]), float(w.phantom.t2[v]),
+                         float(w.phantom.df[v]))
+        V.append(d * np.exp(1j * 0.3 * v) + 0.01 * np.exp(1j * np.arange(len(d))))
+    changed_big = 0
+    for v in V:
+        memo = {}
+
+        def f(i1, i2, i3, i4, delta=0.0):
+            k = int(g.ravel(i1, i2, i3, i4))
+            if k not in memo:
+                memo[k] = orc.cc(v, orc.simulate(w.seq, *map(float, g.values(k))))
+            h = (k * 0x9E3779B97F4A7C15) & ((1 << 64) - 1)
+            return memo[k] + delta * ((h >> 11) / float(1 << 53) * 2.0 - 1.0)
+
+        r0 = orc.zoom_generic(sched, g.shape, f)
+        delta = 0.45 * r0["min_margin"]
+        r1 = orc.zoom_generic(sched, g.shape, lambda *i: f(*i, delta=delta))
+        assert r1["moves"] == r0["moves"] and r1["idx"] == r0["idx"]
+        assert r1["n_eval"] == r0["n_eval"] and r1["calls"] == r0["calls"]
+        r2 = orc.zoom_generic(sched, g.shape, lambda *i: f(*i, delta=1e-2))
+        changed_big += r2["moves"] != r0["moves"]
+    assert changed_big > 0

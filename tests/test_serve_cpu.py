@@ -179,3 +179,18 @@ def test_destroy_drains_inflight_work():
     srv.close()
     assert time.monotonic() - t0 > 0.03
     assert len(tickets) == 5
+
+
+def test_unknown_ticket_is_an_error():
+    """Polling or cancelling a ticket the server never issued fails with
+    MRF_ERR_INVALID and names the ticket."""
+    srv, slots = _server()
+    try:
+        t = srv.submit("brute", slots[0], 500, n_vox=64)
+        srv.wait([t], timeout_s=60)
+        with pytest.raises(L.MRFError, match="unknown ticket"):
+            srv.poll(t + 1000)
+        with pytest.raises(L.MRFError):
+            srv.cancel(t + 1000)
+    finally:
+        srv.close()
