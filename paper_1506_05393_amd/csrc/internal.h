@@ -5,11 +5,14 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/libmrf.h"
+#include "table_cache.h"
 
 namespace mrf {
 
@@ -58,6 +61,8 @@ struct Tables {
   float4* dfT = nullptr;  // [n3][n_tr]
   void* block = nullptr;  // one allocation holding all of the above
 };
+// A held reference to built tables (see get_tables).
+using TablesRef = std::shared_ptr<const Tables>;
 
 }  // namespace mrf
 
@@ -100,16 +105,18 @@ struct mrf_sequence {
   double omega_hz = 0.0;  // 1000 / min TR: CC pseudo-period in df (Property II)
   double* dev = nullptr;  // device FP64 [4][n]: TE, TR-TE, flip angle, RF phase
   float2* demod = nullptr;  // device [n] (cos, sin) of the RF phase (inside dev's allocation)
-  std::mutex mu;
-  std::vector<mrf::Tables> cache;  // small LRU keyed by grid contents and n_tr
+  // the tables of the last four (grid contents, n_tr) keys
+  mrf::LruCache<std::pair<uint64_t, int32_t>, mrf::Tables> cache{4};
 };
 
 namespace mrf {
 // Validate a grid (axis lengths, strictly increasing, finite where required).
 int check_grid(const mrf_grid* g);
 // Tables of (seq, grid, n_tr), built (on `stream`) on first use and cached.
+// *out holds a reference: keep it while the tables are in use (an entry
+// evicted meanwhile by another thread's lookups is freed when released).
 int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t stream,
-               const Tables** out);
+               TablesRef* out);
 int64_t grid_size_checked(const mrf_grid* g);
 // Looks up the device address of this device's static scratch (scratch.hip);
 // called once per device with the device current.

@@ -544,8 +544,9 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
                 "dictionary entries exceed the grid");
   const PlanB p = plan_bf16(d, n_vox, top_k, ctx->n_cu);
   MRF_CHECK_ARG(ws_bytes >= p.total, "workspace too small (%zu < %zu bytes)", ws_bytes, p.total);
-  const Tables* t = nullptr;
-  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, d->n_tr, st, &t);
+  TablesRef tref;  // held until the launches are enqueued
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, d->n_tr, st, &tref);
+  const Tables* t = tref.get();
   if (rc) return rc;
   char* ws = (char*)workspace;
   uint4* A = (uint4*)(ws + p.off_A);

@@ -164,28 +164,20 @@ static uint64_t grid_key(const mrf_grid* g, int32_t n_tr) {
   return h;
 }
 
-static void free_tables(Tables& t) {
-  if (t.block) (void)hipFree(t.block);
-  t = Tables();
+// Owner of one built table block: frees the device memory with the last
+// reference.
+static std::shared_ptr<Tables> own_tables(const Tables& t) {
+  return std::shared_ptr<Tables>(new Tables(t), [](Tables* p) {
+    if (p->block) (void)hipFree(p->block);
+    delete p;
+  });
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t stream,
-               const Tables** out) {
-  const uint64_t key = grid_key(g, n_tr);
-  std::lock_guard<std::mutex> lock(seq->mu);
-  for (size_t i = 0; i < seq->cache.size(); ++i) {
-    if (seq->cache[i].key == key && seq->cache[i].n_tr == n_tr) {
-      if (i + 1 != seq->cache.size()) {  // move to the back (most recent)
-        Tables t = seq->cache[i];
-        seq->cache.erase(seq->cache.begin() + (long)i);
-        seq->cache.push_back(t);
-      }
-      *out = &seq->cache.back();
-      return MRF_OK;
-    }
-  }
+// Builds the tables of (seq, g, n_tr) on `stream` and waits for them.
+static int build_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, uint64_t key,
+                        hipStream_t stream, std::shared_ptr<Tables>* out) {
   Tables t;
   t.key = key;
   t.n_tr = n_tr;
@@ -271,18 +263,23 @@ int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t s
   }
   // the host staging buffer must outlive the copy
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  std::shared_ptr<Tables> owned = own_tables(t);
   if (e != hipSuccess) {
-    free_tables(t);
     set_error("building step tables failed: %s", hipGetErrorString(e));
-    return MRF_ERR_DEVICE;
+    return MRF_ERR_DEVICE;  // `owned` frees the block
   }
-  if (seq->cache.size() >= 4) {
-    free_tables(seq->cache.front());
-    seq->cache.erase(seq->cache.begin());
-  }
-  seq->cache.push_back(t);
-  *out = &seq->cache.back();
+  *out = std::move(owned);
   return MRF_OK;
+}
+
+int get_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, hipStream_t stream,
+               TablesRef* out) {
+  const uint64_t key = grid_key(g, n_tr);
+  return seq->cache.get(std::make_pair(key, n_tr),
+                        [&](std::shared_ptr<Tables>* made) {
+                          return build_tables(seq, g, n_tr, key, stream, made);
+                        },
+                        out);
 }
 
 ProfScope::ProfScope(mrf_context* ctx, const char* name, hipStream_t stream)
@@ -472,7 +469,7 @@ int mrf_sequence_create(mrf_context* ctx, const mrf_sequence_desc* d, mrf_sequen
 
 int mrf_sequence_destroy(mrf_sequence* s) {
   if (!s) return MRF_OK;
-  for (auto& t : s->cache) free_tables(t);
+  s->cache.clear();  // tables still held by a running call are freed by that call
   if (s->dev) (void)hipFree(s->dev);
   delete s;
   return MRF_OK;

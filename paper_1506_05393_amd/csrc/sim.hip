@@ -689,8 +689,9 @@ extern "C" int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq
     MRF_CHECK_ARG(n_tr % 4 == 0, "BF16 dictionaries need n_tr %% 4 == 0 (got %d)", n_tr);
     MRF_CHECK_ARG(((uintptr_t)re & 15) == 0, "BF16 dictionary must be 16-byte aligned");
   }
-  const Tables* t = nullptr;
-  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &t);
+  TablesRef tref;  // held until the launches are enqueued
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &tref);
+  const Tables* t = tref.get();
   if (rc) return rc;
   return launch_sim_dict(ctx, *t, entry_begin, entry_count, dtype, re, im, ld, norm, unit_norm ? 1 : 0,
                          (hipStream_t)stream);
@@ -715,8 +716,9 @@ extern "C" int mrf_cc_map(mrf_context* ctx, const mrf_sequence* seq, const mrf_g
   if (n_vox == 0 || entry_count == 0) return MRF_OK;
   MRF_CHECK_ARG(vox && cc, "vox and cc must not be NULL");
   MRF_CHECK_ARG(((uintptr_t)vox & 7) == 0, "vox must be 8-byte aligned (complex64)");
-  const Tables* t = nullptr;
-  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &t);
+  TablesRef tref;  // held until the launches are enqueued
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &tref);
+  const Tables* t = tref.get();
   if (rc) return rc;
   for (int32_t v = 0; v < n_vox; ++v) {
     rc = launch_cc_map(ctx, *t, entry_begin, entry_count, (const float2*)vox + (int64_t)v * ld_vox,

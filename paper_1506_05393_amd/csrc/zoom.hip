@@ -1265,9 +1265,11 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   hipStream_t st = (hipStream_t)stream;
   static const Tables no_tables;
   const Tables* t = &no_tables;
+  TablesRef tref;  // held until the launches are enqueued
   if (!dict) {
-    rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, st, &t);
+    rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, st, &tref);
     if (rc) return rc;
+    t = tref.get();
   }
 
   ZoomArgs a;
