@@ -47,7 +47,10 @@ class GridS(C.Structure):
 class Stage(C.Structure):
     _fields_ = [("kind", C.c_int32), ("axis0", C.c_int32), ("axis1", C.c_int32),
                 ("step0", C.c_int32), ("step1", C.c_int32), ("window", C.c_int32),
-                ("hop", C.c_double)]
+                ("hop", C.c_double), ("objective", C.c_int32)]
+
+
+OBJ_CC, OBJ_DIST = 0, 1
 
 
 class Schedule(C.Structure):
@@ -59,6 +62,7 @@ class Schedule(C.Structure):
 
 
 OBJECTIVE = C.CFUNCTYPE(C.c_double, C.c_void_p, C.POINTER(C.c_int32))
+OBJECTIVE2 = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double))
 
 _lib = None
 
@@ -89,10 +93,14 @@ def lib():
         L.orc_cc_at.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp, C.c_int32,
                                 C.c_int32, lp, dp, C.c_int32]
         L.orc_prior_half.argtypes = [C.POINTER(GridS), dp, ip]
+        L.orc_objectives_at.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
+                                        C.c_int32, C.c_int32, lp, dp, dp, C.c_int32]
         L.orc_zoom_generic.argtypes = [C.POINTER(Schedule), ip, ip, OBJECTIVE, C.c_void_p,
                                        ip, dp, ip, dp, ip, C.c_int32, ip]
+        L.orc_zoom_generic2.argtypes = [C.POINTER(Schedule), ip, ip, OBJECTIVE2, C.c_void_p,
+                                        ip, dp, ip, dp, ip, C.c_int32, ip]
         L.orc_zoom.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32,
-                               C.POINTER(Schedule), dp, dp, C.c_int32, ip, lp, dp, ip, dp,
+                               C.POINTER(Schedule), dp, dp, C.c_int32, ip, lp, dp, dp, ip, dp,
                                C.c_int32]
         _lib = L
     return _lib
@@ -227,6 +235,29 @@ def cc_at(seq, grid, vox, idx, n_tr=None, threads=0) -> np.ndarray:
     return out
 
 
+def objectives_at(seq, grid, vox, idx, n_tr=None, threads=0) -> tuple:
+    """(cc, score) float64 [n_vox, m]: both ZOOM objectives of each voxel at
+    listed entries idx [n_vox, m] (negative: 0 and -inf)."""
+    vox = np.atleast_2d(np.asarray(vox, np.complex128))
+    n_vox = vox.shape[0]
+    n_tr = vox.shape[1] if n_tr is None else n_tr
+    vox = vox[:, :n_tr]
+    idx = np.ascontiguousarray(np.asarray(idx, np.int64).reshape(n_vox, -1))
+    m = idx.shape[1]
+    s, ks = make_seq(seq)
+    g, kg = make_grid(grid)
+    vr = np.ascontiguousarray(vox.real)
+    vi = np.ascontiguousarray(vox.imag)
+    cc = np.zeros((n_vox, m))
+    sc = np.zeros((n_vox, m))
+    rc = lib().orc_objectives_at(C.byref(s), C.byref(g), n_tr, _dp(vr), _dp(vi), n_vox, m,
+                                 idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(cc), _dp(sc),
+                                 _threads(threads))
+    if rc:
+        raise ValueError(f"orc_objectives_at failed ({rc})")
+    return cc, sc
+
+
 def bruteforce(seq, grid, vox, top_k=1, n_tr=None, threads=0) -> dict:
     """vox: complex [n_vox, n_tr]. Returns idx, cc, margin, pd, topk_idx, topk_cc."""
     vox = np.asarray(vox, np.complex128)
@@ -275,7 +306,7 @@ def cc_map(seq, grid, vox, k0=0, count=None, n_tr=None, threads=0) -> np.ndarray
 
 def schedule_to_dict(s: Schedule) -> dict:
     st = lambda x: dict(kind=x.kind, axis0=x.axis0, axis1=x.axis1, step0=x.step0,
-                        step1=x.step1, window=x.window, hop=x.hop)
+                        step1=x.step1, window=x.window, hop=x.hop, objective=x.objective)
     return dict(stages=[st(s.stages[i]) for i in range(s.n_stages)],
                 outer=[st(s.outer[i]) for i in range(s.n_outer)], outer_max=s.outer_max,
                 starts=[list(s.starts[i]) for i in range(s.n_starts)], pruned=s.pruned,
@@ -284,14 +315,15 @@ def schedule_to_dict(s: Schedule) -> dict:
 
 def schedule_from_dict(d: dict) -> Schedule:
     s = Schedule()
+    mk = lambda x: Stage(x["kind"], x["axis0"], x.get("axis1", 0), x.get("step0", 0),
+                         x.get("step1", 0), x.get("window", 0), x.get("hop", 0.0),
+                         x.get("objective", OBJ_CC))
     s.n_stages = len(d["stages"])
     for i, x in enumerate(d["stages"]):
-        s.stages[i] = Stage(x["kind"], x["axis0"], x.get("axis1", 0), x.get("step0", 0),
-                            x.get("step1", 0), x.get("window", 0), x.get("hop", 0.0))
+        s.stages[i] = mk(x)
     s.n_outer = len(d.get("outer", []))
     for i, x in enumerate(d.get("outer", [])):
-        s.outer[i] = Stage(x["kind"], x["axis0"], x.get("axis1", 0), x.get("step0", 0),
-                           x.get("step1", 0), x.get("window", 0), x.get("hop", 0.0))
+        s.outer[i] = mk(x)
     s.outer_max = d.get("outer_max", 0)
     starts = d.get("starts", [[0, 0, 0, 0]])
     s.n_starts = len(starts)
@@ -331,33 +363,37 @@ def prior_half(grid, half=None) -> list:
 
 
 def zoom_generic(sched: dict, dims, objective: Callable, init=None) -> dict:
-    """Run the ZOOM engine on a Python objective f(i1, i2, i3, i4) -> value."""
+    """Run the ZOOM engine on a Python objective f(i1, i2, i3, i4) -> value,
+    or -> (value for CC stages, value for distance stages)."""
     s = schedule_from_dict(sched)
     dims4 = (C.c_int32 * 4)(*[int(x) for x in (list(dims) + [1] * 4)[:4]])
     calls = []
 
-    def cb(_ctx, ip):
+    def cb(_ctx, ip, out):
         i = tuple(ip[a] for a in range(4))
         calls.append(i)
-        return float(objective(*i))
+        r = objective(*i)
+        a, b = (r, r) if np.isscalar(r) else r
+        out[0] = float(a)
+        out[1] = float(b)
 
-    f = OBJECTIVE(cb)
+    f = OBJECTIVE2(cb)
     bi = (C.c_int32 * 4)()
-    bv = C.c_double()
+    bvs = (C.c_double * 2)()
     ne = C.c_int32()
     mm = C.c_double()
     ini = None if init is None else (C.c_int32 * 4)(*[int(x) for x in init])
     cap = 4096
     path = (C.c_int32 * (5 * cap))()
     plen = C.c_int32()
-    rc = lib().orc_zoom_generic(C.byref(s), dims4, ini, f, None, bi, C.byref(bv),
-                                C.byref(ne), C.byref(mm), path, cap, C.byref(plen))
+    rc = lib().orc_zoom_generic2(C.byref(s), dims4, ini, f, None, bi, bvs,
+                                 C.byref(ne), C.byref(mm), path, cap, C.byref(plen))
     if rc:
         raise ValueError("orc_zoom_generic failed")
     moves = [(tuple(path[5 * i + a] for a in range(4)), path[5 * i + 4])
              for i in range(plen.value)]
-    return dict(idx=tuple(bi[a] for a in range(4)), val=bv.value, n_eval=ne.value,
-                min_margin=mm.value, calls=calls, moves=moves)
+    return dict(idx=tuple(bi[a] for a in range(4)), val=bvs[0], vals=(bvs[0], bvs[1]),
+                n_eval=ne.value, min_margin=mm.value, calls=calls, moves=moves)
 
 
 def zoom(seq, grid, sched: dict, vox, init=None, n_tr=None, threads=0) -> dict:
@@ -373,6 +409,7 @@ def zoom(seq, grid, sched: dict, vox, init=None, n_tr=None, threads=0) -> dict:
     vi = np.ascontiguousarray(vox.imag)
     idx = np.zeros(n_vox, np.int64)
     ccv = np.zeros(n_vox)
+    scv = np.zeros(n_vox)
     ns = np.zeros(n_vox, np.int32)
     mm = np.zeros(n_vox)
     ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
@@ -381,11 +418,11 @@ def zoom(seq, grid, sched: dict, vox, init=None, n_tr=None, threads=0) -> dict:
         ini_arr = np.ascontiguousarray(init, np.int32).reshape(n_vox, 4)
         ini = ip(ini_arr)
     rc = lib().orc_zoom(C.byref(s), C.byref(g), n_tr, C.byref(sc), _dp(vr), _dp(vi), n_vox,
-                        ini, idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(ccv), ip(ns),
-                        _dp(mm), _threads(threads))
+                        ini, idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(ccv), _dp(scv),
+                        ip(ns), _dp(mm), _threads(threads))
     if rc:
         raise ValueError(f"orc_zoom failed ({rc})")
-    return dict(idx=idx, cc=ccv, n_sim=ns, min_margin=mm)
+    return dict(idx=idx, cc=ccv, score=scv, n_sim=ns, min_margin=mm)
 
 
 def nearest_lattice(width: int, height: int, n_slices: int, stride: int) -> np.ndarray:

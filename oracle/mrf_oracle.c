@@ -14,6 +14,11 @@
  *     paper's own CC landscapes is parity unpinned (the figures carrying them
  *     are not available), and so are the B1 stages (the paper has no fourth
  *     parameter).
+ *   - distance objective of the finest-resolution stages (phase-fitted
+ *     residual of the non-normalised fingerprint): pinned by a numerical
+ *     minimisation over the phase, exact matches and scalings, its relation
+ *     to CC with the magnitude fitted, and a NumPy argmin over an
+ *     independently integrated dictionary (tests/test_oracle_objective.py).
  */
 #include "mrf_oracle.h"
 
@@ -697,20 +702,21 @@ int orc_prior_half(const orc_grid* g, const double* half, int32_t* out) {
   return 0;
 }
 
-/* memo: open addressing, key = entry index */
+/* memo: open addressing, key = entry index, both objective values per key */
 typedef struct {
   int64_t* keys;
-  double* vals;
+  double* vals; /* [cap][2] */
   int64_t cap, count;
 } memo_t;
 
-static void memo_init(memo_t* m) {
-  m->cap = 1024;
+static void memo_alloc(memo_t* m, int64_t cap) {
+  m->cap = cap;
   m->count = 0;
   m->keys = (int64_t*)malloc(sizeof(int64_t) * m->cap);
-  m->vals = (double*)malloc(sizeof(double) * m->cap);
+  m->vals = (double*)malloc(sizeof(double) * 2 * m->cap);
   for (int64_t i = 0; i < m->cap; ++i) m->keys[i] = -1;
 }
+static void memo_init(memo_t* m) { memo_alloc(m, 1024); }
 static void memo_free(memo_t* m) { free(m->keys); free(m->vals); }
 static int64_t memo_slot(const memo_t* m, int64_t key) {
   uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
@@ -718,33 +724,31 @@ static int64_t memo_slot(const memo_t* m, int64_t key) {
   while (m->keys[s] != -1 && m->keys[s] != key) s = (s + 1) & (m->cap - 1);
   return s;
 }
-static void memo_put(memo_t* m, int64_t key, double v);
+static void memo_put(memo_t* m, int64_t key, const double* v);
 static void memo_grow(memo_t* m) {
   memo_t n;
-  n.cap = m->cap * 2;
-  n.count = 0;
-  n.keys = (int64_t*)malloc(sizeof(int64_t) * n.cap);
-  n.vals = (double*)malloc(sizeof(double) * n.cap);
-  for (int64_t i = 0; i < n.cap; ++i) n.keys[i] = -1;
+  memo_alloc(&n, m->cap * 2);
   for (int64_t i = 0; i < m->cap; ++i)
-    if (m->keys[i] != -1) memo_put(&n, m->keys[i], m->vals[i]);
+    if (m->keys[i] != -1) memo_put(&n, m->keys[i], m->vals + 2 * i);
   memo_free(m);
   *m = n;
 }
-static void memo_put(memo_t* m, int64_t key, double v) {
+static void memo_put(memo_t* m, int64_t key, const double* v) {
   if (2 * (m->count + 1) > m->cap) memo_grow(m);
   int64_t s = memo_slot(m, key);
   if (m->keys[s] == -1) m->count++;
   m->keys[s] = key;
-  m->vals[s] = v;
+  m->vals[2 * s] = v[0];
+  m->vals[2 * s + 1] = v[1];
 }
 
 typedef struct {
   const orc_schedule* sch;
   int32_t dims[4];
   int32_t lo[4], hi[4];
-  orc_objective obj;
+  orc_objective2 obj;
   void* ctx;
+  int32_t cur_obj; /* objective of the stage being run */
   memo_t memo;
   double min_margin;
   int32_t n_eval;
@@ -766,11 +770,12 @@ static double eval_at(engine* e, const int32_t* i) {
     if (i[a] < e->lo[a] || i[a] > e->hi[a]) return -INFINITY;
   int64_t key = key_of(e, i);
   int64_t s = memo_slot(&e->memo, key);
-  if (e->memo.keys[s] == key) return e->memo.vals[s];
-  double v = e->obj(e->ctx, i);
+  if (e->memo.keys[s] == key) return e->memo.vals[2 * s + e->cur_obj];
+  double v[2];
+  e->obj(e->ctx, i, v);
   memo_put(&e->memo, key, v);
   e->n_eval++;
-  return v;
+  return v[e->cur_obj];
 }
 
 static void need_centre(engine* e) {
@@ -1034,6 +1039,12 @@ static void stage_zoom2(engine* e, const orc_stage* st, int pruned) {
 }
 
 static void run_stage(engine* e, const orc_stage* st) {
+  const int32_t obj = st->objective == ORC_OBJ_DIST ? ORC_OBJ_DIST : ORC_OBJ_CC;
+  if (obj != e->cur_obj) {
+    /* the centre's value under this stage's objective (a memo hit) */
+    e->cur_obj = obj;
+    e->cknown = 0;
+  }
   switch (st->kind) {
     case ORC_SCAN_STRIDE: stage_scan_stride(e, st); break;
     case ORC_SCAN_WINDOW: stage_scan_window(e, st); break;
@@ -1054,7 +1065,7 @@ static int sched_ok(const orc_schedule* s) {
 /* One voxel: every start runs the whole schedule; the best final value wins
  * (ties: lower entry index). The memo is shared across starts. */
 static void engine_run(engine* e, const int32_t* init, int32_t* best_idx,
-                       double* best_val) {
+                       double* best_vals) {
   const orc_schedule* s = e->sch;
   for (int a = 0; a < 4; ++a) {
     e->lo[a] = 0;
@@ -1078,6 +1089,7 @@ static void engine_run(engine* e, const int32_t* init, int32_t* best_idx,
       e->c[a] = v < e->lo[a] ? e->lo[a] : (v > e->hi[a] ? e->hi[a] : v);
     }
     e->cknown = 0;
+    e->cur_obj = ORC_OBJ_CC;
     for (int i = 0; i < s->n_stages; ++i) run_stage(e, &s->stages[i]);
     for (int r = 0; r < s->outer_max && s->n_outer > 0; ++r) {
       int32_t before[4];
@@ -1101,14 +1113,17 @@ static void engine_run(engine* e, const int32_t* init, int32_t* best_idx,
   free(finals);
   free(fkeys);
   memcpy(best_idx, bi, sizeof bi);
-  *best_val = bv;
+  /* both values of the entry returned (it is in the memo) */
+  const int64_t sl = memo_slot(&e->memo, key_of(e, bi));
+  best_vals[0] = e->memo.keys[sl] == key_of(e, bi) ? e->memo.vals[2 * sl] : bv;
+  best_vals[1] = e->memo.keys[sl] == key_of(e, bi) ? e->memo.vals[2 * sl + 1] : bv;
 }
 
-int orc_zoom_generic(const orc_schedule* sch, const int32_t* dims,
-                     const int32_t* init, orc_objective obj, void* ctx,
-                     int32_t* best_idx, double* best_val, int32_t* n_eval,
-                     double* min_margin, int32_t* path, int32_t path_cap,
-                     int32_t* path_len) {
+int orc_zoom_generic2(const orc_schedule* sch, const int32_t* dims,
+                      const int32_t* init, orc_objective2 obj, void* ctx,
+                      int32_t* best_idx, double* best_vals, int32_t* n_eval,
+                      double* min_margin, int32_t* path, int32_t path_cap,
+                      int32_t* path_len) {
   if (!sched_ok(sch) || !dims || !obj) return 1;
   engine e;
   memset(&e, 0, sizeof e);
@@ -1123,12 +1138,36 @@ int orc_zoom_generic(const orc_schedule* sch, const int32_t* dims,
   e.path = path;
   e.path_cap = path ? path_cap : 0;
   memo_init(&e.memo);
-  engine_run(&e, init, best_idx, best_val);
+  engine_run(&e, init, best_idx, best_vals);
   if (path_len) *path_len = e.path_len;
   if (n_eval) *n_eval = e.n_eval;
   if (min_margin) *min_margin = e.min_margin;
   memo_free(&e.memo);
   return 0;
+}
+
+/* a one-valued objective serving both objective kinds */
+typedef struct {
+  orc_objective f;
+  void* ctx;
+} one_valued;
+static void one_valued_eval(void* p, const int32_t* i, double* out) {
+  one_valued* o = (one_valued*)p;
+  out[0] = out[1] = o->f(o->ctx, i);
+}
+
+int orc_zoom_generic(const orc_schedule* sch, const int32_t* dims,
+                     const int32_t* init, orc_objective obj, void* ctx,
+                     int32_t* best_idx, double* best_val, int32_t* n_eval,
+                     double* min_margin, int32_t* path, int32_t path_cap,
+                     int32_t* path_len) {
+  if (!obj) return 1;
+  one_valued o = {obj, ctx};
+  double bv[2];
+  int rc = orc_zoom_generic2(sch, dims, init, one_valued_eval, &o, best_idx, bv, n_eval,
+                             min_margin, path, path_cap, path_len);
+  if (rc == 0 && best_val) *best_val = bv[0];
+  return rc;
 }
 
 typedef struct {
@@ -1139,24 +1178,39 @@ typedef struct {
   int32_t dims[4];
 } phys_ctx;
 
-/* CC of the voxel against the simulated entry at idx (Eq. 1) */
-static double phys_objective(void* p, const int32_t* i) {
+/* The voxel against the simulated entry at idx: out[0] = CC (Eq. 1);
+ * out[1] = the distance score, -min_phi ||v - exp(i phi) d||^2 / ||v||^2,
+ * written out: the best phase makes the product <v, exp(i phi) d> real and
+ * positive, exp(i phi) = <v, d> / |<v, d>| with <v, d> = sum v conj(d); then
+ * the squared residual is summed readout by readout. */
+static void phys_objective(void* p, const int32_t* i, double* out) {
   phys_ctx* c = (phys_ctx*)p;
   int64_t k = (((int64_t)i[0] * c->dims[1] + i[1]) * c->dims[2] + i[2]) * c->dims[3] + i[3];
   entry_factors f;
   tables_view(c->t, k, &f);
   entry_samples(c->t, &f, c->re, c->im);
-  double nd = sqrt(norm2(c->t->n_tr, c->re, c->im));
-  if (nd == 0.0 || c->vnorm == 0.0) return 0.0;
+  const int32_t n = c->t->n_tr;
+  double nd2 = norm2(n, c->re, c->im);
+  double nd = sqrt(nd2);
   double sr, si;
-  cdot(c->t->n_tr, c->vr, c->vi, c->re, c->im, &sr, &si);
-  return sqrt(sr * sr + si * si) / (c->vnorm * nd);
+  cdot(n, c->vr, c->vi, c->re, c->im, &sr, &si);
+  const double sabs = sqrt(sr * sr + si * si);
+  out[0] = (nd == 0.0 || c->vnorm == 0.0) ? 0.0 : sabs / (c->vnorm * nd);
+  /* exp(i phi); any phase when the product is 0 */
+  const double pr = sabs > 0.0 ? sr / sabs : 1.0, pi = sabs > 0.0 ? si / sabs : 0.0;
+  double e2 = 0.0;
+  for (int32_t j = 0; j < n; ++j) {
+    const double rr = c->vr[j] - (pr * c->re[j] - pi * c->im[j]);
+    const double ri = c->vi[j] - (pr * c->im[j] + pi * c->re[j]);
+    e2 += rr * rr + ri * ri;
+  }
+  out[1] = c->vnorm > 0.0 ? -e2 / (c->vnorm * c->vnorm) : -nd2;
 }
 
 int orc_zoom(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
              const orc_schedule* sch, const double* vr, const double* vi,
              int32_t n_vox, const int32_t* init, int64_t* idx, double* cc,
-             int32_t* n_sim, double* min_margin, int32_t n_threads) {
+             double* score, int32_t* n_sim, double* min_margin, int32_t n_threads) {
   if (!sched_ok(sch) || !grid || n_vox < 0 || (n_vox > 0 && (!vr || !vi))) return 1;
   tables t;
   int rc = tables_build(seq, grid, n_tr, &t);
@@ -1180,15 +1234,76 @@ int orc_zoom(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
       c.vi = vi + (size_t)v * n_tr;
       c.vnorm = sqrt(norm2(n_tr, c.vr, c.vi));
       int32_t bi[4];
-      double bv;
+      double bv[2];
       int32_t ne;
       double mm;
-      orc_zoom_generic(sch, dims, init ? init + 4 * (size_t)v : NULL, phys_objective,
-                       &c, bi, &bv, &ne, &mm, NULL, 0, NULL);
+      orc_zoom_generic2(sch, dims, init ? init + 4 * (size_t)v : NULL, phys_objective,
+                        &c, bi, bv, &ne, &mm, NULL, 0, NULL);
       if (idx) idx[v] = (((int64_t)bi[0] * dims[1] + bi[1]) * dims[2] + bi[2]) * dims[3] + bi[3];
-      if (cc) cc[v] = bv;
+      if (cc) cc[v] = bv[0];
+      if (score) score[v] = bv[1];
       if (n_sim) n_sim[v] = ne;
       if (min_margin) min_margin[v] = mm;
+    }
+    free(c.re);
+    free(c.im);
+  }
+  tables_free(&t);
+  return 0;
+}
+
+/* Both objectives of the ZOOM engine (CC and the distance score, as
+ * phys_objective computes them) at listed entries: cc/score[v*m + i] for
+ * entry idx[v*m + i]; a negative index gives CC 0 and score -inf. */
+int orc_objectives_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
+                      const double* vr, const double* vi, int32_t n_vox, int32_t m,
+                      const int64_t* idx, double* cc, double* score, int32_t n_threads) {
+  if (!grid || n_vox < 0 || m < 0 ||
+      (n_vox > 0 && m > 0 && (!vr || !vi || !idx || !cc || !score)))
+    return 1;
+  tables t;
+  int rc = tables_build(seq, grid, n_tr, &t);
+  if (rc) return rc;
+  const int64_t E = grid_size(grid);
+  for (int64_t q = 0; q < (int64_t)n_vox * m; ++q)
+    if (idx[q] >= E) {
+      tables_free(&t);
+      return 1;
+    }
+  const int32_t dims[4] = {t.n1, t.n2, t.n3, t.n4};
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+  {
+    phys_ctx c;
+    c.t = &t;
+    memcpy(c.dims, dims, sizeof dims);
+    c.re = (double*)malloc(sizeof(double) * (size_t)(n_tr + 1));
+    c.im = (double*)malloc(sizeof(double) * (size_t)(n_tr + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+    for (int64_t q = 0; q < (int64_t)n_vox * m; ++q) {
+      const int64_t v = q / m;
+      if (idx[q] < 0) {
+        cc[q] = 0.0;
+        score[q] = -INFINITY;
+        continue;
+      }
+      c.vr = vr + (size_t)v * n_tr;
+      c.vi = vi + (size_t)v * n_tr;
+      c.vnorm = sqrt(norm2(n_tr, c.vr, c.vi));
+      int64_t k = idx[q];
+      int32_t i[4];
+      for (int a = 3; a >= 0; --a) {
+        i[a] = (int32_t)(k % dims[a]);
+        k /= dims[a];
+      }
+      double o[2];
+      phys_objective(&c, i, o);
+      cc[q] = o[0];
+      score[q] = o[1];
     }
     free(c.re);
     free(c.im);

@@ -54,9 +54,17 @@ enum {
   ORC_ZOOM2       = 4  /* 2-D hill climb on (axis0, axis1) with steps (s0, s1) */
 };
 
+/* Objective of a stage: CC of Eq. 1, or the distance of the non-normalised
+ * fingerprint from the raw entry (M0 = 1) with only a global phase fitted,
+ * score = -min_phi ||v - exp(i phi) d||^2 / ||v||^2 (0 at a perfect match;
+ * -||d||^2 for a zero fingerprint). The fingerprint must be in units of M0
+ * (its proton density magnitude divided out). Each entry is simulated once;
+ * both values are kept. */
+enum { ORC_OBJ_CC = 0, ORC_OBJ_DIST = 1 };
 typedef struct {
   int32_t kind, axis0, axis1, step0, step1, window;
   double hop;
+  int32_t objective; /* ORC_OBJ_CC or ORC_OBJ_DIST */
 } orc_stage;
 
 #define ORC_MAX_STAGES 64
@@ -114,6 +122,12 @@ int orc_cc_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr, const doub
               const double* vi, int32_t n_vox, int32_t m, const int64_t* idx, double* out,
               int32_t n_threads);
 
+/* ---- both ZOOM objectives at listed entries: cc/score[v*m + i] for entry
+ * idx[v*m + i] (CC of Eq. 1 and the distance score of ORC_OBJ_DIST; a
+ * negative index gives 0 and -inf) ---- */
+int orc_objectives_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
+                      const double* vr, const double* vi, int32_t n_vox, int32_t m,
+                      const int64_t* idx, double* cc, double* score, int32_t n_threads);
 /* ---- ZOOM ---- */
 int orc_schedule_paper(const orc_grid* grid, const orc_seq* seq,
                        orc_schedule* out);
@@ -122,18 +136,30 @@ int orc_schedule_paper(const orc_grid* grid, const orc_seq* seq,
 int orc_prior_half(const orc_grid* grid, const double* half, int32_t* out);
 /* generic engine on a caller objective; the memo is per call. path (optional):
  * 5 ints per hill-climb move or scan update = new centre and the number of
- * evaluations made when it was reached */
+ * evaluations made when it was reached. Every stage uses obj whatever its
+ * objective field. best_val: the final value of the best start. */
 int orc_zoom_generic(const orc_schedule* sch, const int32_t* dims,
                      const int32_t* init, orc_objective obj, void* ctx,
                      int32_t* best_idx, double* best_val, int32_t* n_eval,
                      double* min_margin, int32_t* path, int32_t path_cap,
                      int32_t* path_len);
-/* physics objective: CC of each voxel against simulated entries.
- * init: [n_vox][4] prior centres or NULL (then the schedule's starts are used) */
+/* the same engine on a two-valued objective: obj2 fills out[0] (used by
+ * ORC_OBJ_CC stages) and out[1] (ORC_OBJ_DIST stages) for one entry, which
+ * is evaluated once. best_vals[2]: both values of the entry returned. */
+typedef void (*orc_objective2)(void* ctx, const int32_t* idx, double* out);
+int orc_zoom_generic2(const orc_schedule* sch, const int32_t* dims,
+                      const int32_t* init, orc_objective2 obj2, void* ctx,
+                      int32_t* best_idx, double* best_vals, int32_t* n_eval,
+                      double* min_margin, int32_t* path, int32_t path_cap,
+                      int32_t* path_len);
+/* physics objective: CC (Eq. 1) and the distance score of each voxel
+ * against simulated entries. init: [n_vox][4] prior centres or NULL (then
+ * the schedule's starts are used). cc: the CC of the entry returned; score
+ * (may be NULL): its distance score. */
 int orc_zoom(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
              const orc_schedule* sch, const double* vr, const double* vi,
              int32_t n_vox, const int32_t* init, int64_t* idx, double* cc,
-             int32_t* n_sim, double* min_margin, int32_t n_threads);
+             double* score, int32_t* n_sim, double* min_margin, int32_t n_threads);
 
 #ifdef __cplusplus
 }
