@@ -299,9 +299,27 @@ enum {
 #define MRF_ZOOM_MAX_STAGES 32
 #define MRF_ZOOM_MAX_STARTS 16
 
+/* Objective of a stage (Discussion: at the finest resolution the paper
+ * removed its errors at T1 > 2400 ms by matching the non-normalised
+ * fingerprints and entries with the Euclidean distance instead of CC):
+ *   MRF_OBJ_CC   the CC of Eq. 1 (every stage of the paper's schedule);
+ *   MRF_OBJ_DIST the distance of the fingerprint, as given, from the raw
+ *                entry (M0 = 1) with only a global phase fitted, scored as
+ *                -min_phi ||v - exp(i phi) d||^2 / ||v||^2 (0 = perfect
+ *                match). The fingerprint must be in units of M0, i.e. its
+ *                proton-density magnitude divided out (the synthetic
+ *                fingerprints of the paper's experiments have M0 = 1).
+ * A schedule with MRF_OBJ_DIST stages runs a kernel that simulates every
+ * candidate with a compensated FP32 dot product (as accurate as one in
+ * twice the precision) and keeps both values per entry; the distance itself
+ * is formed in FP64 from the two norms and that product. Not available
+ * with smoothing sequences or the resident-dictionary search. */
+enum { MRF_OBJ_CC = 0, MRF_OBJ_DIST = 1 };
+
 typedef struct {
   int32_t kind, axis0, axis1, step0, step1, window;
   double hop;
+  int32_t objective; /* MRF_OBJ_CC or MRF_OBJ_DIST */
 } mrf_zoom_stage;
 
 typedef struct {
@@ -340,6 +358,14 @@ int mrf_zoom_schedule_paper(const mrf_grid* grid, const mrf_sequence* seq,
  * Errors: invalid grid, NULL sched, a NaN half width -> MRF_ERR_INVALID. */
 int mrf_zoom_schedule_prior(const mrf_grid* grid, const double* half, mrf_zoom_schedule* sched);
 
+/* Sets the objective of every stage of the finest resolution (unit index
+ * steps: ZOOM1/ZOOM2 with steps 1, SCAN_WINDOW/SCAN_STRIDE with step 1;
+ * both stage lists) to `objective` (MRF_OBJ_CC or MRF_OBJ_DIST). With
+ * MRF_OBJ_DIST on the paper's schedule: the fine df scan and the final 2-D
+ * zoom (and, with a B1 axis, the outer unit-step rounds). Host only.
+ * Errors: NULL sched, another objective -> MRF_ERR_INVALID. */
+int mrf_zoom_schedule_finest_objective(mrf_zoom_schedule* sched, int32_t objective);
+
 /* Local refinement (not a schedule of the paper: its finest-resolution
  * steps, Methods Experiment 2 step 5, used alone): unit-step 2-D zoom on
  * (T1, T2), unit-step 1-D zoom on df (and on B1 with a B1 axis), repeated
@@ -353,9 +379,13 @@ int mrf_zoom_workspace(mrf_context* ctx, const mrf_grid* grid, int32_t n_vox, in
 
 /* vox: complex64 [n_vox][ld_vox] (first n_tr readouts used). init_idx:
  * device int32 [n_vox][4] prior centres, or NULL (then the schedule's
- * starts are used). Outputs (out): idx, cc, margin (= the smallest decision
- * margin along the voxel's path: best minus runner-up CC among the values
- * compared by one decision), pd_re/pd_im of the found entry, n_sim. */
+ * starts are used). Outputs (out): idx, cc (the CC of the entry returned,
+ * whatever objective its last stage used), margin (= the smallest decision
+ * margin along the voxel's path: best minus runner-up among the values
+ * compared by one decision, in the units of that stage's objective; across
+ * starts, of the last stage's objective), pd_re/pd_im of the found entry,
+ * n_sim. Errors: MRF_ERR_UNSUPPORTED for MRF_OBJ_DIST stages with a
+ * smoothing sequence. */
 int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
                     const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
                     int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,

@@ -93,6 +93,7 @@ def lib():
         L.orc_cc_at.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp, C.c_int32,
                                 C.c_int32, lp, dp, C.c_int32]
         L.orc_prior_half.argtypes = [C.POINTER(GridS), dp, ip]
+        L.orc_schedule_finest_objective.argtypes = [C.POINTER(Schedule), C.c_int32]
         L.orc_objectives_at.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
                                         C.c_int32, C.c_int32, lp, dp, dp, C.c_int32]
         L.orc_zoom_generic.argtypes = [C.POINTER(Schedule), ip, ip, OBJECTIVE, C.c_void_p,
@@ -345,6 +346,14 @@ def schedule_paper(seq, grid) -> dict:
     if rc:
         raise ValueError("orc_schedule_paper failed")
     return schedule_to_dict(out)
+
+
+def schedule_finest_objective(sched: dict, objective: int = OBJ_DIST) -> dict:
+    """A copy of the schedule whose unit-step stages use `objective`."""
+    s = schedule_from_dict(sched)
+    if lib().orc_schedule_finest_objective(C.byref(s), int(objective)):
+        raise ValueError("orc_schedule_finest_objective failed")
+    return schedule_to_dict(s)
 
 
 def prior_half(grid, half=None) -> list:

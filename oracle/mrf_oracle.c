@@ -702,6 +702,27 @@ int orc_prior_half(const orc_grid* g, const double* half, int32_t* out) {
   return 0;
 }
 
+/* Finest resolution (Discussion): the stages at unit index steps get the
+ * given objective. */
+static int finest_stage(const orc_stage* st) {
+  if (st->kind == ORC_ZOOM2) return st->step0 <= 1 && st->step1 <= 1;
+  if (st->kind == ORC_ZOOM1 || st->kind == ORC_SCAN_WINDOW || st->kind == ORC_SCAN_STRIDE)
+    return st->step0 <= 1;
+  return 0;
+}
+
+int orc_schedule_finest_objective(orc_schedule* s, int32_t objective) {
+  if (!s || (objective != ORC_OBJ_CC && objective != ORC_OBJ_DIST)) return 1;
+  if (s->n_stages < 0 || s->n_stages > ORC_MAX_STAGES || s->n_outer < 0 ||
+      s->n_outer > ORC_MAX_STAGES)
+    return 1;
+  for (int i = 0; i < s->n_stages; ++i)
+    if (finest_stage(&s->stages[i])) s->stages[i].objective = objective;
+  for (int i = 0; i < s->n_outer; ++i)
+    if (finest_stage(&s->outer[i])) s->outer[i].objective = objective;
+  return 0;
+}
+
 /* memo: open addressing, key = entry index, both objective values per key */
 typedef struct {
   int64_t* keys;

@@ -131,6 +131,8 @@ int orc_objectives_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
 /* ---- ZOOM ---- */
 int orc_schedule_paper(const orc_grid* grid, const orc_seq* seq,
                        orc_schedule* out);
+/* every stage at unit index steps (the finest resolution) gets `objective` */
+int orc_schedule_finest_objective(orc_schedule* sched, int32_t objective);
 /* neighbour-prior half widths (Experiment 3) in index steps from physical
  * half widths half[4] (T1 ms, T2 ms, df Hz, B1; NULL: 3000, 800, 150, 0.3) */
 int orc_prior_half(const orc_grid* grid, const double* half, int32_t* out);

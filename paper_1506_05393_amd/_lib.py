@@ -80,6 +80,7 @@ _SIGS = [
      [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
       C.POINTER(GridDesc), ResultView, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("mrf_zoom_schedule_finest_objective", C.c_int, [C.c_void_p, C.c_int32]),
     ("mrf_static_scratch_bytes", C.c_size_t, []),
     ("mrf_match_bruteforce_noalloc", C.c_int,
      [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, ResultView,
@@ -125,7 +126,10 @@ ZOOM_MAX_STAGES, ZOOM_MAX_STARTS = 32, 16
 class ZoomStage(C.Structure):
     _fields_ = [("kind", C.c_int32), ("axis0", C.c_int32), ("axis1", C.c_int32),
                 ("step0", C.c_int32), ("step1", C.c_int32), ("window", C.c_int32),
-                ("hop", C.c_double)]
+                ("hop", C.c_double), ("objective", C.c_int32)]
+
+
+OBJ_CC, OBJ_DIST = 0, 1
 
 
 class ZoomSchedule(C.Structure):

@@ -343,7 +343,7 @@ STAGE_KINDS = {"scan_stride": 0, "scan_window": 1, "scan_hops": 2, "zoom1": 3, "
 
 def schedule_to_dict(s: "L.ZoomSchedule") -> dict:
     st = lambda x: dict(kind=x.kind, axis0=x.axis0, axis1=x.axis1, step0=x.step0,
-                        step1=x.step1, window=x.window, hop=x.hop)
+                        step1=x.step1, window=x.window, hop=x.hop, objective=x.objective)
     return dict(stages=[st(s.stages[i]) for i in range(s.n_stages)],
                 outer=[st(s.outer[i]) for i in range(s.n_outer)], outer_max=s.outer_max,
                 starts=[list(s.starts[i]) for i in range(s.n_starts)], pruned=s.pruned,
@@ -355,7 +355,8 @@ def schedule_from_dict(d: dict) -> "L.ZoomSchedule":
     if len(d["stages"]) > L.ZOOM_MAX_STAGES or len(d.get("outer", [])) > L.ZOOM_MAX_STAGES:
         raise ValueError("too many stages")
     mk = lambda x: L.ZoomStage(x["kind"], x["axis0"], x.get("axis1", 0), x.get("step0", 0),
-                               x.get("step1", 0), x.get("window", 0), x.get("hop", 0.0))
+                               x.get("step1", 0), x.get("window", 0), x.get("hop", 0.0),
+                               x.get("objective", L.OBJ_CC))
     s.n_stages = len(d["stages"])
     for i, x in enumerate(d["stages"]):
         s.stages[i] = mk(x)
@@ -378,6 +379,15 @@ def schedule_paper(ctx: Context, seq: Sequence, grid) -> dict:
     g = grid if isinstance(grid, GridArg) else GridArg(grid)
     s = L.ZoomSchedule()
     L.check(ctx._lib.mrf_zoom_schedule_paper(g.ptr, seq.handle, C.byref(s)))
+    return schedule_to_dict(s)
+
+
+def schedule_finest_objective(sched: dict, objective: int = 1) -> dict:
+    """A copy of the schedule with every finest-resolution (unit-step) stage
+    scored by `objective` (libmrf mrf_zoom_schedule_finest_objective; 1: the
+    distance of the non-normalised fingerprint)."""
+    s = schedule_from_dict(sched)
+    L.check(L.load().mrf_zoom_schedule_finest_objective(C.byref(s), int(objective)))
     return schedule_to_dict(s)
 
 

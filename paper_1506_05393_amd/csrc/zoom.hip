@@ -128,15 +128,36 @@ struct EngineParams {
   int32_t dims[4];
 };
 
-template <int G, bool SM, bool GA>
+// Accumulates s + a b as the unevaluated pair (s, c): the rounding error of
+// the product (from an FMA) and of the sum (TwoSum) are gathered in c, the
+// compensated dot product of Ogita, Rump and Oishi ("Dot2"), which is as
+// accurate as a dot product in twice the working precision. Contraction is
+// off so that the product and the sum are each rounded once.
+__device__ __forceinline__ void dot2_acc(float a, float b, float& s, float& c) {
+#pragma clang fp contract(off)
+  const float p = a * b;
+  const float ep = fmaf(a, b, -p);
+  const float t = s + p;
+  const float z = t - s;
+  const float es = (s - (t - z)) + (p - z);
+  s = t;
+  c += ep + es;
+}
+
+// DI: the engine can evaluate both objectives (CC and the distance score of
+// the non-normalised fingerprint); every candidate is then simulated with the
+// compensated dot product and the memo keeps both values.
+template <int G, bool SM, bool GA, bool DI = false>
 struct Engine {
   EngineParams pa;
 
   static constexpr int64_t kIndexMask = ((int64_t)1 << 40) - 1;
   const float2* vx;  // the voxel's fingerprint (global memory, read-only)
   float vinv;        // 1 / ||v||: the unit-norm voxel is vx * vinv
+  double vn;         // ||v|| (FP64)
   int64_t* mkey;     // this wave's memo (global memory)
-  float* mval;
+  float* mval;       // [slots] CC, or with DI [slots][2] (CC, distance score)
+  int32_t obj;       // objective of the stage being run (MRF_OBJ_*; DI only)
   int64_t tag;       // voxel serial << 40
   float* nbv;  // [8] neighbour values of one pruned move (LDS)
   int32_t lane;   // lane within the voxel's group of G lanes
@@ -179,8 +200,9 @@ struct Engine {
   // The smoothing kernel, whose delay line already fills the registers, keeps
   // three (six made it slower: 22-24 -> 27 ms).
   static constexpr int kAhead = SM ? 3 : 6;
-  template <bool LANE_R, bool X_AXIS>
-  __device__ float simulate_cc_t(const int32_t* i, float* pdr, float* pdi, double* pn2) const {
+  template <bool LANE_R, bool X_AXIS, bool COMP>
+  __device__ float simulate_cc_t(const int32_t* i, float* pdr, float* pdi, double* pn2,
+                                 float* psc) const {
     typedef float v2 __attribute__((ext_vector_type(2)));
     typedef float v4 __attribute__((ext_vector_type(4)));
     typedef const __attribute__((address_space(1))) v2 gf2;
@@ -207,6 +229,7 @@ struct Engine {
     };
     Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
     float dr = 0.0f, di = 0.0f;
+    float cr = 0.0f, ci = 0.0f;  // COMP: the compensation terms of dr, di
     double n2 = 0.0;
     // SM: a delay line of five raw samples, demodulated by the RF phase;
     // readout j yields smoothed sample o = j - 2 (scale 0 while o < 0),
@@ -227,8 +250,15 @@ struct Engine {
     auto accumulate = [&](float sx, float sy, v2 v) {
       // v conj(d): (vr + i vi)(x - i y), v the unit-norm voxel
       const float vr = v.x * vinv, vi = v.y * vinv;
-      dr = fmaf(vr, sx, fmaf(vi, sy, dr));
-      di = fmaf(vi, sx, fmaf(-vr, sy, di));
+      if constexpr (COMP) {
+        dot2_acc(vr, sx, dr, cr);
+        dot2_acc(vi, sy, dr, cr);
+        dot2_acc(vi, sx, di, ci);
+        dot2_acc(-vr, sy, di, ci);
+      } else {
+        dr = fmaf(vr, sx, fmaf(vi, sy, dr));
+        di = fmaf(vi, sx, fmaf(-vr, sy, di));
+      }
       n2 = fma((double)sx, (double)sx, n2);
       n2 = fma((double)sy, (double)sy, n2);
     };
@@ -312,11 +342,32 @@ struct Engine {
         }
       }
     }
-    if (pdr) *pdr = dr;
-    if (pdi) *pdi = di;
-    if (pn2) *pn2 = n2;
-    if (!(n2 > 0.0)) return 0.0f;
-    return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
+    if constexpr (COMP) {
+      // the pairs as FP64 values; |<v, d>| = |<v * vinv, d>| / vinv, and
+      // the distance score -||v - exp(i phi) d||^2 / ||v||^2 (best phase)
+      // = -(1 + ||d||^2 / ||v||^2 - 2 |<v, d>| / ||v||^2)
+      const double sr = (double)dr + (double)cr, si = (double)di + (double)ci;
+      const double dabs = sqrt(sr * sr + si * si);
+      if (pdr) *pdr = (float)sr;
+      if (pdi) *pdi = (float)si;
+      if (pn2) *pn2 = n2;
+      if (psc) {
+        const double vv = vn * vn;
+        *psc = vn > 0.0 ? (float)(-(1.0 + n2 / vv - 2.0 * (dabs / (double)vinv) / vv))
+                        : (float)(-n2);
+      }
+      if (!(n2 > 0.0)) return 0.0f;
+      return (float)(dabs / sqrt(n2));
+    } else {
+      (void)cr;
+      (void)ci;
+      (void)psc;
+      if (pdr) *pdr = dr;
+      if (pdi) *pdi = di;
+      if (pn2) *pn2 = n2;
+      if (!(n2 > 0.0)) return 0.0f;
+      return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
+    }
   }
   // GA: CC of up to kGather resident entries against the voxel, read by the
   // whole group: lane l takes readout pairs l, l + G, ... of every entry's
@@ -397,13 +448,15 @@ struct Engine {
     if (pn2) *pn2 = n2[0];
   }
 
+  // DI kernels simulate every candidate with the compensated dot product
+  // (psc receives the distance score)
   __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
-                               double* pn2 = nullptr) const {
+                               double* pn2 = nullptr, float* psc = nullptr) const {
     if (pa.dims[3] > 1)
-      return pa.x_axis ? simulate_cc_t<true, true>(i, pdr, pdi, pn2)
-                       : simulate_cc_t<true, false>(i, pdr, pdi, pn2);
-    return pa.x_axis ? simulate_cc_t<false, true>(i, pdr, pdi, pn2)
-                     : simulate_cc_t<false, false>(i, pdr, pdi, pn2);
+      return pa.x_axis ? simulate_cc_t<true, true, DI>(i, pdr, pdi, pn2, psc)
+                       : simulate_cc_t<true, false, DI>(i, pdr, pdi, pn2, psc);
+    return pa.x_axis ? simulate_cc_t<false, true, DI>(i, pdr, pdi, pn2, psc)
+                     : simulate_cc_t<false, false, DI>(i, pdr, pdi, pn2, psc);
   }
 
   // Memo: this wave's private open-addressing table in global memory. A slot
@@ -419,16 +472,32 @@ struct Engine {
     if constexpr (GA) return mkey[s];
     return __hip_atomic_load(mkey + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // DI: both values of a slot are one 64-bit word (CC low, score high)
+  __device__ float2 memo_ld_pair(uint32_t s) const {
+    const uint64_t w = __hip_atomic_load((uint64_t*)mval + s, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((uint32_t)w), __uint_as_float((uint32_t)(w >> 32)));
+  }
   __device__ float memo_ld_val(uint32_t s) const {
     if constexpr (GA) return mval[s];
+    if constexpr (DI) {
+      const float2 p = memo_ld_pair(s);
+      return obj == MRF_OBJ_DIST ? p.y : p.x;
+    }
     return __hip_atomic_load(mval + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __device__ void memo_st(uint32_t s, int64_t kv, float v) const {
+  __device__ void memo_st(uint32_t s, int64_t kv, float v, float v2 = 0.0f) const {
     if constexpr (GA) {
       mval[s] = v;
       mkey[s] = kv;
     } else {
-      __hip_atomic_store(mval + s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if constexpr (DI) {
+        const uint64_t w = (uint64_t)__float_as_uint(v) | ((uint64_t)__float_as_uint(v2) << 32);
+        __hip_atomic_store((uint64_t*)mval + s, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        (void)v2;
+        __hip_atomic_store(mval + s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       __hip_atomic_store(mkey + s, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -436,6 +505,7 @@ struct Engine {
   // Wave-level evaluation: every lane with `valid` asks for the value at i.
   __device__ float eval(bool valid, const int32_t* i) {
     float val = -INFINITY;
+    float cc_v = -INFINITY, sc_v = -INFINITY;  // DI: both values of a new entry
     bool need = false;
     int64_t k = -1;
     const int32_t cap = pa.memo_cap;
@@ -480,7 +550,14 @@ struct Engine {
           if (lane == srcs[e]) val = cv[e];
       }
     } else {
-      if (need) val = simulate_cc(i);
+      if (need) {
+        if constexpr (DI) {
+          cc_v = simulate_cc(i, nullptr, nullptr, nullptr, &sc_v);
+          val = obj == MRF_OBJ_DIST ? sc_v : cc_v;
+        } else {
+          val = simulate_cc(i);
+        }
+      }
     }
     uint64_t m = grp_ballot<G>(need, gbase);
     n_sim += __popcll(m);
@@ -488,12 +565,13 @@ struct Engine {
       const int src = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       const int64_t ks = __shfl(k, src, G);
-      const float vv = __shfl(val, src, G);
+      const float vv = __shfl(DI ? cc_v : val, src, G);
+      const float v2 = DI ? __shfl(sc_v, src, G) : 0.0f;
       if (memo_count * 4 < cap * 3) {
         if (lane == 0) {
           uint32_t s = memo_home(ks);
           while ((memo_ld_key(s) & ~kIndexMask) == tag) s = (s + 1) & (cap - 1);
-          memo_st(s, tag | ks, vv);
+          memo_st(s, tag | ks, vv, v2);
         }
         ++memo_count;
       } else {
@@ -772,6 +850,14 @@ struct Engine {
   }
 
   __device__ void run_stage(const mrf_zoom_stage& st, bool pruned) {
+    if constexpr (DI) {
+      const int32_t o = st.objective == MRF_OBJ_DIST ? MRF_OBJ_DIST : MRF_OBJ_CC;
+      if (o != obj) {
+        // the centre's value under this stage's objective (a memo hit)
+        obj = o;
+        cknown = false;
+      }
+    }
     switch (st.kind) {
       case MRF_SCAN_STRIDE: scan_stride(st.axis0, st.step0); break;
       case MRF_SCAN_WINDOW: scan_window(st.axis0, st.step0, st.window); break;
@@ -809,7 +895,7 @@ __host__ __device__ inline size_t zoom_gather_memo_lds() {
 // One wave per block, 64 / G voxels per wave: each group of G lanes runs its
 // own voxel's stage machine and pulls its own voxels from the queue, so the
 // lanes that a decision leaves idle in one group work for the others.
-template <int G, bool SM, bool GA>
+template <int G, bool SM, bool GA, bool DI>
 __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   constexpr int NG = 64 / G;
   extern __shared__ __align__(16) unsigned char sm[];
@@ -834,7 +920,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     for (int32_t i = lane; i < kGatherMemo; i += 64) mkey[i] = 0;
   } else {
     mkey = a.memo_keys + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
-    mval = a.memo_vals + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
+    // DI: two values per slot, so each group's block of values is twice as long
+    mval = a.memo_vals + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap * (DI ? 2 : 1);
     memo_cap = a.memo_cap;
     for (int32_t i = lane; i < NG * a.memo_cap; i += 64)
       __hip_atomic_store(a.memo_keys + (int64_t)blockIdx.x * NG * a.memo_cap + i, (int64_t)0,
@@ -872,20 +959,27 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       prior_v = (s * H + py) * W + px;
     }
 
-    // the voxel's norm (FP64); the search reads the voxel scaled by 1 / norm
+    // the voxel's norm (FP64); the search reads the voxel scaled by 1 / norm.
+    // Summed in an order that does not depend on the group size (so neither
+    // does any result): group lane l < 8 adds readouts l, l + 8, ... in
+    // turn, the eight partial sums are added pairwise, and lane 0's total is
+    // broadcast to the group.
     const float2* src = a.vox + (int64_t)v * a.ld_vox;
     double s2 = 0.0;
-    for (int32_t j = glane; j < n; j += G) {
-      const float2 x = src[j];
-      s2 = fma((double)x.x, (double)x.x, s2);
-      s2 = fma((double)x.y, (double)x.y, s2);
+    if (glane < 8) {
+      for (int32_t j = glane; j < n; j += 8) {
+        const float2 x = src[j];
+        s2 = fma((double)x.x, (double)x.x, s2);
+        s2 = fma((double)x.y, (double)x.y, s2);
+      }
     }
-    for (int o = G / 2; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, G);
+    for (int o = 4; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, G);
+    s2 = __shfl(s2, 0, G);
     const double nv = sqrt(s2);
     const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
     ++serial;
 
-    Engine<G, SM, GA> e;
+    Engine<G, SM, GA, DI> e;
     e.pa.t1T = a.t1T;
     e.pa.t1ti = a.t1ti;
     e.pa.t2T = a.t2T;
@@ -904,6 +998,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
 
     e.vx = src;
     e.vinv = inv;
+    e.vn = nv;
+    e.obj = MRF_OBJ_CC;
     e.mkey = mkey;
     e.mval = mval;
     e.tag = serial << 40;
@@ -944,6 +1040,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       const int32_t* s0 = init ? init : S->starts[st];
       for (int q = 0; q < 4; ++q) e.c[q] = min(max(s0[q], e.lo[q]), e.hi[q]);
       e.cknown = false;
+      e.obj = MRF_OBJ_CC;
       for (int i = 0; i < S->n_stages; ++i) e.run_stage(S->stages[i], S->pruned != 0);
       for (int r = 0; r < S->outer_max && S->n_outer > 0; ++r) {
         const int32_t b0 = e.c[0], b1 = e.c[1], b2 = e.c[2], b3 = e.c[3];
@@ -966,23 +1063,28 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     for (int st = 0; st < n_starts; ++st)
       if (fin_k[st] != bk) e.log_pair(bv, fin_v[st]);
 
-    // proton density of the found entry: <v, d> / ||d||^2
+    // proton density of the found entry: <v, d> / ||d||^2 (and, for DI, its
+    // CC: the search's last values may be distance scores)
     float dr = 0.0f, di = 0.0f;
     double n2 = 0.0;
+    float cc_best = bv;
     if constexpr (GA) {
       if (a.pd_re || a.pd_im) {
-        constexpr int KG = Engine<G, SM, GA>::kGather;
+        constexpr int KG = Engine<G, SM, GA, DI>::kGather;
         int64_t ks[KG];
         for (int q = 0; q < KG; ++q) ks[q] = bk;
         float cv[KG];
         e.gather_cc(ks, 1, cv, &dr, &di, &n2);
       }
     } else {
-      if (glane == 0 && (a.pd_re || a.pd_im)) e.simulate_cc(bi, &dr, &di, &n2);
+      if (glane == 0 && (DI || a.pd_re || a.pd_im)) {
+        const float c1 = e.simulate_cc(bi, &dr, &di, &n2);
+        if (DI) cc_best = c1;
+      }
     }
     if (glane == 0) {
       a.idx[v] = bk;
-      if (a.cc) a.cc[v] = bv;
+      if (a.cc) a.cc[v] = cc_best;
       if (a.margin) a.margin[v] = e.mm;
       if (a.n_sim) a.n_sim[v] = e.overflow ? -e.n_sim : e.n_sim;
       if (a.pd_re) a.pd_re[v] = n2 > 0.0 ? (float)(nv * (double)dr / n2) : 0.0f;
@@ -995,21 +1097,21 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-template <bool SM, bool GA>
+template <bool SM, bool GA, bool DI = false>
 static void launch_zoom_groups(int group, int blocks, size_t lds, hipStream_t st,
                                const ZoomArgs& a) {
   if constexpr (GA) {
     (void)group;  // whole-wave groups (zoom_plan)
-    hipLaunchKernelGGL((k_zoom<64, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((k_zoom<64, SM, GA, DI>), dim3(blocks), dim3(64), lds, st, a);
   } else {
     if (group == 8)
-      hipLaunchKernelGGL((k_zoom<8, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+      hipLaunchKernelGGL((k_zoom<8, SM, GA, DI>), dim3(blocks), dim3(64), lds, st, a);
     else if (group == 16)
-      hipLaunchKernelGGL((k_zoom<16, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+      hipLaunchKernelGGL((k_zoom<16, SM, GA, DI>), dim3(blocks), dim3(64), lds, st, a);
     else if (group == 32)
-      hipLaunchKernelGGL((k_zoom<32, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+      hipLaunchKernelGGL((k_zoom<32, SM, GA, DI>), dim3(blocks), dim3(64), lds, st, a);
     else
-      hipLaunchKernelGGL((k_zoom<64, SM, GA>), dim3(blocks), dim3(64), lds, st, a);
+      hipLaunchKernelGGL((k_zoom<64, SM, GA, DI>), dim3(blocks), dim3(64), lds, st, a);
   }
 }
 
@@ -1040,6 +1142,7 @@ static mrf_zoom_stage stage(int32_t kind, int32_t a0, int32_t a1, int32_t s0, in
   s.step1 = s1;
   s.window = w;
   s.hop = hop;
+  s.objective = MRF_OBJ_CC;
   return s;
 }
 
@@ -1085,7 +1188,9 @@ static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_en
   p.off_sched = 256;
   p.off_keys = al(p.off_sched + sizeof(mrf_zoom_schedule));
   p.off_vals = al(p.off_keys + sizeof(int64_t) * slots);
-  p.total = al(p.off_vals + sizeof(float) * slots);
+  // values: one float per slot, or two (CC, distance score) for schedules
+  // with distance stages
+  p.total = al(p.off_vals + 2 * sizeof(float) * slots);
   return p;
 }
 
@@ -1162,6 +1267,29 @@ extern "C" int mrf_zoom_schedule_prior(const mrf_grid* g, const double* half,
   return MRF_OK;
 }
 
+extern "C" int mrf_zoom_schedule_finest_objective(mrf_zoom_schedule* o, int32_t objective) {
+  MRF_CHECK_ARG(o, "NULL argument");
+  MRF_CHECK_ARG(objective == MRF_OBJ_CC || objective == MRF_OBJ_DIST,
+                "objective must be MRF_OBJ_CC or MRF_OBJ_DIST");
+  MRF_CHECK_ARG(o->n_stages >= 0 && o->n_stages <= MRF_ZOOM_MAX_STAGES &&
+                    o->n_outer >= 0 && o->n_outer <= MRF_ZOOM_MAX_STAGES,
+                "bad stage counts");
+  auto finest = [](const mrf_zoom_stage& st) {
+    switch (st.kind) {
+      case MRF_ZOOM2: return st.step0 <= 1 && st.step1 <= 1;
+      case MRF_ZOOM1:
+      case MRF_SCAN_WINDOW:
+      case MRF_SCAN_STRIDE: return st.step0 <= 1;
+      default: return false;
+    }
+  };
+  for (int i = 0; i < o->n_stages; ++i)
+    if (finest(o->stages[i])) o->stages[i].objective = objective;
+  for (int i = 0; i < o->n_outer; ++i)
+    if (finest(o->outer[i])) o->outer[i].objective = objective;
+  return MRF_OK;
+}
+
 extern "C" int mrf_zoom_schedule_local(const mrf_grid* g, int32_t outer_max,
                                        mrf_zoom_schedule* o) {
   int rc = check_grid(g);
@@ -1204,6 +1332,8 @@ static int check_schedule(const mrf_zoom_schedule* s, const int32_t* dims) {
       MRF_CHECK_ARG(st[i].kind != MRF_ZOOM2 || st[i].axis0 != st[i].axis1,
                     "stage %d: a 2-D zoom needs two different axes", i);
       MRF_CHECK_ARG(st[i].window >= 0 && std::isfinite(st[i].hop), "stage %d: bad window/hop", i);
+      MRF_CHECK_ARG(st[i].objective == MRF_OBJ_CC || st[i].objective == MRF_OBJ_DIST,
+                    "stage %d: unknown objective %d", i, st[i].objective);
     }
   }
   for (int i = 0; i < s->n_starts; ++i)
@@ -1259,6 +1389,13 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   if (n_vox == 0) return MRF_OK;
   MRF_CHECK_ARG(vox != nullptr && out.idx != nullptr, "vox and out.idx must not be NULL");
   MRF_CHECK_ARG(ld_vox >= n_tr, "ld_vox must be >= n_tr");
+  bool dist = false;  // any stage scored by the distance objective
+  for (int i = 0; i < sched->n_stages; ++i) dist |= sched->stages[i].objective == MRF_OBJ_DIST;
+  for (int i = 0; i < sched->n_outer; ++i) dist |= sched->outer[i].objective == MRF_OBJ_DIST;
+  if (dist && (dict || seq->smooth)) {
+    set_error("distance-objective stages need the simulating search without smoothing");
+    return MRF_ERR_UNSUPPORTED;
+  }
   const ZoomPlan plan = zoom_plan(ctx->n_cu, n_vox, n_tr, grid_size_checked(grid), dict != nullptr);
   MRF_CHECK_ARG(workspace != nullptr && ws_bytes >= plan.total,
                 "workspace too small (%zu < %zu bytes)", ws_bytes, plan.total);
@@ -1319,6 +1456,8 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
       launch_zoom_groups<false, true>(plan.group, blocks, lds, st, a);
     else if (t->smooth)
       launch_zoom_groups<true, false>(plan.group, blocks, lds, st, a);
+    else if (dist)
+      launch_zoom_groups<false, false, true>(plan.group, blocks, lds, st, a);
     else
       launch_zoom_groups<false, false>(plan.group, blocks, lds, st, a);
   };

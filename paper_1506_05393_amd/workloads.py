@@ -60,6 +60,28 @@ def volume(n_slices: int = 8, side: int = 256) -> Workload:
     return Workload(f"volume{n_slices}x{side}x{side}_N1000_B1", seq, grid, ph, 1000)
 
 
+def exp3_slice(n_tr: int = 500) -> Workload:
+    """Experiment 3's searching ranges at its finest resolution: T1 800-3200 ms
+    and T2 50-600 ms at 1 ms, df -48-84 Hz at 1 Hz (the paper's half-open
+    ranges; 2401 x 551 x 133 = 175,952,483 entries, never stored), N = 500
+    readouts of the sequence family (seed 1). 64x64 smooth phantom (seed 103)
+    whose truths are rounded onto that grid; noise-free, unit PD and zero
+    phase, as the paper's synthetic fingerprints (ZOOM only)."""
+    seq = I.make_sequence(n_tr, 1)
+    grid = I.make_grid(I.grid_halfopen(800, 3201, 1), I.grid_halfopen(50, 601, 1),
+                       I.grid_halfopen(-48, 85, 1))
+    ph = I.phantom_smooth(64, 103, snr=float("inf"), t1_range=(800.0, 3200.0),
+                          t2_range=(50.0, 600.0), df_range=(-48.0, 84.0))
+    i1 = np.clip(np.rint(ph.t1 - 800.0), 0, len(grid.t1_ms) - 1).astype(np.int64)
+    i2 = np.clip(np.rint(ph.t2 - 50.0), 0, len(grid.t2_ms) - 1).astype(np.int64)
+    i3 = np.clip(np.rint(ph.df + 48.0), 0, len(grid.df_hz) - 1).astype(np.int64)
+    nv = ph.n_vox
+    on = I.Phantom(ph.shape, grid.t1_ms[i1], grid.t2_ms[i2], grid.df_hz[i3], np.ones(nv),
+                   grid.ravel(i1, i2, i3), np.zeros(nv), np.ones(nv), float("inf"),
+                   ph.noise_key)
+    return Workload(f"exp3_slice64x64_N{n_tr}_E{grid.size}", seq, grid, on, n_tr)
+
+
 def exp1_ccmap():
     """CC mapping after Experiment 1: T1 100-5500 ms and T2 50-1200 ms at
     10 ms, df -300-300 Hz at 1 Hz (half-open ranges: 540 x 115 x 600 =

@@ -96,3 +96,19 @@ def test_prior_schedule_builder_matches_hand_worked_and_oracle(orc):
         assert api.prior_half_widths(g, *half) == orc.prior_half(g, half)
     s = api.schedule_with_prior(dict(stages=[], starts=[[0, 0, 0, 0]]), workloads.slice64().grid)
     assert s["prior_half"] == [300, 160, 150, -1]
+
+
+def test_finest_objective_builder_matches_oracle(orc):
+    """mrf_zoom_schedule_finest_objective (host only) flags the same stages
+    as the oracle's builder: the unit-step ones of both lists."""
+    from paper_1506_05393_amd import api, workloads
+    for w in (workloads.small_dgs(), workloads.slice64(), workloads.volume(1, 8)):
+        s = orc.schedule_paper(w.seq, w.grid)
+        a = api.schedule_finest_objective(s, 1)
+        b = orc.schedule_finest_objective(s, 1)
+        assert a == b
+        for st in a["stages"] + a["outer"]:
+            unit = (st["kind"] == 4 and st["step0"] <= 1 and st["step1"] <= 1) or \
+                   (st["kind"] in (0, 1, 3) and st["step0"] <= 1)
+            assert st["objective"] == (1 if unit else 0)
+        assert api.schedule_finest_objective(a, 0) == s
