@@ -247,6 +247,14 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def host_threads() -> int:
+    """The host threads this process may use (affinity), capped by OMP_NUM_THREADS."""
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
+    return threads
+
+
 def cpu_baseline(w, target_s: float):
     """The FP64 oracle's brute force on a bounded sample: a few voxels against
     a leading slab of T1 rows of the grid, extrapolated to the whole grid."""
@@ -259,10 +267,7 @@ def cpu_baseline(w, target_s: float):
     clean = np.stack([oracle.simulate(w.seq, ph.t1[v], ph.t2[v], ph.df[v], ph.b1[v])
                       for v in vox])
     V = I.compose_fingerprints(clean, ph, vox).astype(np.complex64)
-    # the host threads this process may use (affinity), capped by OMP_NUM_THREADS
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
-        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
+    threads = host_threads()
     # calibrate on 2 T1 rows, then size the sample to about target_s
     rows = 2
     sub = I.make_grid(w.grid.t1_ms[:rows], w.grid.t2_ms, w.grid.df_hz)
@@ -287,6 +292,160 @@ def cpu_baseline(w, target_s: float):
                          "sample": f"{nv} voxels x {sub1.size} entries (1 T1 row) in {dt1:.1f} s"},
             "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
+
+def _param_errors(grid, idx, ref_idx):
+    """Mean and max |dT1| (ms), |dT2| (ms), |ddf| (Hz) between grid entries."""
+    a = np.stack(grid.values(np.asarray(idx, np.int64))[:3], axis=1)
+    b = np.stack(grid.values(np.asarray(ref_idx, np.int64))[:3], axis=1)
+    d = np.abs(a - b)
+    return {k: {"mean": float(d[:, i].mean()), "max": float(d[:, i].max())}
+            for i, k in enumerate(("T1_ms", "T2_ms", "df_Hz"))}
+
+
+def _agreement(idx, ref_idx, pinned):
+    same = np.asarray(idx) == np.asarray(ref_idx)
+    return {"pinned": int(pinned.sum()), "voxels": int(len(same)),
+            "agreement_pinned": float(same[pinned].mean()) if pinned.any() else None,
+            "agreement_all": float(same.mean())}
+
+
+def oracle_agreement(api, ctx, torch, threads: int):
+    """The small workload (16x16 phantom, N = 200, 50,400 entries; on-grid and
+    off-grid truths) with fingerprints synthesised by the oracle: the FP64
+    oracle's brute force and ZOOM (paper schedule and the 4 x 4 multi-start
+    schedule), timed on all host threads and on one, against the library's
+    FP32 brute force, BF16 + re-scoring, and both ZOOM schedules on the same
+    fingerprints. Agreement on pinned voxels (oracle margin > 1e-5) and on
+    all, and the T1/T2/df errors against the oracle."""
+    import oracle
+    from paper_1506_05393_amd import inputs as I
+    from paper_1506_05393_amd import workloads as W
+    out = {}
+    for on_grid in (True, False):
+        w = W.small_dgs(on_grid)
+        ph = w.phantom
+        clean = np.stack([oracle.simulate(w.seq, ph.t1[v], ph.t2[v], ph.df[v], ph.b1[v])
+                          for v in range(ph.n_vox)])
+        V = I.compose_fingerprints(clean, ph).astype(np.complex64)
+        s_paper = oracle.schedule_paper(w.seq, w.grid)
+        s_multi = oracle.schedule_multistart(w.seq, w.grid, 4, 4, 8)
+        t = time.perf_counter()
+        bf = oracle.bruteforce(w.seq, w.grid, V, top_k=2, threads=threads)
+        t_bf = time.perf_counter() - t
+        t = time.perf_counter()
+        zp = oracle.zoom(w.seq, w.grid, s_paper, V, threads=threads)
+        t_zp = time.perf_counter() - t
+        t = time.perf_counter()
+        zm = oracle.zoom(w.seq, w.grid, s_multi, V, threads=threads)
+        t_zm = time.perf_counter() - t
+        sub = np.arange(0, ph.n_vox, 16)  # one core: every 16th voxel
+        t = time.perf_counter()
+        oracle.bruteforce(w.seq, w.grid, V[sub], threads=1)
+        t_bf1 = (time.perf_counter() - t) * ph.n_vox / len(sub)
+        t = time.perf_counter()
+        oracle.zoom(w.seq, w.grid, s_multi, V[sub], threads=1)
+        t_zm1 = (time.perf_counter() - t) * ph.n_vox / len(sub)
+        # the library on the same fingerprints
+        sq = api.Sequence(ctx, w.seq)
+        Vd = torch.from_numpy(V).cuda()
+        d32 = api.simulate_dictionary(ctx, sq, w.grid, dtype="f32")
+        d16 = api.simulate_dictionary(ctx, sq, w.grid, dtype="bf16")
+        gpu = {"fp32": api.match_bruteforce(ctx, d32, Vd, top_k=2),
+               "bf16_rescore": api.match_bruteforce(ctx, d16, Vd, top_k=8, seq=sq, grid=w.grid),
+               "zoom_paper": api.zoom_search(ctx, sq, w.grid, Vd, sched=s_paper),
+               "zoom_multistart_4x4": api.zoom_search(ctx, sq, w.grid, Vd, sched=s_multi)}
+        torch.cuda.synchronize()
+        pin_bf = bf["margin"] > 1e-5
+        res = {"oracle_seconds": {"bruteforce": t_bf, "zoom_paper": t_zp,
+                                  "zoom_multistart_4x4": t_zm, "threads": threads,
+                                  "bruteforce_one_core": t_bf1,
+                                  "zoom_multistart_4x4_one_core": t_zm1,
+                                  "one_core_sample": f"every 16th voxel ({len(sub)}), scaled"},
+               "oracle_zoom_vs_bruteforce": {
+                   "paper": _agreement(zp["idx"], bf["idx"], pin_bf),
+                   "multistart_4x4": _agreement(zm["idx"], bf["idx"], pin_bf),
+                   "n_sim_mean": {"paper": float(zp["n_sim"].mean()),
+                                  "multistart_4x4": float(zm["n_sim"].mean())}}}
+        for name, r in gpu.items():
+            idx = r["idx"].cpu().numpy()
+            cc = r["cc"].cpu().numpy().astype(np.float64)
+            ref = bf if not name.startswith("zoom") else (zp if name == "zoom_paper" else zm)
+            pin = pin_bf if ref is bf else ref["min_margin"] > 1e-5
+            e = {"vs": "oracle brute force" if ref is bf else "oracle ZOOM, same schedule",
+                 **_agreement(idx, ref["idx"], pin),
+                 "max_abs_dCC": float(np.abs(cc - ref["cc"]).max()),
+                 "param_error_vs_oracle": _param_errors(w.grid, idx, ref["idx"])}
+            if on_grid:
+                e["param_error_vs_truth"] = _param_errors(w.grid, idx, ph.truth_idx)
+            if name.startswith("zoom"):
+                e["agreement_with_oracle_bruteforce"] = _agreement(idx, bf["idx"], pin_bf)
+                e["n_sim_mean"] = float(r["n_sim"].double().mean().item())
+            res[name] = e
+        out["on_grid" if on_grid else "off_grid"] = res
+        del d32, d16
+    return out
+
+
+def slice_epsilon_agreement(w, gpu: dict):
+    """The slice workload against the stored oracle brute force of its seeded
+    64-voxel subset (tests/golden/slice64_bruteforce_oracle.json, written by
+    the oracle alone): for each GPU path the fraction of subset voxels whose
+    returned entry's oracle CC, against the oracle's own fingerprint, is
+    within 1e-5 of the oracle's best, and index agreement on pinned ones."""
+    import oracle
+    from paper_1506_05393_amd import inputs as I
+    path = os.path.join(ROOT, "tests", "golden", "slice64_bruteforce_oracle.json")
+    with open(path) as f:
+        G = json.load(f)
+    vox = np.array(G["noisy_voxels"])
+    n = len(vox)
+    ph = w.phantom
+    clean = np.stack([oracle.simulate(w.seq, ph.t1[v], ph.t2[v], ph.df[v], ph.b1[v])
+                      for v in vox])
+    V = I.compose_fingerprints(clean, ph, vox).astype(np.complex64)
+    best = np.array(G["cc"][:n])
+    pinned = np.array(G["margin"][:n]) > 1e-5
+    ref_idx = np.array(G["idx"][:n])
+    out = {"subset": f"{n} phantom voxels (PCG64(2024)), oracle brute force over the full grid",
+           "pinned": int(pinned.sum())}
+    for name, idx in gpu.items():
+        at = oracle.cc_at(w.seq, w.grid, V, idx[vox][:, None])[:, 0]
+        out[name] = {"eps_agreement_1e-5": float(np.mean(at >= best - 1e-5)),
+                     "index_agreement": float(np.mean(idx[vox] == ref_idx)),
+                     "index_agreement_pinned": (float(np.mean(idx[vox][pinned] == ref_idx[pinned]))
+                                                if pinned.any() else None),
+                     "max_shortfall": float(np.max(best - at))}
+    return out
+
+
+def slice_zoom_oracle_timing(w, threads: int):
+    """The oracle's ZOOM (paper schedule) on every voxel of the slice, all host
+    threads, and on every 16th voxel on one core (scaled)."""
+    import oracle
+    from paper_1506_05393_amd import inputs as I
+    ph = w.phantom
+    clean = np.stack([oracle.simulate(w.seq, ph.t1[v], ph.t2[v], ph.df[v], ph.b1[v])
+                      for v in range(ph.n_vox)])
+    V = I.compose_fingerprints(clean, ph).astype(np.complex64)
+    s = oracle.schedule_paper(w.seq, w.grid)
+    t = time.perf_counter()
+    z = oracle.zoom(w.seq, w.grid, s, V, threads=threads)
+    t_all = time.perf_counter() - t
+    sub = np.arange(0, ph.n_vox, 16)
+    t = time.perf_counter()
+    oracle.zoom(w.seq, w.grid, s, V[sub], threads=1)
+    t_one = (time.perf_counter() - t) * ph.n_vox / len(sub)
+    return {"value": ph.n_vox / t_all, "unit": "voxels/s", "cores": threads,
+            "seconds": t_all, "n_sim_mean": float(z["n_sim"].mean()),
+            "one_core": {"value": ph.n_vox / t_one, "unit": "voxels/s",
+                         "sample": f"every 16th voxel ({len(sub)}) on one core, scaled"}}
+
+
+# Flops per simulated readout of a ZOOM candidate with pulses about x (RF
+# phases 0/180 deg, the benchmark sequences): pulse 6, two free-evolution
+# intervals 2 x 15, the voxel scaling 2 and v conj(d) 8 in FP32, |d|^2 4 in
+# FP64; rated against the FP32 VALU peak without packed FP32.
+ZOOM_FLOPS_PER_STEP = 50.0
 
 # FP32 flops per entry and readout of the CC-map recursion with general RF
 # pulses: 3x3 rotation (15), two precession + relaxation intervals (2 x 10),
@@ -605,6 +764,18 @@ def main():
     torch.cuda.synchronize()
     zl = [a_.elapsed_time(b_) for a_, b_ in zl]
     nsim = outz["n_sim"].cpu().numpy()
+    # the 4 x 4 multi-start schedule on the same slice
+    sched_ms = api.schedule_multistart(ctx, sq, ga, 4, 4, 8)
+    outzm = api._result_tensors(n_vox, ctx.device, with_nsim=True)
+    zm = []
+    for _ in range(10):
+        a_, b_ = ev(), ev()
+        a_.record()
+        api.zoom_search(ctx, sq, ga, vox, sched=sched_ms, workspace=wsz, out=outzm)
+        b_.record()
+        zm.append((a_, b_))
+    torch.cuda.synchronize()
+    zm = [a_.elapsed_time(b_) for a_, b_ in zm]
     ccm = None
     if not args.no_ccmap:
         log("cc map (Experiment 1) ...")
@@ -698,11 +869,32 @@ def main():
                      "bf16_ms": float(np.median(per_row["dict_bf16"])),
                      "bf16_GB_per_s": (E * N * 4 + E * 8) /
                                       (float(np.median(per_row["dict_bf16"])) * 1e-3) / 1e9},
+        "zoom_multistart": {
+            "schedule": "paper stages from a 4 x 4 start lattice over T1/T2 (ends included), "
+                        "outer rounds [df window, fine df, 2-D zooms 100/50/20/10/1 ms] <= 8",
+            "slice_ms_p50": float(np.percentile(zm, 50)),
+            "slice_ms_p99": float(np.percentile(zm, 99)), "repeats": len(zm),
+            "voxels_per_s": n_vox / (float(np.median(zm)) * 1e-3),
+            "n_sim_mean": float(outzm["n_sim"].double().mean().item()),
+            "speedup_vs_f32": float(np.median(per_row["match_f32"]) / np.median(zm)),
+            "speedup_vs_bf16": float(np.median(per_row["match_bf16_rescore"]) / np.median(zm)),
+            "index_agreement_vs_f32": float(np.mean(outzm["idx"].cpu().numpy() == idx32))},
         "zoom_voxels_per_s": n_vox / (float(np.median(zl)) * 1e-3),
         "zoom": {"schedule": "paper (Methods, Experiment 2 steps 1-5)",
                  "n_sim_mean": float(nsim.mean()), "n_sim_max": int(nsim.max()),
                  "slice_ms_p50": float(np.percentile(zl, 50)),
-                 "slice_ms_p99": float(np.percentile(zl, 99)), "repeats": len(zl)},
+                 "slice_ms_p99": float(np.percentile(zl, 99)), "repeats": len(zl),
+                 "roofline": {
+                     "bound": "alu", "kernel": "k_zoom",
+                     "achieved": float(nsim.sum()) * N * ZOOM_FLOPS_PER_STEP /
+                                 (float(np.median(zl)) * 1e-3) / 1e12,
+                     "peak": FP32_VALU_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                     "frac": float(nsim.sum()) * N * ZOOM_FLOPS_PER_STEP /
+                             (float(np.median(zl)) * 1e-3) / 1e12 / FP32_VALU_UNPACKED_TFLOPS,
+                     "flops_per_readout": ZOOM_FLOPS_PER_STEP,
+                     "algorithmic_flops_per_launch": float(nsim.sum()) * N * ZOOM_FLOPS_PER_STEP,
+                     "note": "sum over voxels of entries simulated x readouts x flops per "
+                             "readout, over the slice's median call time"}},
         "slice_latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                              "p99": float(np.percentile(step_ms, 99))},
         "device_peaks": peaks,
@@ -735,7 +927,42 @@ def main():
             f"p99 {res['serving']['latency_ms_p99']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        cb = cpu_baseline(w, args.cpu_seconds)
+        if args.workload == "slice64":
+            th = host_threads()
+            log("oracle ZOOM on the slice ...")
+            cb["zoom"] = slice_zoom_oracle_timing(w, th)
+            log("agreement with the oracle (small workload, slice subset) ...")
+            res["agreement_vs_oracle"] = {
+                "small_dgs": oracle_agreement(api, ctx, torch, th),
+                "slice64_subset": slice_epsilon_agreement(
+                    w, {"fp32": idx32, "bf16_rescore": idx16, "zoom_paper": idxz,
+                        "zoom_multistart_4x4": outzm["idx"].cpu().numpy(),
+                        "fp32_refined": rf32})}
+        res["cpu_baseline"] = cb
+        if "agreement_vs_oracle" in res:
+            ag = res["agreement_vs_oracle"]
+            small = ag["small_dgs"]
+            sl = ag["slice64_subset"]
+            pin = lambda k: min(small[g][k]["agreement_pinned"] for g in ("on_grid", "off_grid"))
+            pin_bf = lambda k: min(small[g][k]["agreement_with_oracle_bruteforce"]
+                                   ["agreement_pinned"] for g in ("on_grid", "off_grid"))
+            res["speedups_at_agreement"] = {
+                "what": "speedup on the 64x64 slice; agreement with the FP64 oracle's brute force "
+                        "on pinned voxels (margin > 1e-5) of the small workload (on- and off-grid, "
+                        "the lower) and the fraction of the slice's stored 64-voxel oracle subset "
+                        "within 1e-5 of the best CC",
+                "bf16_rescore_vs_fp32": {"speedup": res["bf16"]["speedup_vs_f32"],
+                                         "agreement_pinned_small": pin("bf16_rescore"),
+                                         "eps_agreement_slice": sl["bf16_rescore"]["eps_agreement_1e-5"]},
+                "zoom_multistart_4x4_vs_fp32": {
+                    "speedup": res["zoom_multistart"]["speedup_vs_f32"],
+                    "agreement_pinned_small": pin_bf("zoom_multistart_4x4"),
+                    "eps_agreement_slice": sl["zoom_multistart_4x4"]["eps_agreement_1e-5"]},
+                "zoom_paper_vs_fp32": {
+                    "speedup": res["zoom_vs_brute"]["speedup_vs_f32"],
+                    "agreement_pinned_small": pin_bf("zoom_paper"),
+                    "eps_agreement_slice": sl["zoom_paper"]["eps_agreement_1e-5"]}}
     print(json.dumps(res), flush=True)
 
 

@@ -358,6 +358,24 @@ int mrf_zoom_schedule_paper(const mrf_grid* grid, const mrf_sequence* seq,
  * Errors: invalid grid, NULL sched, a NaN half width -> MRF_ERR_INVALID. */
 int mrf_zoom_schedule_prior(const mrf_grid* grid, const double* half, mrf_zoom_schedule* sched);
 
+/* Multi-start form of the paper's schedule (Methods, Experiment 2 steps
+ * 1-5 from several initial values; Discussion: "a second searching process
+ * can be used after finding an approximate value for T1 and T2"): the
+ * stages of mrf_zoom_schedule_paper run from each of n_t1 x n_t2 starts, an
+ * index lattice over the T1 and T2 axes from their first to their last
+ * value (round_half_away(q (n - 1) / (k - 1)); one start per axis sits at
+ * index (n - 1) / 2), df index 0; then an outer round [df window scan,
+ * fine df scan, 2-D zooms at 100, 50, 20 and 10 ms, unit 2-D zoom (, unit
+ * B1 zoom)] is repeated up to outer_max times until the centre stays; the
+ * best final CC over the starts wins. 4 x 4 starts with outer_max 8 is the
+ * cheapest lattice found to agree with brute force on every voxel whose
+ * brute-force margin exceeds 1e-5 on the small workload (~970 entries per
+ * voxel against 50,400). Host only.
+ * Errors: as mrf_zoom_schedule_paper; n_t1 * n_t2 outside
+ * [1, MRF_ZOOM_MAX_STARTS] or outer_max outside [0, 64] -> MRF_ERR_INVALID. */
+int mrf_zoom_schedule_multistart(const mrf_grid* grid, const mrf_sequence* seq, int32_t n_t1,
+                                 int32_t n_t2, int32_t outer_max, mrf_zoom_schedule* out);
+
 /* Sets the objective of every stage of the finest resolution (unit index
  * steps: ZOOM1/ZOOM2 with steps 1, SCAN_WINDOW/SCAN_STRIDE with step 1;
  * both stage lists) to `objective` (MRF_OBJ_CC or MRF_OBJ_DIST). With

@@ -94,6 +94,8 @@ def lib():
                                 C.c_int32, lp, dp, C.c_int32]
         L.orc_prior_half.argtypes = [C.POINTER(GridS), dp, ip]
         L.orc_schedule_finest_objective.argtypes = [C.POINTER(Schedule), C.c_int32]
+        L.orc_schedule_multistart.argtypes = [C.POINTER(GridS), C.POINTER(Seq), C.c_int32,
+                                              C.c_int32, C.c_int32, C.POINTER(Schedule)]
         L.orc_objectives_at.argtypes = [C.POINTER(Seq), C.POINTER(GridS), C.c_int32, dp, dp,
                                         C.c_int32, C.c_int32, lp, dp, dp, C.c_int32]
         L.orc_zoom_generic.argtypes = [C.POINTER(Schedule), ip, ip, OBJECTIVE, C.c_void_p,
@@ -345,6 +347,16 @@ def schedule_paper(seq, grid) -> dict:
     rc = lib().orc_schedule_paper(C.byref(g), C.byref(s), C.byref(out))
     if rc:
         raise ValueError("orc_schedule_paper failed")
+    return schedule_to_dict(out)
+
+
+def schedule_multistart(seq, grid, k1: int = 4, k2: int = 4, outer_max: int = 8) -> dict:
+    """The paper's stages from a k1 x k2 start lattice, then outer rounds."""
+    s, ks = make_seq(seq)
+    g, kg = make_grid(grid)
+    out = Schedule()
+    if lib().orc_schedule_multistart(C.byref(g), C.byref(s), k1, k2, outer_max, C.byref(out)):
+        raise ValueError("orc_schedule_multistart failed")
     return schedule_to_dict(out)
 
 

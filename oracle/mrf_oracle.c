@@ -679,6 +679,42 @@ int orc_schedule_paper(const orc_grid* g, const orc_seq* seq, orc_schedule* o) {
   return 0;
 }
 
+/* The paper's stages from several initial values (Methods, Experiment 2;
+ * Discussion: a second searching process after approximate T1 and T2):
+ * k1 x k2 starts spread evenly over the T1 and T2 index ranges, ends
+ * included, df index 0; afterwards the rounds [df scan of step 3 within the
+ * 75 Hz window, finest df scan, 2-D zooms at 100, 50, 20, 10 ms and at unit
+ * steps (+ unit B1 zoom)] repeat at most outer_max times while the centre
+ * moves. */
+int orc_schedule_multistart(const orc_grid* g, const orc_seq* seq, int32_t k1, int32_t k2,
+                            int32_t outer_max, orc_schedule* o) {
+  if (orc_schedule_paper(g, seq, o)) return 1;
+  if (k1 < 1 || k2 < 1 || k1 * k2 > ORC_MAX_STARTS || outer_max < 0) return 1;
+  int32_t b1 = o->starts[0][3];
+  o->n_starts = 0;
+  for (int32_t a = 0; a < k1; ++a) {
+    for (int32_t b = 0; b < k2; ++b) {
+      int32_t* st = o->starts[o->n_starts++];
+      st[0] = k1 == 1 ? (g->n1 - 1) / 2 : round_half_away((double)a * (g->n1 - 1) / (k1 - 1));
+      st[1] = k2 == 1 ? (g->n2 - 1) / 2 : round_half_away((double)b * (g->n2 - 1) / (k2 - 1));
+      st[2] = 0;
+      st[3] = b1;
+    }
+  }
+  int32_t n = 0;
+  o->outer[n++] = o->stages[1]; /* df window, step 3 Hz */
+  o->outer[n++] = o->stages[5]; /* finest df scan */
+  const double r[4] = {100.0, 50.0, 20.0, 10.0};
+  for (int i = 0; i < 4; ++i)
+    o->outer[n++] = mk(ORC_ZOOM2, 0, 1, idx_step(r[i], g->t1, g->n1), idx_step(r[i], g->t2, g->n2),
+                       0, 0.0);
+  o->outer[n++] = mk(ORC_ZOOM2, 0, 1, 1, 1, 0, 0.0);
+  if (g->n4 > 1) o->outer[n++] = mk(ORC_ZOOM1, 3, 0, 1, 0, 0, 0.0);
+  o->n_outer = n;
+  o->outer_max = outer_max;
+  return 0;
+}
+
 /* Neighbour prior (Methods, Experiment 3): the ranges T1p +- 3000 ms,
  * T2p +- 800 ms and dfp +- 150 Hz around a neighbour's result, intersected
  * with the search ranges. Here the half widths are given physically (B1 is

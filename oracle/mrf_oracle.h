@@ -131,6 +131,11 @@ int orc_objectives_at(const orc_seq* seq, const orc_grid* grid, int32_t n_tr,
 /* ---- ZOOM ---- */
 int orc_schedule_paper(const orc_grid* grid, const orc_seq* seq,
                        orc_schedule* out);
+/* the paper's stages from a k1 x k2 lattice of starts over the T1/T2 index
+ * ranges (ends included), then outer rounds [df window, fine df scan, 2-D
+ * zooms at 100, 50, 20, 10 ms and unit steps (+ unit B1)] */
+int orc_schedule_multistart(const orc_grid* grid, const orc_seq* seq, int32_t k1, int32_t k2,
+                            int32_t outer_max, orc_schedule* out);
 /* every stage at unit index steps (the finest resolution) gets `objective` */
 int orc_schedule_finest_objective(orc_schedule* sched, int32_t objective);
 /* neighbour-prior half widths (Experiment 3) in index steps from physical

@@ -81,6 +81,8 @@ _SIGS = [
       C.POINTER(GridDesc), ResultView, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
     ("mrf_zoom_schedule_finest_objective", C.c_int, [C.c_void_p, C.c_int32]),
+    ("mrf_zoom_schedule_multistart", C.c_int,
+     [C.POINTER(GridDesc), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     ("mrf_static_scratch_bytes", C.c_size_t, []),
     ("mrf_match_bruteforce_noalloc", C.c_int,
      [C.c_void_p, C.POINTER(DictView), C.c_void_p, C.c_int32, C.c_int64, C.c_int32, ResultView,

@@ -382,6 +382,17 @@ def schedule_paper(ctx: Context, seq: Sequence, grid) -> dict:
     return schedule_to_dict(s)
 
 
+def schedule_multistart(ctx: Context, seq: Sequence, grid, n_t1: int = 4, n_t2: int = 4,
+                        outer_max: int = 8) -> dict:
+    """The paper's stages from an n_t1 x n_t2 lattice of starts with an outer
+    refinement round (see mrf_zoom_schedule_multistart)."""
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    s = L.ZoomSchedule()
+    L.check(ctx._lib.mrf_zoom_schedule_multistart(g.ptr, seq.handle, int(n_t1), int(n_t2),
+                                                  int(outer_max), C.byref(s)))
+    return schedule_to_dict(s)
+
+
 def schedule_finest_objective(sched: dict, objective: int = 1) -> dict:
     """A copy of the schedule with every finest-resolution (unit-step) stage
     scored by `objective` (libmrf mrf_zoom_schedule_finest_objective; 1: the

@@ -1267,6 +1267,46 @@ extern "C" int mrf_zoom_schedule_prior(const mrf_grid* g, const double* half,
   return MRF_OK;
 }
 
+extern "C" int mrf_zoom_schedule_multistart(const mrf_grid* g, const mrf_sequence* seq,
+                                            int32_t n_t1, int32_t n_t2, int32_t outer_max,
+                                            mrf_zoom_schedule* o) {
+  int rc = mrf_zoom_schedule_paper(g, seq, o);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_t1 >= 1 && n_t2 >= 1 && n_t1 * n_t2 <= MRF_ZOOM_MAX_STARTS,
+                "need 1 <= n_t1 * n_t2 <= %d starts", MRF_ZOOM_MAX_STARTS);
+  MRF_CHECK_ARG(outer_max >= 0 && outer_max <= 64, "outer_max must be in [0, 64]");
+  // starts: an n_t1 x n_t2 lattice of grid indices spanning each axis from
+  // its first to its last value (a single start sits at the middle)
+  auto lattice = [](int32_t k, int32_t n, int32_t q) {
+    if (k == 1) return (n - 1) / 2;
+    return h_round_half_away((double)q * (double)(n - 1) / (double)(k - 1));
+  };
+  const int32_t b1 = o->starts[0][3];
+  o->n_starts = n_t1 * n_t2;
+  for (int32_t a = 0; a < n_t1; ++a)
+    for (int32_t b = 0; b < n_t2; ++b) {
+      int32_t* st = o->starts[a * n_t2 + b];
+      st[0] = lattice(n_t1, g->t1_ms.n, a);
+      st[1] = lattice(n_t2, g->t2_ms.n, b);
+      st[2] = 0;
+      st[3] = b1;
+    }
+  // outer rounds: the df window and fine df scans of step 1 and step 3,
+  // then 2-D zooms from 100 ms down to the unit step (and the unit B1 zoom)
+  const mrf_axis &T1 = g->t1_ms, &T2 = g->t2_ms;
+  int k = 0;
+  o->outer[k++] = o->stages[1];
+  o->outer[k++] = o->stages[5];
+  const double rs[4] = {100.0, 50.0, 20.0, 10.0};
+  for (double r : rs)
+    o->outer[k++] = stage(MRF_ZOOM2, 0, 1, h_idx_step(r, T1), h_idx_step(r, T2), 0, 0.0);
+  o->outer[k++] = stage(MRF_ZOOM2, 0, 1, 1, 1, 0, 0.0);
+  if (g->b1.n > 1) o->outer[k++] = stage(MRF_ZOOM1, 3, 0, 1, 0, 0, 0.0);
+  o->n_outer = k;
+  o->outer_max = outer_max;
+  return MRF_OK;
+}
+
 extern "C" int mrf_zoom_schedule_finest_objective(mrf_zoom_schedule* o, int32_t objective) {
   MRF_CHECK_ARG(o, "NULL argument");
   MRF_CHECK_ARG(objective == MRF_OBJ_CC || objective == MRF_OBJ_DIST,

@@ -76,6 +76,11 @@ def test_schedule_builders_agree(ctx, orc, name):
     assert a["stages"] == b["stages"]
     assert a["outer"] == b["outer"] and a["outer_max"] == b["outer_max"]
     assert a["starts"] == b["starts"]
+    for k1, k2, om in ((4, 4, 8), (1, 3, 2), (2, 1, 0)):
+        a = api.schedule_multistart(ctx, sq, w.grid, k1, k2, om)
+        b = orc.schedule_multistart(w.seq, w.grid, k1, k2, om)
+        assert a == b, (k1, k2)
+        assert len(a["starts"]) == k1 * k2
 
 
 @pytest.mark.parametrize("variant", ["paper", "pruned", "multistart_outer"])

@@ -499,3 +499,24 @@ def test_decision_margin_bounds_what_a_perturbation_can_change(orc):
         r2 = orc.zoom_generic(sched, g.shape, lambda *i: f(*i, delta=1e-2))
         changed_big += r2["moves"] != r0["moves"]
     assert changed_big > 0
+
+
+def test_multistart_schedule_by_hand(orc):
+    """The multi-start lattice on a 7 x 5 grid: 3 x 2 starts at T1 indices
+    0, 3, 6 and T2 indices 0, 4 (ends included); one start per axis sits at
+    the middle; the outer round is the df window, the fine df scan and 2-D
+    zooms down to the unit step; the stage list is the paper's."""
+    seq = I.make_sequence(20, 2)
+    grid = I.make_grid(np.linspace(300, 2100, 7), np.linspace(40, 200, 5), np.arange(-8.0, 9.0, 2.0))
+    s = orc.schedule_multistart(seq, grid, 3, 2, 5)
+    assert [st[:2] for st in s["starts"]] == [[0, 0], [0, 4], [3, 0], [3, 4], [6, 0], [6, 4]]
+    assert all(st[2] == 0 and st[3] == 0 for st in s["starts"])
+    paper = orc.schedule_paper(seq, grid)
+    assert s["stages"] == paper["stages"] and s["outer_max"] == 5
+    kinds = [(o["kind"], o["axis0"], o["step0"], o["step1"]) for o in s["outer"]]
+    assert kinds[0] == (1, 2, paper["stages"][1]["step0"], 0)
+    assert kinds[1] == (1, 2, 1, 0) and kinds[-1] == (4, 0, 1, 1)
+    # T1 step 300 ms: 100 and 50 ms round to index steps 0.33 -> 1; T2 step 40 ms
+    assert [k[2:] for k in kinds[2:6]] == [(1, 3), (1, 1), (1, 1), (1, 1)]
+    one = orc.schedule_multistart(seq, grid, 1, 1, 0)
+    assert [st[:2] for st in one["starts"]] == [[3, 2]]
