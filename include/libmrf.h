@@ -409,6 +409,21 @@ int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* g
                     int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                     mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
 
+/* As mrf_zoom_search for a batch whose voxels use different readout counts
+ * of the same sequence (prefixes, e.g. slices acquired with N = 500 and
+ * N = 1000 searched in one launch): voxel v uses its first vox_n_tr[v]
+ * readouts (device int32 [n_vox], each in [1, n_tr_max]); the step tables
+ * of the first n_tr_max readouts serve every prefix, so each voxel's result
+ * equals a search of that voxel alone with n_tr = vox_n_tr[v], bit for bit.
+ * Workspace as mrf_zoom_workspace with n_tr_max. Counts outside
+ * [1, n_tr_max] are clamped to it on the device. Errors: as
+ * mrf_zoom_search, plus NULL vox_n_tr with voxels and a smoothing sequence
+ * -> MRF_ERR_INVALID. */
+int mrf_zoom_search_ragged(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid* grid,
+                           const mrf_zoom_schedule* sched, const void* vox, int32_t n_vox,
+                           int64_t ld_vox, int32_t n_tr_max, const int32_t* vox_n_tr,
+                           mrf_result_view out, void* workspace, size_t ws_bytes, void* stream);
+
 /* MRF-ZOOM over a resident dictionary (Results: the MZfulldict variant, the
  * fastest of the paper's timings): the same search as mrf_zoom_search, but
  * each visited entry is read from `dict` instead of simulated. dict: an
@@ -515,7 +530,11 @@ typedef struct {
   int32_t mode;        /* mrf_serve_mode */
   int32_t slot;
   int32_t n_tr;        /* readouts used; brute force: one of the slot's lengths;
-                          ZOOM: any value up to the longest */
+                          ZOOM: any value up to the longest. A batch holds
+                          requests of one slot and mode, of any readout counts:
+                          ZOOM voxels of different counts share one launch
+                          (mrf_zoom_search_ragged); brute force runs one GEMM
+                          per count within the batch (the GEMM's K is shared) */
   int32_t n_vox;       /* >= 0; 0 completes at submission */
   const void* vox;     /* complex64 [n_vox][ld_vox] device */
   int64_t ld_vox;      /* >= n_tr */
@@ -526,6 +545,10 @@ typedef struct {
   size_t budget_bytes, resident_bytes, reserved_bytes, peak_reserved_bytes, arena_peak_bytes;
   int64_t submitted, rejected, done, failed, cancelled, batches, max_batch_requests;
   int32_t peak_inflight;
+  /* per mode (0 brute force, 1 ZOOM): batches launched, requests they held,
+   * and batches holding more than one readout count */
+  int64_t admitted;
+  int64_t mode_batches[2], mode_requests[2], mixed_length_batches[2];
 } mrf_server_stats;
 
 int mrf_server_create(mrf_context* ctx, const mrf_server_config* cfg, mrf_server** out);

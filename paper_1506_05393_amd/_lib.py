@@ -155,6 +155,10 @@ _SIGS += [
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("mrf_zoom_search_ragged", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
+      C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
     ("mrf_zoom_search_dict", C.c_int,
      [C.c_void_p, C.POINTER(DictView), C.POINTER(GridDesc), C.POINTER(ZoomSchedule), C.c_void_p,
       C.c_int32, C.c_int64, C.c_int32, C.c_void_p, ResultView, C.c_void_p, C.c_size_t,
@@ -189,7 +193,9 @@ class ServerStats(C.Structure):
                 ("arena_peak_bytes", C.c_size_t), ("submitted", C.c_int64),
                 ("rejected", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
                 ("cancelled", C.c_int64), ("batches", C.c_int64),
-                ("max_batch_requests", C.c_int64), ("peak_inflight", C.c_int32)]
+                ("max_batch_requests", C.c_int64), ("peak_inflight", C.c_int32),
+                ("admitted", C.c_int64), ("mode_batches", C.c_int64 * 2),
+                ("mode_requests", C.c_int64 * 2), ("mixed_length_batches", C.c_int64 * 2)]
 
 
 SERVE_BRUTE, SERVE_ZOOM = 0, 1

@@ -465,6 +465,31 @@ def zoom_search(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, sched: Opt
     return r
 
 
+def zoom_search_ragged(ctx: Context, seq: Sequence, grid, vox: torch.Tensor,
+                       vox_n_tr: torch.Tensor, sched: Optional[dict] = None,
+                       workspace: Optional[Workspace] = None, out: Optional[dict] = None,
+                       stream=None) -> dict:
+    """MRF-ZOOM over voxels with their own readout counts (int32 cuda [n_vox],
+    each <= vox.shape[1] and the sequence length) in one launch."""
+    if vox.dtype != torch.complex64 or not vox.is_cuda or vox.stride(1) != 1:
+        raise ValueError("vox must be a complex64 CUDA tensor with contiguous rows")
+    vn = vox_n_tr.to(device=ctx.device, dtype=torch.int32).contiguous()
+    n_tr = int(vn.max().item()) if vn.numel() else 1
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    s = schedule_from_dict(schedule_paper(ctx, seq, g) if sched is None else sched)
+    n_vox = vox.shape[0]
+    nb = C.c_size_t()
+    L.check(ctx._lib.mrf_zoom_workspace(ctx.handle, g.ptr, n_vox, n_tr, C.byref(nb)))
+    ws = workspace if workspace is not None else Workspace(ctx.device)
+    buf = ws.get(int(nb.value))
+    r = out if out is not None else _result_tensors(n_vox, ctx.device, with_nsim=True)
+    r["_n_tr"] = vn
+    L.check(ctx._lib.mrf_zoom_search_ragged(
+        ctx.handle, seq.handle, g.ptr, C.byref(s), vox.data_ptr(), n_vox, vox.stride(0), n_tr,
+        vn.data_ptr(), _result_view(r), buf.data_ptr(), buf.numel(), _stream_ptr(stream)))
+    return r
+
+
 def zoom_search_dict(ctx: Context, d: Dictionary, grid, vox: torch.Tensor, sched: dict,
                      n_tr: Optional[int] = None, init: Optional[torch.Tensor] = None,
                      workspace: Optional[Workspace] = None, out: Optional[dict] = None,
@@ -572,7 +597,8 @@ class Server:
     def stats(self) -> dict:
         s = L.ServerStats()
         L.check(self._lib.mrf_server_stats_read(self.handle, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in L.ServerStats._fields_}
+        val = lambda x: list(x) if isinstance(x, C.Array) else x
+        return {k: val(getattr(s, k)) for k, _ in L.ServerStats._fields_}
 
     def wait(self, tickets, timeout_s: float = 60.0, sleep_s: float = 0.0005):
         import time

@@ -84,6 +84,13 @@ __global__ __launch_bounds__(256) void k_prefix_norm_bf16(const uint4* __restric
   norm[e] = sqrt(acc);
 }
 
+// Per-voxel readout counts of a ZOOM batch: n values from one request.
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t* __restrict__ dst, int64_t n,
+                                                  int32_t value) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i < n) dst[i] = value;
+}
+
 // First-fit allocator over [0, cap) with coalescing; offsets only (the
 // device base is added by the caller, or absent on the fake device).
 class Arena {
@@ -160,7 +167,7 @@ struct Req {
 // Byte layout of one batch's block.
 struct Layout {
   int64_t ld_stage = 0;
-  size_t stage = 0, idx = 0, cc = 0, margin = 0, pd_re = 0, pd_im = 0, n_sim = 0, ws = 0;
+  size_t stage = 0, idx = 0, cc = 0, margin = 0, pd_re = 0, pd_im = 0, n_sim = 0, vn = 0, ws = 0;
   size_t ws_bytes = 0, total = 0;
 };
 
@@ -235,7 +242,7 @@ int batch_layout(mrf_server* srv, const Slot& s, int32_t mode, int32_t n_tr, int
   o += align_up((size_t)n_vox * (size_t)L->ld_stage * 8);
   L->idx = o;
   o += align_up((size_t)n_vox * 8);
-  size_t* f4[] = {&L->cc, &L->margin, &L->pd_re, &L->pd_im, &L->n_sim};
+  size_t* f4[] = {&L->cc, &L->margin, &L->pd_re, &L->pd_im, &L->n_sim, &L->vn};
   for (size_t* p : f4) {
     *p = o;
     o += align_up((size_t)n_vox * 4);
@@ -280,14 +287,25 @@ void launch_batch(mrf_server* srv, Batch* b, int si) {
     b->failed = true;
     b->err = std::string(what) + ": " + msg;
   };
+  // gather: each request's voxels, its own readout count, rows of the batch's
+  // longest count; ZOOM batches also get every voxel's readout count
   int64_t v0 = 0;
   for (Req* r : b->reqs) {
     const hipError_t e = hipMemcpy2DAsync(stage + (size_t)v0 * L.ld_stage * 8, (size_t)L.ld_stage * 8,
-                                          r->r.vox, (size_t)r->r.ld_vox * 8, (size_t)b->n_tr * 8,
+                                          r->r.vox, (size_t)r->r.ld_vox * 8, (size_t)r->r.n_tr * 8,
                                           (size_t)r->r.n_vox, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) {
       fail("gathering voxels", hipGetErrorString(e));
       break;
+    }
+    if (b->mode == MRF_SERVE_ZOOM) {
+      hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((r->r.n_vox + 255) / 256)), dim3(256), 0, st,
+                         (int32_t*)(base + L.vn) + v0, (int64_t)r->r.n_vox, r->r.n_tr);
+      const hipError_t e2 = hipGetLastError();
+      if (e2 != hipSuccess) {
+        fail("gathering voxels", hipGetErrorString(e2));
+        break;
+      }
     }
     v0 += r->r.n_vox;
   }
@@ -299,15 +317,32 @@ void launch_batch(mrf_server* srv, Batch* b, int si) {
   o.pd_im = (float*)(base + L.pd_im);
   o.n_sim = b->mode == MRF_SERVE_ZOOM ? (int32_t*)(base + L.n_sim) : nullptr;
   if (!b->failed) {
-    int rc;
+    int rc = MRF_OK;
     if (b->mode == MRF_SERVE_BRUTE) {
-      const mrf_dict_view v = slot_view(s, b->n_tr);
-      rc = mrf_match_bruteforce(srv->ctx, &v, stage, (int32_t)b->n_vox, L.ld_stage,
-                                s.dtype == MRF_BF16 ? kTopKBF16 : kTopKF32, s.seq, &s.grid, o,
-                                nullptr, nullptr, base + L.ws, L.ws_bytes, st);
+      // one GEMM per readout count (the requests are ordered by count), on
+      // consecutive voxel ranges of the stage, sharing the workspace in turn
+      int64_t c0 = 0;
+      size_t i = 0;
+      while (rc == MRF_OK && i < b->reqs.size()) {
+        const int32_t n_tr = b->reqs[i]->r.n_tr;
+        int64_t nv = 0;
+        for (; i < b->reqs.size() && b->reqs[i]->r.n_tr == n_tr; ++i) nv += b->reqs[i]->r.n_vox;
+        const mrf_dict_view v = slot_view(s, n_tr);
+        mrf_result_view oc = o;
+        oc.idx += c0;
+        oc.cc += c0;
+        oc.margin += c0;
+        oc.pd_re += c0;
+        oc.pd_im += c0;
+        rc = mrf_match_bruteforce(srv->ctx, &v, stage + (size_t)c0 * L.ld_stage * 8, (int32_t)nv,
+                                  L.ld_stage, s.dtype == MRF_BF16 ? kTopKBF16 : kTopKF32, s.seq,
+                                  &s.grid, oc, nullptr, nullptr, base + L.ws, L.ws_bytes, st);
+        c0 += nv;
+      }
     } else {
-      rc = mrf_zoom_search(srv->ctx, s.seq, &s.grid, &s.sched, stage, (int32_t)b->n_vox, L.ld_stage,
-                           b->n_tr, nullptr, o, base + L.ws, L.ws_bytes, st);
+      rc = mrf_zoom_search_ragged(srv->ctx, s.seq, &s.grid, &s.sched, stage, (int32_t)b->n_vox,
+                                  L.ld_stage, b->n_tr, (const int32_t*)(base + L.vn), o,
+                                  base + L.ws, L.ws_bytes, st);
     }
     if (rc) fail("search", mrf_last_error());
   }
@@ -384,6 +419,7 @@ void admit(mrf_server* srv) {
     if (srv->inflight >= srv->cfg.max_inflight || srv->reserved + r->footprint > avail) break;
     srv->pending.pop_front();
     r->admitted = true;
+    srv->st.admitted++;
     srv->reserved += r->footprint;
     srv->inflight++;
     srv->st.peak_reserved_bytes = std::max(srv->st.peak_reserved_bytes, srv->reserved);
@@ -393,7 +429,8 @@ void admit(mrf_server* srv) {
 }
 
 // Form and launch batches on idle streams: the oldest admitted request's
-// (slot, mode, n_tr) with every later admitted request of the same key.
+// (slot, mode) with every later admitted request of the same key, whatever
+// its readout count; the batch's buffers are laid out for its longest count.
 void launch_ready(mrf_server* srv) {
   const int64_t max_vox = srv->cfg.max_batch_vox > 0 ? srv->cfg.max_batch_vox : kDefaultMaxBatchVox;
   for (size_t si = 0; si < srv->running.size(); ++si) {
@@ -404,23 +441,29 @@ void launch_ready(mrf_server* srv) {
     auto b = std::make_unique<Batch>();
     b->slot = head->r.slot;
     b->mode = head->r.mode;
-    b->n_tr = head->r.n_tr;
+    b->n_tr = 0;
     const Slot& s = *srv->slots[b->slot];
     size_t reserved_sum = 0;
     Layout L;
     for (Req* r : srv->admitted) {
       if (r->state == MRF_REQ_CANCELLED) continue;
-      if (r->r.slot != b->slot || r->r.mode != b->mode || r->r.n_tr != b->n_tr) continue;
+      if (r->r.slot != b->slot || r->r.mode != b->mode) continue;
       if (!b->reqs.empty() && b->n_vox + r->r.n_vox > max_vox) break;
+      const int32_t n_tr = std::max(b->n_tr, r->r.n_tr);
       Layout L2;
-      if (batch_layout(srv, s, b->mode, b->n_tr, b->n_vox + r->r.n_vox, &L2)) break;
+      if (batch_layout(srv, s, b->mode, n_tr, b->n_vox + r->r.n_vox, &L2)) break;
       if (!b->reqs.empty() && L2.total > reserved_sum + r->footprint) break;
       b->reqs.push_back(r);
       b->n_vox += r->r.n_vox;
+      b->n_tr = n_tr;
       reserved_sum += r->footprint;
       L = L2;
     }
     if (b->reqs.empty()) continue;
+    // brute force runs one GEMM per readout count: order the requests by count
+    if (b->mode == MRF_SERVE_BRUTE)
+      std::stable_sort(b->reqs.begin(), b->reqs.end(),
+                       [](const Req* x, const Req* y) { return x->r.n_tr < y->r.n_tr; });
     if (!srv->arena.alloc(L.total, &b->off)) return;  // fragmented: wait for a completion
     b->L = L;
     for (Req* r : b->reqs) {
@@ -430,6 +473,14 @@ void launch_ready(mrf_server* srv) {
     }
     srv->st.batches++;
     srv->st.max_batch_requests = std::max<int64_t>(srv->st.max_batch_requests, (int64_t)b->reqs.size());
+    const int mi = b->mode == MRF_SERVE_ZOOM ? 1 : 0;
+    srv->st.mode_batches[mi]++;
+    srv->st.mode_requests[mi] += (int64_t)b->reqs.size();
+    for (Req* r : b->reqs)
+      if (r->r.n_tr != b->reqs.front()->r.n_tr) {
+        srv->st.mixed_length_batches[mi]++;
+        break;
+      }
     launch_batch(srv, b.get(), (int)si);
     srv->running[si] = std::move(b);
   }
@@ -633,8 +684,11 @@ extern "C" int mrf_serve_submit(mrf_server* srv, const mrf_request* req, uint64_
   auto r = std::make_unique<Req>();
   r->r = *req;
   if (req->n_vox > 0) {
+    // reserved at the slot's longest readout count: a batch's buffers are laid
+    // out for its longest count, so any mix of counts fits the reservations
+    const Slot& s = *srv->slots[req->slot];
     Layout L;
-    rc = batch_layout(srv, *srv->slots[req->slot], req->mode, req->n_tr, req->n_vox, &L);
+    rc = batch_layout(srv, s, req->mode, s.n_tr_max, req->n_vox, &L);
     if (rc) return rc;
     r->footprint = L.total;
   }

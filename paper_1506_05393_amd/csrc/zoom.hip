@@ -29,6 +29,8 @@ struct ZoomArgs {
   const float4* dfT;
   const float* rf;
   int32_t n_tr, inversion;
+  int32_t tab_n;            // readouts per table row (>= every voxel's readout count)
+  const int32_t* vox_n_tr;  // per-voxel readout counts [n_vox], or NULL (all n_tr)
   int32_t x_axis;  // every RF phase a multiple of 180 deg: pulses rotate about x
   int32_t dims[4];
   const float2* vox;
@@ -125,6 +127,7 @@ struct EngineParams {
   const float4* dfT;
   const float* rf;
   int32_t n_tr, inversion, memo_cap, x_axis;
+  int32_t tab_n;  // readouts per table row (n_tr is this voxel's count, <= tab_n)
   int32_t dims[4];
 };
 
@@ -209,11 +212,11 @@ struct Engine {
     typedef const __attribute__((address_space(1))) v4 gf4;
     typedef const __attribute__((address_space(1))) float gf1;
     constexpr int NR = X_AXIS ? 4 : 9;  // pulse values read per readout
-    const int32_t n = pa.n_tr;
-    gf2* p1 = (gf2*)(pa.t1T + (int64_t)i[0] * n);
-    gf2* p2 = (gf2*)(pa.t2T + (int64_t)i[1] * n);
-    gf4* pd = (gf4*)(pa.dfT + (int64_t)i[2] * n);
-    gf1* Rp = (gf1*)(pa.rf + (LANE_R ? (int64_t)i[3] * n * 9 : 0));
+    const int32_t n = pa.n_tr, tn = pa.tab_n;
+    gf2* p1 = (gf2*)(pa.t1T + (int64_t)i[0] * tn);
+    gf2* p2 = (gf2*)(pa.t2T + (int64_t)i[1] * tn);
+    gf4* pd = (gf4*)(pa.dfT + (int64_t)i[2] * tn);
+    gf1* Rp = (gf1*)(pa.rf + (LANE_R ? (int64_t)i[3] * tn * 9 : 0));
     gf2* vl = (gf2*)vx;
     // the pulse values of readout j: R[0..8], or R11, R12, R21, R22
     auto ld_pulse = [&](int32_t j, float (&r)[NR]) {
@@ -899,7 +902,6 @@ template <int G, bool SM, bool GA, bool DI>
 __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
   constexpr int NG = 64 / G;
   extern __shared__ __align__(16) unsigned char sm[];
-  const int32_t n = a.n_tr;
   const int lane = threadIdx.x;
   const int grp = lane / G, glane = lane % G, gbase = grp * G;
   unsigned char* gsm = sm + (size_t)grp * zoom_group_lds();
@@ -965,6 +967,10 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     // turn, the eight partial sums are added pairwise, and lane 0's total is
     // broadcast to the group.
     const float2* src = a.vox + (int64_t)v * a.ld_vox;
+    // this voxel's readouts: a batch may mix readout counts (prefixes of the
+    // same sequence, whose tables are prefixes of the longest one's)
+    // (clamped to the tables' [1, n_tr], so no table row is read past its end)
+    const int32_t n = a.vox_n_tr ? min(max(a.vox_n_tr[v], 1), a.n_tr) : a.n_tr;
     double s2 = 0.0;
     if (glane < 8) {
       for (int32_t j = glane; j < n; j += 8) {
@@ -985,7 +991,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.pa.t2T = a.t2T;
     e.pa.dfT = a.dfT;
     e.pa.rf = a.rf;
-    e.pa.n_tr = a.n_tr;
+    e.pa.n_tr = n;
+    e.pa.tab_n = a.tab_n;
     e.pa.inversion = a.inversion;
     e.pa.x_axis = a.x_axis;
     if constexpr (SM) {
@@ -1403,7 +1410,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
                        int64_t ld_vox, int32_t n_tr, const int32_t* init_idx,
                        const int64_t* init_flat, mrf_result_view out, void* workspace,
                        size_t ws_bytes, void* stream, const int32_t* lattice = nullptr,
-                       const mrf_dict_view* dict = nullptr) {
+                       const mrf_dict_view* dict = nullptr, const int32_t* vox_n_tr = nullptr) {
   MRF_CHECK_ARG(ctx && (seq || dict), "context and sequence (or dictionary) must not be NULL");
   int rc = check_grid(grid);
   if (rc) return rc;
@@ -1432,6 +1439,8 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   bool dist = false;  // any stage scored by the distance objective
   for (int i = 0; i < sched->n_stages; ++i) dist |= sched->stages[i].objective == MRF_OBJ_DIST;
   for (int i = 0; i < sched->n_outer; ++i) dist |= sched->outer[i].objective == MRF_OBJ_DIST;
+  MRF_CHECK_ARG(!vox_n_tr || dict || !seq->smooth,
+                "per-voxel readout counts need a sequence without smoothing");
   if (dist && (dict || seq->smooth)) {
     set_error("distance-objective stages need the simulating search without smoothing");
     return MRF_ERR_UNSUPPORTED;
@@ -1456,6 +1465,8 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.dfT = t->dfT;
   a.rf = t->rf;
   a.n_tr = n_tr;
+  a.tab_n = n_tr;  // the tables (or rows) hold n_tr readouts; voxels may use prefixes
+  a.vox_n_tr = vox_n_tr;
   a.inversion = t->inversion;
   a.x_axis = t->x_axis_pulses;
   a.sm = smooth_weights(t->smooth ? t->smooth : 3, n_tr);
@@ -1528,6 +1539,17 @@ extern "C" int mrf_zoom_search(mrf_context* ctx, const mrf_sequence* seq, const 
                                void* stream) {
   return zoom_search(ctx, seq, grid, sched, vox, n_vox, ld_vox, n_tr, init_idx, nullptr, out,
                      workspace, ws_bytes, stream);
+}
+
+extern "C" int mrf_zoom_search_ragged(mrf_context* ctx, const mrf_sequence* seq,
+                                      const mrf_grid* grid, const mrf_zoom_schedule* sched,
+                                      const void* vox, int32_t n_vox, int64_t ld_vox,
+                                      int32_t n_tr_max, const int32_t* vox_n_tr,
+                                      mrf_result_view out, void* workspace, size_t ws_bytes,
+                                      void* stream) {
+  MRF_CHECK_ARG(vox_n_tr != nullptr || n_vox == 0, "vox_n_tr must not be NULL");
+  return zoom_search(ctx, seq, grid, sched, vox, n_vox, ld_vox, n_tr_max, nullptr, nullptr, out,
+                     workspace, ws_bytes, stream, nullptr, nullptr, vox_n_tr);
 }
 
 extern "C" int mrf_zoom_search_dict(mrf_context* ctx, const mrf_dict_view* dict,

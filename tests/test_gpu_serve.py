@@ -131,3 +131,32 @@ def test_server_keeps_serving_after_an_invalid_request(env):
         assert srv.poll(t)[0] == "done"
     finally:
         srv.close()
+
+
+def test_mixed_readout_counts_share_a_batch(env):
+    """With one stream held by a first request, later requests of one slot and
+    mode with readout counts 100 and 200 form one batch (ZOOM: one launch
+    with per-voxel counts; brute force: one GEMM per count), and every result
+    equals the same request served alone, bit for bit."""
+    api, ctx, sqs, grid = env
+    srv = api.Server(ctx, 4 * GB, max_inflight=64, n_streams=1)
+    try:
+        slot = srv.register(sqs[0], grid, "bf16", lengths=(100, 200))
+        reqs = [(m, slot, (100, 200)[i % 2], _voxels(api, ctx, sqs[0], grid, 97 + 31 * i, 300 + i))
+                for m in ("zoom", "brute") for i in range(4)]
+        alone = []
+        for q in reqs:
+            alone += _run(srv, [q])[1]
+        st0 = srv.stats()
+        busy = ("brute", slot, 200, _voxels(api, ctx, sqs[0], grid, 8192, 299))
+        tickets, mix = _run(srv, [busy] + reqs)
+        st = srv.stats()
+    finally:
+        srv.close()
+    mixed = [st["mixed_length_batches"][m] - st0["mixed_length_batches"][m] for m in (0, 1)]
+    print(f"mixed-count batches: brute {mixed[0]}, zoom {mixed[1]}; "
+          f"{st['batches'] - st0['batches']} batches for {len(reqs) + 1} requests")
+    assert mixed[0] >= 1 and mixed[1] >= 1
+    for i, (a, b) in enumerate(zip(alone, mix[1:])):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (i, k)

@@ -294,3 +294,31 @@ def test_results_do_not_depend_on_voxel_group_size(ctx):
         for key in ("idx", "cc", "margin", "pd_re", "pd_im", "n_sim"):
             assert torch.equal(part[key], full[key][:m]), (m, key)
     assert bool((full["n_sim"] > 0).all())
+
+
+def test_ragged_readout_counts_in_one_launch(ctx, orc):
+    """Voxels with readout counts 120, 200, 57 and 1 searched together
+    (mrf_zoom_search_ragged) give, voxel by voxel, the results of searching
+    each count's voxels alone, bit for bit; a sampled voxel of each count
+    meets the oracle bar at its count."""
+    from paper_1506_05393_amd import api
+    w = _cfg1()
+    V = oracle_fingerprints(orc, w.seq, w.phantom)
+    counts = np.array([120, 200, 57, 1])[np.arange(len(V)) % 4].astype(np.int32)
+    sq = api.Sequence(ctx, w.seq)
+    sched = orc.schedule_paper(w.seq, w.grid)
+    Vd = to_dev(V)
+    rag = api.zoom_search_ragged(ctx, sq, w.grid, Vd, torch.from_numpy(counts).cuda(), sched=sched)
+    torch.cuda.synchronize()
+    for n in (120, 200, 57, 1):
+        sel = np.flatnonzero(counts == n)
+        alone = api.zoom_search(ctx, sq, w.grid, to_dev(V[sel]), sched=sched, n_tr=n)
+        torch.cuda.synchronize()
+        idx = torch.from_numpy(sel).cuda()
+        for k in ("idx", "cc", "margin", "pd_re", "pd_im", "n_sim"):
+            assert torch.equal(rag[k][idx], alone[k]), (n, k)
+        if n >= 57:
+            ref = orc.zoom(w.seq, w.grid, sched, V[sel[:16], :n], threads=8)
+            got = rag["idx"][idx[:16]].cpu().numpy()
+            pinned = ref["min_margin"] > MARGIN
+            assert np.all(got[pinned] == ref["idx"][pinned])

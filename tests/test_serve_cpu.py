@@ -62,9 +62,13 @@ def test_budget_fifo_and_batching_under_poisson_load():
     assert st["peak_inflight"] <= 16
     assert st["reserved_bytes"] == 0
     assert st["done"] == 48 and st["failed"] == 0
-    # continuous batching: some batches held several requests
+    # continuous batching: some batches held several requests, and batches
+    # span readout counts (a batch is keyed by slot and mode only)
     assert st["batches"] < 48 and st["max_batch_requests"] > 1
-    # first-in first-out within a key: a later request never starts first
+    assert sum(st["mode_batches"]) == st["batches"]
+    assert sum(st["mode_requests"]) == 48 and st["admitted"] == 48
+    # first-in first-out within a batch key: a later request never starts first
+    keys = [k[:2] for k in keys]
     for k in set(keys):
         starts = [polls[i][2] for i in range(48) if keys[i] == k]
         assert starts == sorted(starts)
@@ -194,3 +198,24 @@ def test_unknown_ticket_is_an_error():
             srv.cancel(t + 1000)
     finally:
         srv.close()
+
+
+def test_batches_span_readout_counts():
+    """Requests of one slot and mode queued behind a busy stream share a
+    batch whatever their readout counts (500 and 1000 here), for both modes;
+    the reservations (each at the slot's longest count) cover the batch."""
+    srv, slots = _server(budget_mb=400, n_streams=1, max_inflight=64, fake_ns_per_byte=0.5)
+    try:
+        first = srv.submit("brute", slots[0], 1000, n_vox=4096)  # keeps the stream busy
+        tickets = [first]
+        for mode in ("brute", "zoom"):
+            for i in range(6):
+                tickets.append(srv.submit(mode, slots[1], (500, 1000)[i % 2], n_vox=1024))
+        srv.wait(tickets, timeout_s=120)
+        st = srv.stats()
+        assert all(srv.poll(t)[0] == "done" for t in tickets)
+    finally:
+        srv.close()
+    assert st["mixed_length_batches"][0] >= 1 and st["mixed_length_batches"][1] >= 1
+    assert st["mode_requests"] == [7, 6] and st["batches"] <= 4
+    assert st["arena_peak_bytes"] <= st["peak_reserved_bytes"]
