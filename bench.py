@@ -45,7 +45,10 @@ def parse():
                    help="skip ZOOM over a resident dictionary")
     p.add_argument("--no-peaks", action="store_true",
                    help="skip the measured device peaks (MFMA-only loops, write and copy streams)")
-    p.add_argument("--serve-requests", type=int, default=60)
+    p.add_argument("--serve-seconds", type=float, default=60.0,
+                   help="length of the serving stream (arrival times)")
+    p.add_argument("--serve-requests", type=int, default=0,
+                   help="cap on the requests of the serving stream (0: none)")
     p.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     return p.parse_args()
 
@@ -161,20 +164,25 @@ def volume_bench(api, ctx, torch, n_slices: int = 8, side: int = 256):
     return res
 
 
-def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
-    """Request stream through the server: Poisson arrivals at `rate`/s, slices of
-    32^2, 64^2, 96^2 or 128^2 voxels, N in {500, 1000}, three sequences
-    (seeds 2-4) with resident BF16 dictionaries over a 1.6M-entry grid, half
-    brute force (BF16 + FP32 re-scoring), half MRF-ZOOM (simulated on the fly).
-    Latency = completion observed by the server - submission."""
+def serve_bench(api, ctx, torch, seconds: float, rate: float, seed: int = 4,
+                max_requests: int = 0):
+    """Request stream through the server: Poisson arrivals at `rate`/s for
+    `seconds`, slices of 32^2, 64^2, 96^2 or 128^2 voxels, N in {500, 1000},
+    three sequences (seeds 2-4) with resident BF16 dictionaries over a
+    1.6M-entry grid, half brute force (BF16 + FP32 re-scoring), half
+    MRF-ZOOM (simulated on the fly). Latency = completion observed by the
+    server - submission. Returns the summary and, per request type (mode,
+    N), a seeded 1% of the distinct voxels it served with their parameters,
+    noise draws and served results, for the oracle re-check."""
     from paper_1506_05393_amd import inputs as I
     from paper_1506_05393_amd import workloads as W
     grid = W.serving_grid()
-    seqs = [api.Sequence(ctx, I.make_sequence(1000, s)) for s in (2, 3, 4)]
+    seqs_h = [I.make_sequence(1000, s) for s in (2, 3, 4)]
+    seqs = [api.Sequence(ctx, q) for q in seqs_h]
     sizes = [32, 64, 96, 128]
     rng = np.random.default_rng(seed)
     # voxel pools: in-grid parameters, GPU-simulated signals, SNR 30 noise
-    pools = {}
+    pools, params, noises = {}, {}, {}
     for si, sq in enumerate(seqs):
         for n in sizes:
             nv = n * n
@@ -185,9 +193,11 @@ def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
             noise = torch.randn(sig.shape, dtype=torch.complex64, device="cuda", generator=g)
             sigma = sig.abs().pow(2).mean(dim=1, keepdim=True).sqrt() / 30
             pools[(si, n)] = (sig + sigma * noise).contiguous()
+            params[(si, n)] = p
+            noises[(si, n)] = noise
     resident = 3 * ((grid.size + 255) // 256 * 256 * 250 * 16 + 2 * grid.size * 8)
     budget = resident + 24 * (1 << 30)
-    srv = api.Server(ctx, budget, max_inflight=64, n_streams=2)
+    srv = api.Server(ctx, budget, max_inflight=64, n_streams=2, refine_bf16=True)
     try:
         slots = [srv.register(sq, grid, "bf16", lengths=(500, 1000)) for sq in seqs]
         warm = [srv.submit(m, s, n, pools[(s, 32)]) for m in ("brute", "zoom") for s in slots
@@ -196,30 +206,66 @@ def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
         st0 = srv.stats()
         trace = []
         t = 0.0
-        for _ in range(n_req):
+        while True:
             t += rng.exponential(1.0 / rate)
+            if t > seconds or (max_requests and len(trace) >= max_requests):
+                break
             trace.append((t, ("brute", "zoom")[rng.integers(2)], int(rng.integers(3)),
                           int(rng.choice([500, 1000])), int(rng.choice(sizes))))
-        tickets, meta = [], []
+        tickets, meta, rejected = [], [], 0
         t0 = time.perf_counter()
+        last_log = t0
         for at, mode, s, n_tr, n in trace:
             d = at - (time.perf_counter() - t0)
             if d > 0:
                 time.sleep(d)
-            tickets.append(srv.submit(mode, slots[s], n_tr, pools[(s, n)]))
-            meta.append((mode, n * n))
-        srv.wait(tickets, timeout_s=600)
+            try:
+                tickets.append(srv.submit(mode, slots[s], n_tr, pools[(s, n)]))
+                meta.append((mode, s, n_tr, n))
+            except Exception:
+                rejected += 1
+            if time.perf_counter() - last_log > 15:
+                last_log = time.perf_counter()
+                log(f"serving: {len(tickets)} requests submitted")
+        srv.wait(tickets, timeout_s=900)
         polls = [srv.poll(tk) for tk in tickets]
         st = srv.stats()
+        # per request type, the first served result of every pool it used
+        recheck = {}
+        rs = np.random.default_rng(seed + 1)
+        for i, (mode, s, n_tr, n) in enumerate(meta):
+            key = f"{mode}_N{n_tr}"
+            pool = recheck.setdefault(key, {"mode": mode, "n_tr": n_tr, "items": {}})["items"]
+            if (s, n) in pool or polls[i][0] != "done":
+                continue
+            nv = n * n
+            pick = np.sort(rs.choice(nv, max(1, nv // 100), replace=False))
+            r = srv.result(tickets[i])
+            pick_t = torch.from_numpy(pick).cuda()
+            pool[(s, n)] = {"seq": s, "voxels": pick, "params": params[(s, n)][pick],
+                            "noise": noises[(s, n)][pick_t, :n_tr].cpu().numpy(),
+                            "idx": r["idx"][pick_t].cpu().numpy(),
+                            "cc": r["cc"][pick_t].cpu().numpy()}
     finally:
         srv.close()
+    n_req = len(tickets)
     lat = np.array([p[3] - p[1] for p in polls])
     span_s = (max(p[3] for p in polls) - min(p[1] for p in polls)) * 1e-3
-    vox = sum(m[1] for m in meta)
+    vox = sum(m[3] * m[3] for m in meta)
     by_mode = {m: np.array([lat[i] for i in range(n_req) if meta[i][0] == m]) for m in ("brute", "zoom")}
-    return {
-        "workload": f"Poisson {rate:g} req/s, {n_req} requests, sizes 32^2..128^2, N in {{500,1000}}, "
-                    f"3 sequences, grid {grid.size} entries, BF16 resident, half brute / half ZOOM",
+    mb = [st["mode_batches"][k] - st0["mode_batches"][k] for k in (0, 1)]
+    mr = [st["mode_requests"][k] - st0["mode_requests"][k] for k in (0, 1)]
+    mx = [st["mixed_length_batches"][k] - st0["mixed_length_batches"][k] for k in (0, 1)]
+    summary = {
+        "workload": f"Poisson {rate:g} req/s for {seconds:g} s, sizes 32^2..128^2, N in "
+                    f"{{500,1000}}, 3 sequences, grid {grid.size} entries, BF16 resident, half "
+                    f"brute / half ZOOM",
+        "brute_force": "BF16 GEMM, top-8 FP32 re-scoring, unit-step FP32 refinement",
+        "offered_requests": len(trace),
+        "submitted": int(st["submitted"] - st0["submitted"]),
+        "admitted": int(st["admitted"] - st0["admitted"]),
+        "rejected": int(st["rejected"] - st0["rejected"]) + rejected,
+        "done": int(sum(p[0] == "done" for p in polls)),
         "failed": int(sum(p[0] != "done" for p in polls)),
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
@@ -228,12 +274,86 @@ def serve_bench(api, ctx, torch, n_req: int, rate: float, seed: int = 4):
         "voxels_per_s": vox / span_s,
         "requests_per_s": n_req / span_s,
         "offered_requests_per_s": rate,
+        "span_s": span_s,
         "batches": int(st["batches"] - st0["batches"]),
+        "batches_by_mode": {"brute": mb[0], "zoom": mb[1]},
+        "requests_per_batch_by_mode": {"brute": mr[0] / max(mb[0], 1), "zoom": mr[1] / max(mb[1], 1)},
+        "mixed_count_batches_by_mode": {"brute": mx[0], "zoom": mx[1]},
         "max_batch_requests": int(st["max_batch_requests"]),
         "resident_GB": st["resident_bytes"] / 1e9,
         "peak_reserved_GB": st["peak_reserved_bytes"] / 1e9,
         "budget_GB": st["budget_bytes"] / 1e9,
     }
+    return summary, {"grid": grid, "seqs": seqs_h, "types": recheck}
+
+
+def serve_recheck(sample) -> dict:
+    """The oracle re-check of the served results: for each request type, the
+    sampled voxels' fingerprints are synthesised by the oracle from the same
+    parameters and noise draws (SNR 30); the oracle's CC of the served entry
+    must equal the served CC within 1e-5; a brute-force result must be a
+    maximum of its 26 unit neighbours under the oracle within 1e-5, and on 8
+    voxels per type within 1e-5 of the oracle's own brute force over the
+    whole grid; a ZOOM result must equal the oracle's ZOOM (paper schedule)
+    on voxels whose oracle decision margins exceed 1e-5."""
+    import oracle
+    grid, seqs = sample["grid"], sample["seqs"]
+    th = host_threads()
+    out = {}
+    moves = [[(0, a), (1, b), (2, c)] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+             if (a, b, c) != (0, 0, 0)]
+    dims = np.array(grid.shape)
+    for key, t in sample["types"].items():
+        n_tr = t["n_tr"]
+        res = {"voxels": 0, "cc_at_index_max_abs_d": 0.0}
+        worst_local, eps_ok, eps_n, pin_n, pin_ok = -np.inf, 0, 0, 0, 0
+        for (s, n), it in t["items"].items():
+            # the pool's signals span the whole sequence (its noise level too);
+            # a request uses their first n_tr readouts
+            seq = seqs[s]
+            p = it["params"]
+            clean = np.stack([oracle.simulate(seq, *map(float, q)) for q in p])
+            sigma = np.sqrt(np.mean(np.abs(clean) ** 2, axis=1, keepdims=True)) / 30.0
+            V = (clean[:, :n_tr] + sigma * it["noise"]).astype(np.complex64)
+            idx, cc = it["idx"], it["cc"].astype(np.float64)
+            at = oracle.cc_at(seq, grid, V, idx[:, None], n_tr=n_tr, threads=th)[:, 0]
+            res["voxels"] += len(idx)
+            res["cc_at_index_max_abs_d"] = max(res["cc_at_index_max_abs_d"], float(np.abs(at - cc).max()))
+            if t["mode"] == "brute":
+                u = np.stack(grid.unravel(idx), 1)
+                cols = []
+                for mv in moves:
+                    q = u.copy()
+                    for ax, d in mv:
+                        q[:, ax] += d
+                    ok = np.all((q >= 0) & (q < dims), axis=1)
+                    cols.append(np.where(ok, grid.ravel(q[:, 0], q[:, 1], q[:, 2], q[:, 3]), -1))
+                nb = oracle.cc_at(seq, grid, V, np.stack(cols, 1), n_tr=n_tr, threads=th)
+                worst_local = max(worst_local, float((nb.max(axis=1) - at).max()))
+                if eps_n < 8:
+                    k = min(8 - eps_n, len(idx))
+                    bf = oracle.bruteforce(seq, grid, V[:k], n_tr=n_tr, threads=th)
+                    eps_ok += int(np.sum(at[:k] >= bf["cc"] - 1e-5))
+                    eps_n += k
+            else:
+                # the slot's schedule: the paper's for the whole sequence
+                z = oracle.zoom(seq, grid, oracle.schedule_paper(seq, grid), V, n_tr=n_tr,
+                                threads=th)
+                pinned = z["min_margin"] > 1e-5
+                pin_n += int(pinned.sum())
+                pin_ok += int(np.sum(idx[pinned] == z["idx"][pinned]))
+        if t["mode"] == "brute":
+            res["local_max_excess_max"] = worst_local
+            res["oracle_bruteforce_voxels"] = eps_n
+            res["within_1e-5_of_oracle_best"] = eps_ok / max(eps_n, 1)
+            res["pass"] = bool(res["cc_at_index_max_abs_d"] < 1e-5 and worst_local <= 1e-5
+                               and eps_ok == eps_n)
+        else:
+            res["pinned"] = pin_n
+            res["agreement_pinned"] = pin_ok / max(pin_n, 1)
+            res["pass"] = bool(res["cc_at_index_max_abs_d"] < 1e-5 and pin_ok == pin_n)
+        out[key] = res
+    return out
 
 
 def cpu_model() -> str:
@@ -920,11 +1040,14 @@ def main():
     if not args.no_volume:
         log("volume ...")
         res["volume"] = volume_bench(api, ctx, torch)
+    serve_sample = None
     if not args.no_serve:
         log("serving ...")
-        res["serving"] = serve_bench(api, ctx, torch, args.serve_requests, args.serve_rate)
-        log(f"serving done: p50 {res['serving']['latency_ms_p50']:.1f} ms, "
-            f"p99 {res['serving']['latency_ms_p99']:.1f} ms")
+        res["serving"], serve_sample = serve_bench(api, ctx, torch, args.serve_seconds,
+                                                   args.serve_rate,
+                                                   max_requests=args.serve_requests)
+        log(f"serving done: {res['serving']['done']} requests, p50 "
+            f"{res['serving']['latency_ms_p50']:.1f} ms, p99 {res['serving']['latency_ms_p99']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(w, args.cpu_seconds)
@@ -940,6 +1063,9 @@ def main():
                         "zoom_multistart_4x4": outzm["idx"].cpu().numpy(),
                         "fp32_refined": rf32})}
         res["cpu_baseline"] = cb
+        if serve_sample is not None:
+            log("oracle re-check of served results ...")
+            res["serving"]["oracle_recheck"] = serve_recheck(serve_sample)
         if "agreement_vs_oracle" in res:
             ag = res["agreement_vs_oracle"]
             small = ag["small_dgs"]

@@ -524,6 +524,14 @@ typedef struct {
   int32_t fake_device;
   double fake_ns_per_byte;
   uint64_t fake_fail_ticket;
+  /* 1: brute-force results of BF16 slots are refined after the FP32
+   * re-scoring by the unit-step local search (mrf_zoom_schedule_local, 8
+   * rounds) started at them, so that each is a maximum of its unit
+   * neighbours in FP32 (the best entry can fall outside the BF16 top 8 when
+   * its neighbours' BF16 scores are within the BF16 rounding of it); n_sim
+   * then counts the entries the refinement simulated. 0: re-scored results
+   * as mrf_match_bruteforce returns them. */
+  int32_t refine_bf16;
 } mrf_server_config;
 
 typedef struct {

@@ -151,6 +151,7 @@ struct Slot {
   void* im = nullptr;
   std::map<int32_t, double*> norms;  // readout count -> device norms
   mrf_zoom_schedule sched{};
+  mrf_zoom_schedule local{};  // unit-step refinement of BF16 brute-force results
   size_t resident = 0;
 };
 
@@ -168,6 +169,7 @@ struct Req {
 struct Layout {
   int64_t ld_stage = 0;
   size_t stage = 0, idx = 0, cc = 0, margin = 0, pd_re = 0, pd_im = 0, n_sim = 0, vn = 0, ws = 0;
+  size_t start = 0;  // refinement: the re-scored entries it starts from
   size_t ws_bytes = 0, total = 0;
 };
 
@@ -247,14 +249,22 @@ int batch_layout(mrf_server* srv, const Slot& s, int32_t mode, int32_t n_tr, int
     *p = o;
     o += align_up((size_t)n_vox * 4);
   }
+  L->start = o;
+  o += align_up((size_t)n_vox * 8);
   size_t ws = 0;
   if (srv->fake) {
     ws = 4096 + (size_t)n_vox * 64;
   } else if (mode == MRF_SERVE_BRUTE) {
     const mrf_dict_view v = slot_view(s, n_tr);
-    const int rc = mrf_match_workspace(srv->ctx, &v, (int32_t)n_vox,
-                                       s.dtype == MRF_BF16 ? kTopKBF16 : kTopKF32, &ws);
+    int rc = mrf_match_workspace(srv->ctx, &v, (int32_t)n_vox,
+                                 s.dtype == MRF_BF16 ? kTopKBF16 : kTopKF32, &ws);
     if (rc) return rc;
+    if (srv->cfg.refine_bf16 && s.dtype == MRF_BF16) {
+      size_t wz = 0;
+      rc = mrf_zoom_workspace(srv->ctx, &s.grid, (int32_t)n_vox, n_tr, &wz);
+      if (rc) return rc;
+      ws = std::max(ws, wz);
+    }
   } else {
     const int rc = mrf_zoom_workspace(srv->ctx, &s.grid, (int32_t)n_vox, n_tr, &ws);
     if (rc) return rc;
@@ -315,7 +325,8 @@ void launch_batch(mrf_server* srv, Batch* b, int si) {
   o.margin = (float*)(base + L.margin);
   o.pd_re = (float*)(base + L.pd_re);
   o.pd_im = (float*)(base + L.pd_im);
-  o.n_sim = b->mode == MRF_SERVE_ZOOM ? (int32_t*)(base + L.n_sim) : nullptr;
+  const bool refined = b->mode == MRF_SERVE_BRUTE && srv->cfg.refine_bf16 && s.dtype == MRF_BF16;
+  o.n_sim = b->mode == MRF_SERVE_ZOOM || refined ? (int32_t*)(base + L.n_sim) : nullptr;
   if (!b->failed) {
     int rc = MRF_OK;
     if (b->mode == MRF_SERVE_BRUTE) {
@@ -337,6 +348,20 @@ void launch_batch(mrf_server* srv, Batch* b, int si) {
         rc = mrf_match_bruteforce(srv->ctx, &v, stage + (size_t)c0 * L.ld_stage * 8, (int32_t)nv,
                                   L.ld_stage, s.dtype == MRF_BF16 ? kTopKBF16 : kTopKF32, s.seq,
                                   &s.grid, oc, nullptr, nullptr, base + L.ws, L.ws_bytes, st);
+        if (rc == MRF_OK && srv->cfg.refine_bf16 && s.dtype == MRF_BF16) {
+          // unit-step FP32 refinement from the re-scored entries
+          int64_t* start = (int64_t*)(base + L.start) + c0;
+          const hipError_t e = hipMemcpyAsync(start, oc.idx, (size_t)nv * 8,
+                                              hipMemcpyDeviceToDevice, st);
+          if (e != hipSuccess) {
+            fail("refinement", hipGetErrorString(e));
+            break;
+          }
+          oc.n_sim = (int32_t*)(base + L.n_sim) + c0;
+          rc = mrf_zoom_search_from(srv->ctx, s.seq, &s.grid, &s.local,
+                                    stage + (size_t)c0 * L.ld_stage * 8, (int32_t)nv, L.ld_stage,
+                                    n_tr, start, oc, base + L.ws, L.ws_bytes, st);
+        }
         c0 += nv;
       }
     } else {
@@ -358,8 +383,7 @@ void launch_batch(mrf_server* srv, Batch* b, int si) {
       } cp[] = {{d.idx, o.idx + v0, n * 8},     {d.cc, o.cc + v0, n * 4},
                 {d.margin, o.margin + v0, n * 4}, {d.pd_re, o.pd_re + v0, n * 4},
                 {d.pd_im, o.pd_im + v0, n * 4},
-                {b->mode == MRF_SERVE_ZOOM ? d.n_sim : nullptr,
-                 o.n_sim ? o.n_sim + v0 : nullptr, n * 4}};
+                {o.n_sim ? d.n_sim : nullptr, o.n_sim ? o.n_sim + v0 : nullptr, n * 4}};
       for (auto& c : cp) {
         if (!c.dst || !c.src) continue;
         const hipError_t e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, st);
@@ -665,6 +689,8 @@ extern "C" int mrf_server_register(mrf_server* srv, const mrf_sequence* seq, con
       return bail(MRF_ERR_DEVICE);
     }
     rc = mrf_zoom_schedule_paper(&s->grid, seq, &s->sched);
+    if (rc) return bail(rc);
+    rc = mrf_zoom_schedule_local(&s->grid, 8, &s->local);
     if (rc) return bail(rc);
   } else {
     for (int32_t n : lengths) s->norms[n] = nullptr;

@@ -160,3 +160,29 @@ def test_mixed_readout_counts_share_a_batch(env):
     for i, (a, b) in enumerate(zip(alone, mix[1:])):
         for k in a:
             assert np.array_equal(a[k], b[k]), (i, k)
+
+
+def test_refined_bf16_results_equal_direct_refinement(env):
+    """With refine_bf16 the served brute-force result of a BF16 slot is the
+    re-scored result refined by the unit-step local search, exactly as the
+    direct entry points give it (mrf_match_bruteforce, then
+    mrf_zoom_search_from with mrf_zoom_schedule_local(8)), for two readout
+    counts in one batch."""
+    api, ctx, sqs, grid = env
+    srv = api.Server(ctx, 4 * GB, max_inflight=16, n_streams=1, refine_bf16=True)
+    try:
+        slot = srv.register(sqs[0], grid, "bf16", lengths=(100, 200))
+        reqs = [("brute", slot, n, _voxels(api, ctx, sqs[0], grid, 300, 400 + n)) for n in (100, 200)]
+        served = _run(srv, reqs)[1]
+    finally:
+        srv.close()
+    for (m, s, n_tr, vox), got in zip(reqs, served):
+        d = api.simulate_dictionary(ctx, sqs[0], grid, n_tr=n_tr, dtype="bf16")
+        r = api.match_bruteforce(ctx, d, vox, top_k=8, seq=sqs[0], grid=grid)
+        ref = api.zoom_search(ctx, sqs[0], grid, vox, sched=api.schedule_local(grid, 8), n_tr=n_tr,
+                              start=r["idx"])
+        torch.cuda.synchronize()
+        for k in ("idx", "cc", "margin", "pd_re", "pd_im"):
+            assert np.array_equal(ref[k].cpu().numpy(), got[k]), (n_tr, k)
+        moved = float(np.mean(ref["idx"].cpu().numpy() != r["idx"].cpu().numpy()))
+        print(f"N={n_tr}: refinement moved {moved:.3f} of the re-scored results")
