@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "compensated.h"
 #include "internal.h"
 #include "match_common.h"
 #include "match_kernels.h"
@@ -373,7 +374,9 @@ __global__ __launch_bounds__(64) void k_merge_wave(MergeArgs a) {
 }
 
 // PD = <v, d> / ||d||^2 of the best entry (Theory: PD from the signal scale).
-// One wave per voxel; FP32 planar dictionary.
+// One wave per voxel; FP32 planar dictionary. The product is accumulated in
+// FP32 with compensation (Dot2) and the lanes' pairs are added with TwoSum;
+// only the entry's norm is accumulated in FP64.
 __global__ __launch_bounds__(64) void k_pd_f32(const float2* __restrict__ vox, int64_t ld_vox,
                                                int32_t n_vox, int32_t n_tr, const float* Bre,
                                                const float* Bim, int64_t ld,
@@ -383,27 +386,36 @@ __global__ __launch_bounds__(64) void k_pd_f32(const float2* __restrict__ vox, i
   const int lane = threadIdx.x;
   if (v >= n_vox) return;
   const int32_t e = best_i[(int64_t)v * kk];
-  double sr = 0.0, si = 0.0, n2 = 0.0;
+  float sr = 0.0f, cr = 0.0f, si = 0.0f, ci = 0.0f;
+  double n2 = 0.0;
   if (e != 0x7fffffff) {
     for (int j = lane; j < n_tr; j += 64) {
       const float2 x = vox[(int64_t)v * ld_vox + j];
-      const double dr = Bre[(int64_t)j * ld + e], di = Bim[(int64_t)j * ld + e];
-      sr += (double)x.x * dr + (double)x.y * di;
-      si += (double)x.y * dr - (double)x.x * di;
-      n2 += dr * dr + di * di;
+      const float dr = Bre[(int64_t)j * ld + e], di = Bim[(int64_t)j * ld + e];
+      dot2_acc(x.x, dr, sr, cr);
+      dot2_acc(x.y, di, sr, cr);
+      dot2_acc(x.y, dr, si, ci);
+      dot2_acc(-x.x, di, si, ci);
+      n2 = fma((double)dr, (double)dr, n2);
+      n2 = fma((double)di, (double)di, n2);
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
-    sr += __shfl_xor(sr, o);
-    si += __shfl_xor(si, o);
+    // the partner's pair as it was before this step's addition
+    const float osr = __shfl_xor(sr, o), ocr = __shfl_xor(cr, o);
+    const float osi = __shfl_xor(si, o), oci = __shfl_xor(ci, o);
+    two_sum_acc(sr, cr, osr);
+    cr += ocr;
+    two_sum_acc(si, ci, osi);
+    ci += oci;
     n2 += __shfl_xor(n2, o);
   }
   if (lane == 0) {
     // n_tr may be a prefix of the stored entries: use the prefix norm
     (void)norm;
-    const double d2 = n2;
-    if (pd_re) pd_re[v] = d2 > 0.0 ? (float)(sr / d2) : 0.0f;
-    if (pd_im) pd_im[v] = d2 > 0.0 ? (float)(si / d2) : 0.0f;
+    const float d2 = (float)n2;
+    if (pd_re) pd_re[v] = d2 > 0.0f ? (sr + cr) / d2 : 0.0f;
+    if (pd_im) pd_im[v] = d2 > 0.0f ? (si + ci) / d2 : 0.0f;
   }
 }
 

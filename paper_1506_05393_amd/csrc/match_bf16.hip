@@ -17,6 +17,7 @@
 #include "internal.h"
 #include "match_common.h"
 #include "match_kernels.h"
+#include "compensated.h"
 #include "smooth.h"
 
 namespace mrf {
@@ -355,14 +356,6 @@ struct RescoreArgs {
   int64_t* topk_idx;
   float* topk_cc;
 };
-
-// s + c += x, with the rounding error of the addition kept in c (Knuth's TwoSum).
-__device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
-  const float t = s + x;
-  const float z = t - s;
-  c += (s - (t - z)) + (x - z);
-  s = t;
-}
 
 template <bool SM>
 __global__ __launch_bounds__(64) void k_rescore(RescoreArgs a) {

@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "bloch.h"
+#include "compensated.h"
 #include "internal.h"
 #include "sim_kernels.h"
 #include "smooth.h"
@@ -133,10 +134,12 @@ struct EntryState {
   float r1ti[kQ];
 };
 
-// CC-map accumulators (MODE 3): <v, d> per entry and ||v||^2, FP32 partial
-// sums of four readouts added into FP64 (as the entry norms).
+// CC-map accumulators (MODE 3): <v, d> per entry, FP32 partial sums of four
+// readouts added with compensation (TwoSum: the sum and its rounding error,
+// both FP32), and ||v||^2, a norm, whose partials are added into FP64 as the
+// entry norms are.
 struct Dots {
-  double re[kQ], im[kQ];
+  float re[kQ], re_c[kQ], im[kQ], im_c[kQ];
   double vn2;
 };
 
@@ -169,7 +172,7 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
     m[q] = initial_spin(a.inversion, st.r1ti[q]);
     n2[q] = 0.0;
     nb[q] = 0.0;
-    dt.re[q] = dt.im[q] = 0.0;
+    dt.re[q] = dt.im[q] = dt.re_c[q] = dt.im_c[q] = 0.0f;
 #pragma unroll
     for (int k = 0; k < kSmoothLen; ++k) hx[q][k] = hy[q][k] = 0.f;
   }
@@ -191,8 +194,8 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
       nb[q] += (double)partb[q];
       part[q] = partb[q] = 0.f;
       if (MODE == 3) {
-        dt.re[q] += (double)pre[q];
-        dt.im[q] += (double)pim[q];
+        two_sum_acc(dt.re[q], dt.re_c[q], pre[q]);
+        two_sum_acc(dt.im[q], dt.im_c[q], pim[q]);
         pre[q] = pim[q] = 0.f;
       }
     }
@@ -427,9 +430,11 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int64_t e = blk0 + tid + kThreads * q;
+      // |<v, d>|^2 in FP32 from the compensated sums; the norms in FP64
+      const float re = dt.re[q] + dt.re_c[q], im = dt.im[q] + dt.im_c[q];
+      const float num = fmaf(re, re, im * im);
       const double den = n2[q] * dt.vn2;
-      const double num = dt.re[q] * dt.re[q] + dt.im[q] * dt.im[q];
-      if (e < a.count) a.cc[e] = den > 0.0 ? (float)sqrt(num / den) : 0.0f;
+      if (e < a.count) a.cc[e] = den > 0.0 ? (float)sqrt((double)num / den) : 0.0f;
     }
   } else if (a.norm) {
 #pragma unroll

@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "bloch.h"
+#include "compensated.h"
 #include "internal.h"
 #include "smooth.h"
 
@@ -130,22 +131,6 @@ struct EngineParams {
   int32_t tab_n;  // readouts per table row (n_tr is this voxel's count, <= tab_n)
   int32_t dims[4];
 };
-
-// Accumulates s + a b as the unevaluated pair (s, c): the rounding error of
-// the product (from an FMA) and of the sum (TwoSum) are gathered in c, the
-// compensated dot product of Ogita, Rump and Oishi ("Dot2"), which is as
-// accurate as a dot product in twice the working precision. Contraction is
-// off so that the product and the sum are each rounded once.
-__device__ __forceinline__ void dot2_acc(float a, float b, float& s, float& c) {
-#pragma clang fp contract(off)
-  const float p = a * b;
-  const float ep = fmaf(a, b, -p);
-  const float t = s + p;
-  const float z = t - s;
-  const float es = (s - (t - z)) + (p - z);
-  s = t;
-  c += ep + es;
-}
 
 // DI: the engine can evaluate both objectives (CC and the distance score of
 // the non-normalised fingerprint); every candidate is then simulated with the
