@@ -96,7 +96,8 @@ int mrf_sequence_destroy(mrf_sequence* seq);
 
 /* Parameter grid: one strictly increasing host value list per axis
  * (T1 ms > 0, T2 ms > 0, df Hz, B1 scale of every flip angle). b1.n == 0
- * means B1 = 1. T1 or T2 may be +inf (no relaxation). */
+ * means B1 = 1. T1 or T2 may be +inf (no relaxation). At most 2^39 entries
+ * (more -> MRF_ERR_INVALID). */
 typedef struct {
   int32_t n;
   const double* v;

@@ -58,8 +58,9 @@ int check_grid(const mrf_grid* g) {
   if ((rc = check_axis(g->t2_ms, "t2", false, true))) return rc;
   if ((rc = check_axis(g->df_hz, "df", false, false))) return rc;
   if ((rc = check_axis(g->b1, "b1", true, false))) return rc;
-  if (grid_size_checked(g) > ((int64_t)1 << 40)) {
-    set_error("grid too large");
+  // (ZOOM's memo keys hold an entry index in 39 bits)
+  if (grid_size_checked(g) > ((int64_t)1 << 39)) {
+    set_error("grid too large (more than 2^39 entries)");
     return MRF_ERR_INVALID;
   }
   return MRF_OK;

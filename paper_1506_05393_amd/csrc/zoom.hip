@@ -139,7 +139,20 @@ template <int G, bool SM, bool GA, bool DI = false>
 struct Engine {
   EngineParams pa;
 
+  // memo key: (voxel serial << 40) | kSpecBit? | entry index (< 2^39)
   static constexpr int64_t kIndexMask = ((int64_t)1 << 40) - 1;
+  static constexpr int64_t kSpecBit = (int64_t)1 << 39;
+  // Look-ahead: a decision that leaves lanes of its group idle fills them
+  // with entries that later decisions are likely to ask for (the next points
+  // along a 1-D climb, the neighbours one more 2-D move ahead, the first
+  // points of the following zoom stages at the current centre). Their values
+  // go to the memo flagged kSpecBit; the first decision that reads one
+  // counts it in n_sim, so n_sim still counts the entries the search
+  // consulted, and no decision depends on which lane computed a value.
+  // (The gathering engine reads rows instead and does not look ahead.)
+  static constexpr bool kLookAhead = !GA;
+  const mrf_zoom_stage* nxt;  // the stages after the running one
+  int32_t n_nxt;
   const float2* vx;  // the voxel's fingerprint (global memory, read-only)
   float vinv;        // 1 / ||v||: the unit-norm voxel is vx * vinv
   double vn;         // ||v|| (FP64)
@@ -474,6 +487,14 @@ struct Engine {
     }
     return __hip_atomic_load(mval + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // rewrites a slot's key (its value stays): clears the look-ahead flag
+  __device__ void memo_st_key(uint32_t s, int64_t kv) const {
+    if constexpr (GA) {
+      mkey[s] = kv;
+    } else {
+      __hip_atomic_store(mkey + s, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
   __device__ void memo_st(uint32_t s, int64_t kv, float v, float v2 = 0.0f) const {
     if constexpr (GA) {
       mval[s] = v;
@@ -491,10 +512,14 @@ struct Engine {
   }
 
   // Wave-level evaluation: every lane with `valid` asks for the value at i.
-  __device__ float eval(bool valid, const int32_t* i) {
+  // A lane with `spec` (look-ahead) is evaluated only when a lane of its
+  // group without it needs a simulation in the same call, and not when a
+  // lane asks for the same entry; its value is for the memo only.
+  __device__ float eval(bool valid, const int32_t* i, bool spec = false) {
     float val = -INFINITY;
     float cc_v = -INFINITY, sc_v = -INFINITY;  // DI: both values of a new entry
     bool need = false;
+    bool first_read = false;  // a decision's first read of a look-ahead entry
     int64_t k = -1;
     const int32_t cap = pa.memo_cap;
     if (valid && in_range(i)) {
@@ -504,14 +529,32 @@ struct Engine {
       need = true;
       for (int32_t probe = 0; probe < cap; ++probe) {
         const int64_t mk = memo_ld_key(s);
-        if (mk == tagged) {
+        if ((mk & ~kSpecBit) == tagged) {
           val = memo_ld_val(s);
           need = false;
+          if (kLookAhead && (mk & kSpecBit) && !spec) {
+            first_read = true;
+            memo_st_key(s, tagged);
+          }
           break;
         }
         if ((mk & ~kIndexMask) != tag) break;  // empty for this voxel
         s = (s + 1) & (cap - 1);
       }
+    }
+    uint64_t mspec = 0;
+    if constexpr (kLookAhead) {
+      // look-ahead lanes ride along only with a needed simulation, and
+      // never twice for one entry
+      const bool real = grp_ballot<G>(need && !spec, gbase) != 0;
+      bool drop = spec && need && !real;
+      for (int o = 0; o < G; ++o) {
+        const int64_t ko = __shfl(k, o, G);
+        const int no = __shfl((int)need | ((int)spec << 1), o, G);
+        if (spec && (no & 1) && ko == k && o != lane && (!(no & 2) || o < lane)) drop = true;
+      }
+      if (drop) need = false;
+      mspec = grp_ballot<G>(need && spec, gbase);
     }
     if constexpr (GA) {
       // the group reads the needed entries together, kGather at a time
@@ -548,21 +591,24 @@ struct Engine {
       }
     }
     uint64_t m = grp_ballot<G>(need, gbase);
-    n_sim += __popcll(m);
+    n_sim += __popcll(m & ~mspec) + __popcll(grp_ballot<G>(first_read, gbase));
     while (m) {
       const int src = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
+      const bool sp = (mspec >> src) & 1;
       const int64_t ks = __shfl(k, src, G);
       const float vv = __shfl(DI ? cc_v : val, src, G);
       const float v2 = DI ? __shfl(sc_v, src, G) : 0.0f;
-      if (memo_count * 4 < cap * 3) {
+      // look-ahead entries keep to half the slots, so the entries that
+      // decisions ask for still find room
+      if (memo_count * 4 < cap * 3 && (!sp || memo_count * 2 < cap)) {
         if (lane == 0) {
           uint32_t s = memo_home(ks);
           while ((memo_ld_key(s) & ~kIndexMask) == tag) s = (s + 1) & (cap - 1);
-          memo_st(s, tag | ks, vv, v2);
+          memo_st(s, tag | ks | (sp ? kSpecBit : 0), vv, v2);
         }
         ++memo_count;
-      } else {
+      } else if (!sp) {
         overflow = true;
       }
     }
@@ -688,6 +734,93 @@ struct Engine {
     });
   }
 
+  // ---- look-ahead points ---------------------------------------------------
+  // The first decision of a zoom stage taken from the centre asks for
+  // c -/+ s (1-D) or the 8 neighbours (2-D); a scan is not looked into.
+  __device__ static int first_count(const mrf_zoom_stage& st) {
+    return st.kind == MRF_ZOOM1 ? 2 : (st.kind == MRF_ZOOM2 ? 8 : 0);
+  }
+  __device__ void first_point(const mrf_zoom_stage& st, int q, int32_t* p) const {
+    for (int a = 0; a < 4; ++a) p[a] = c[a];
+    const int s0 = st.step0 > 0 ? st.step0 : 1;
+    if (st.kind == MRF_ZOOM1) {
+      p[st.axis0] += q == 0 ? -s0 : s0;
+    } else {
+      const int s1 = st.step1 > 0 ? st.step1 : 1;
+      p[st.axis0] += nb_d0(q) * s0;
+      p[st.axis1] += nb_d1(q) * s1;
+    }
+  }
+  // points of the first decisions of the next two stages, up to a scan
+  __device__ int ahead_count() const {
+    int n = 0;
+    for (int t = 0; t < n_nxt && t < 2; ++t) {
+      const int m = first_count(nxt[t]);
+      if (m == 0) break;
+      n += m;
+    }
+    return n;
+  }
+  __device__ void ahead_point(int r, int32_t* p) const {
+    for (int t = 0; t < n_nxt && t < 2; ++t) {
+      const int m = first_count(nxt[t]);
+      if (r < m) {
+        first_point(nxt[t], r, p);
+        return;
+      }
+      r -= m;
+    }
+  }
+  // look-ahead point r of a 1-D zoom decision at c (step s on axis ax; dir
+  // = the direction of the stage's last move, 0 before any): the next point
+  // of the climb (both ways before a move), the next stages' first points,
+  // then further along the climb
+  __device__ void zoom1_ahead(int r, int ax, int s, int dir, int32_t* p) const {
+    for (int a = 0; a < 4; ++a) p[a] = c[a];
+    const int n0 = dir == 0 ? 2 : 1;
+    if (r < n0) {
+      p[ax] += (dir == 0 ? (r == 0 ? 2 : -2) : 2 * dir) * s;
+      return;
+    }
+    r -= n0;
+    const int na = ahead_count();
+    if (r < na) {
+      ahead_point(r, p);
+      return;
+    }
+    r -= na;
+    if (dir == 0) {
+      const int m = 3 + r / 2;
+      p[ax] += ((r & 1) ? -m : m) * s;
+    } else {
+      p[ax] += (3 + r) * dir * s;
+    }
+  }
+  // look-ahead point r of a 2-D zoom decision at c: the points that become
+  // neighbours after one more move along the last direction d (3 after a
+  // move along an axis, 5 after a diagonal one; none before a move), then
+  // the next stages' first points; false past them
+  __device__ bool zoom2_ahead(int r, int a0, int a1, int s0, int s1, int d, int32_t* p) const {
+    for (int a = 0; a < 4; ++a) p[a] = c[a];
+    if (d >= 0) {
+      for (int w = 0; w < 8; ++w) {
+        const int e0 = nb_d0(d) + nb_d0(w), e1 = nb_d1(d) + nb_d1(w);
+        if (e0 != 2 && e0 != -2 && e1 != 2 && e1 != -2) continue;
+        if (r == 0) {
+          p[a0] += e0 * s0;
+          p[a1] += e1 * s1;
+          return true;
+        }
+        --r;
+      }
+    }
+    if (r < ahead_count()) {
+      ahead_point(r, p);
+      return true;
+    }
+    return false;
+  }
+
   __device__ void move_to(const int32_t* p, float v) {
     for (int q = 0; q < 4; ++q) c[q] = p[q];
     cval = v;
@@ -696,35 +829,49 @@ struct Engine {
   __device__ void zoom1(int ax, int s, bool pruned) {
     s = s > 0 ? s : 1;
     need_centre();
+    int dir = 0;
     for (int guard = 0; guard < (1 << 20); ++guard) {
       int32_t L[4] = {c[0], c[1], c[2], c[3]}, R[4] = {c[0], c[1], c[2], c[3]};
       L[ax] -= s;
       R[ax] += s;
+      // lane 0 asks for R (pruned) or L, lane 1 for R; the others look ahead
+      int32_t P[4];
+      bool sp = false;
+      if (kLookAhead && lane >= 2) {
+        zoom1_ahead(lane - 2, ax, s, dir, P);
+        sp = true;
+      } else {
+        for (int a = 0; a < 4; ++a) P[a] = (lane == 0) != pruned ? L[a] : R[a];
+        sp = kLookAhead && pruned && lane == 1;
+      }
       if (pruned) {
-        const float vr = __shfl(eval(lane == 0, R), 0, G);
+        const float vr = __shfl(eval(lane == 0 || sp, P, sp), 0, G);
         log_pair(vr, cval);
         if (vr > cval) {
           move_to(R, vr);
+          dir = 1;
           continue;
         }
         const float vl = __shfl(eval(lane == 0, L), 0, G);
         log_pair(vl, cval);
         if (vl > cval) {
           move_to(L, vl);
+          dir = -1;
           continue;
         }
         break;
       }
-      const int32_t* P = lane == 0 ? L : R;
-      const float v = eval(lane < 2, P);
+      const float v = eval(lane < 2 || sp, P, sp);
       log_top2(lane < 2 ? v : -INFINITY, true);
       const float vl = __shfl(v, 0, G), vr = __shfl(v, 1, G);
       const bool right = vr > vl;
       const float bv = right ? vr : vl;
-      if (bv > cval)
+      if (bv > cval) {
         move_to(right ? R : L, bv);
-      else
+        dir = right ? 1 : -1;
+      } else {
         break;
+      }
     }
   }
 
@@ -735,12 +882,16 @@ struct Engine {
     for (int q = 0; q < 4; ++q) p[q] = c[q] + (q == a0 ? nb_d0(w) * s0 : 0) + (q == a1 ? nb_d1(w) * s1 : 0);
   }
 
-  // evaluate the neighbours in `mask` (bit w = neighbour w), one per lane
-  __device__ void eval_nb(uint32_t mask, int a0, int a1, int s0, int s1) {
+  // evaluate the neighbours in `mask` (bit w = neighbour w), one per lane;
+  // the move's other neighbours and lanes 8 and up look ahead (d: the last
+  // move's direction, -1 before any)
+  __device__ void eval_nb(uint32_t mask, int a0, int a1, int s0, int s1, int d) {
     int32_t p[4];
     neighbour(lane & 7, a0, a1, s0, s1, p);
     const bool mine = lane < 8 && ((mask >> lane) & 1u);
-    const float v = eval(mine, p);
+    bool sp = false;
+    if (kLookAhead) sp = lane < 8 ? !mine : zoom2_ahead(lane - 8, a0, a1, s0, s1, d, p);
+    const float v = eval(mine || sp, p, sp);
     if (mine) nbv[lane] = v;
     wave_fence();
   }
@@ -750,11 +901,14 @@ struct Engine {
     s1 = s1 > 0 ? s1 : 1;
     need_centre();
     enum { NL = 0, NR, ND, NU, NLD, NLU, NRD, NRU };
+    int d = -1;  // the last move's direction
     for (int guard = 0; guard < (1 << 20); ++guard) {
       if (!pruned) {
         int32_t p[4];
         neighbour(lane & 7, a0, a1, s0, s1, p);
-        const float v = eval(lane < 8, p);
+        bool sp = false;
+        if (kLookAhead && lane >= 8) sp = zoom2_ahead(lane - 8, a0, a1, s0, s1, d, p);
+        const float v = eval(lane < 8 || sp, p, sp);
         log_top2(lane < 8 ? v : -INFINITY, true);
         float bv;
         const int src = grp_first_max<G>(lane < 8 ? v : -INFINITY, bv, gbase);
@@ -762,6 +916,7 @@ struct Engine {
           int32_t q[4];
           neighbour(src, a0, a1, s0, s1, q);
           move_to(q, bv);
+          d = src;
         } else {
           break;
         }
@@ -772,7 +927,7 @@ struct Engine {
       if (lane < 8) v[lane] = -INFINITY;
       wave_fence();
       const float C = cval;
-      eval_nb((1u << NL) | (1u << ND), a0, a1, s0, s1);
+      eval_nb((1u << NL) | (1u << ND), a0, a1, s0, s1, d);
       log_pair(v[NL], C);
       log_pair(v[ND], C);
       const bool upL = v[NL] > C, upD = v[ND] > C;
@@ -780,18 +935,18 @@ struct Engine {
       uint32_t cand = 0;
       if (upL && upD) {
         cand = (1u << NL) | (1u << ND);
-        eval_nb(1u << NLD, a0, a1, s0, s1);
+        eval_nb(1u << NLD, a0, a1, s0, s1, d);
         log_pair(v[NLD], C);
         if (v[NLD] > C) target = NLD;
       } else if (!upL && !upD) {
-        eval_nb((1u << NR) | (1u << NU), a0, a1, s0, s1);
+        eval_nb((1u << NR) | (1u << NU), a0, a1, s0, s1, d);
         log_pair(v[NR], C);
         log_pair(v[NU], C);
         const bool upR = v[NR] > C, upU = v[NU] > C;
         if (!upR && !upU) break;
         if (upR && upU) {
           cand = (1u << NR) | (1u << NU);
-          eval_nb(1u << NRU, a0, a1, s0, s1);
+          eval_nb(1u << NRU, a0, a1, s0, s1, d);
           log_pair(v[NRU], C);
           if (v[NRU] > C) target = NRU;
         } else {
@@ -799,11 +954,11 @@ struct Engine {
         }
       } else if (upL) {
         cand = 1u << NL;
-        eval_nb(1u << NU, a0, a1, s0, s1);
+        eval_nb(1u << NU, a0, a1, s0, s1, d);
         log_pair(v[NU], C);
         if (v[NU] > C) {
           cand |= 1u << NU;
-          eval_nb(1u << NLU, a0, a1, s0, s1);
+          eval_nb(1u << NLU, a0, a1, s0, s1, d);
           log_pair(v[NLU], C);
           if (v[NLU] > C) target = NLU;
         } else {
@@ -811,11 +966,11 @@ struct Engine {
         }
       } else {
         cand = 1u << ND;
-        eval_nb(1u << NR, a0, a1, s0, s1);
+        eval_nb(1u << NR, a0, a1, s0, s1, d);
         log_pair(v[NR], C);
         if (v[NR] > C) {
           cand |= 1u << NR;
-          eval_nb(1u << NRD, a0, a1, s0, s1);
+          eval_nb(1u << NRD, a0, a1, s0, s1, d);
           log_pair(v[NRD], C);
           if (v[NRD] > C) target = NRD;
         } else {
@@ -834,6 +989,7 @@ struct Engine {
       int32_t q[4];
       neighbour(target, a0, a1, s0, s1, q);
       move_to(q, v[target]);
+      d = target;
     }
   }
 
@@ -992,6 +1148,8 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.vinv = inv;
     e.vn = nv;
     e.obj = MRF_OBJ_CC;
+    e.nxt = S->stages;
+    e.n_nxt = 0;
     e.mkey = mkey;
     e.mval = mval;
     e.tag = serial << 40;
@@ -1033,10 +1191,18 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
       for (int q = 0; q < 4; ++q) e.c[q] = min(max(s0[q], e.lo[q]), e.hi[q]);
       e.cknown = false;
       e.obj = MRF_OBJ_CC;
-      for (int i = 0; i < S->n_stages; ++i) e.run_stage(S->stages[i], S->pruned != 0);
+      for (int i = 0; i < S->n_stages; ++i) {
+        e.nxt = S->stages + i + 1;
+        e.n_nxt = S->n_stages - i - 1;
+        e.run_stage(S->stages[i], S->pruned != 0);
+      }
       for (int r = 0; r < S->outer_max && S->n_outer > 0; ++r) {
         const int32_t b0 = e.c[0], b1 = e.c[1], b2 = e.c[2], b3 = e.c[3];
-        for (int i = 0; i < S->n_outer; ++i) e.run_stage(S->outer[i], S->pruned != 0);
+        for (int i = 0; i < S->n_outer; ++i) {
+          e.nxt = S->outer + i + 1;
+          e.n_nxt = S->n_outer - i - 1;
+          e.run_stage(S->outer[i], S->pruned != 0);
+        }
         if (b0 == e.c[0] && b1 == e.c[1] && b2 == e.c[2] && b3 == e.c[3]) break;
       }
       e.need_centre();
