@@ -59,6 +59,18 @@ struct Tables {
   float2* t1T = nullptr;  // [n1][n_tr]
   float2* t2T = nullptr;  // [n2][n_tr]
   float4* dfT = nullptr;  // [n3][n_tr]
+  // TE = TR - TE at every readout (TE = TR / 2, as in bSSFP): both halves of
+  // each TR share their factors, kept once in compact entry-major rows of tq
+  // readouts (n_tr rounded up to a multiple of 4, so a 16-byte load covers
+  // four readouts of h1 / h2 and two of hd); NULL otherwise
+  int32_t symmetric = 0;
+  int32_t tq = 0;
+  float* h1 = nullptr;   // [n1][tq]  1-E1 over TE
+  float* h2 = nullptr;   // [n2][tq]  1-E2 over TE
+  float2* hd = nullptr;  // [n3][tq]  (cos-1, sin) over TE
+  // x-axis pulses (x_axis_pulses): (R11, R12, R21, R22) per readout, the
+  // only entries of the rotation that are not exact 0 or 1; NULL otherwise
+  float4* xr = nullptr;  // [n4][tq]
   void* block = nullptr;  // one allocation holding all of the above
 };
 // A held reference to built tables (see get_tables).

@@ -94,6 +94,11 @@ struct K0Args {
   float2* t1T;
   float2* t2T;
   float4* dfT;
+  int32_t tq;  // compact row length (when any of h1, h2, hd, xr is set)
+  float* h1;
+  float* h2;
+  float2* hd;
+  float4* xr;
 };
 
 __global__ void k_step_tables(K0Args a) {
@@ -111,6 +116,7 @@ __global__ void k_step_tables(K0Args a) {
                                    (float)one_minus_exp(a.tb[j], a.ax1[i]));
       a.t1[u] = f;
       a.t1T[(int64_t)i * a.n_tr + j] = f;
+      if (a.h1) a.h1[(int64_t)i * a.tq + j] = f.x;
       continue;
     }
     u -= n_t1;
@@ -125,6 +131,7 @@ __global__ void k_step_tables(K0Args a) {
                                    (float)one_minus_exp(a.tb[j], a.ax2[i]));
       a.t2[u] = f;
       a.t2T[(int64_t)i * a.n_tr + j] = f;
+      if (a.h2) a.h2[(int64_t)i * a.tq + j] = f.x;
       continue;
     }
     u -= n_t2;
@@ -135,12 +142,15 @@ __global__ void k_step_tables(K0Args a) {
       precession(a.tb[j], a.ax3[i], &f.z, &f.w);
       a.df[u] = f;
       a.dfT[(int64_t)i * a.n_tr + j] = f;
+      if (a.hd) a.hd[(int64_t)i * a.tq + j] = make_float2(f.x, f.y);
       continue;
     }
     u -= n_df;
     {
       int b = (int)(u / a.n_tr), j = (int)(u % a.n_tr);
-      pulse_matrix(a.fa[j], a.ph[j], a.ax4[b], a.rf + ((int64_t)b * a.n_tr + j) * 9);
+      float* R = a.rf + ((int64_t)b * a.n_tr + j) * 9;
+      pulse_matrix(a.fa[j], a.ph[j], a.ax4[b], R);
+      if (a.xr) a.xr[(int64_t)b * a.tq + j] = make_float4(R[4], R[5], R[7], R[8]);
     }
   }
 }
@@ -201,7 +211,18 @@ static int build_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, uint
   size_t o_t1T = align256(o_rf + sizeof(float) * 9 * nt * t.n4);
   size_t o_t2T = align256(o_t1T + sizeof(float2) * nt * t.n1);
   size_t o_dfT = align256(o_t2T + sizeof(float2) * nt * t.n2);
-  size_t o_in = align256(o_dfT + sizeof(float4) * nt * t.n3);
+  // compact tables: symmetric TRs (TE exactly equal to TR - TE in FP64, so
+  // both halves' FP32 factors are the same numbers) and x-axis pulses
+  t.symmetric = n_tr > 0;
+  for (int32_t j = 0; j < n_tr; ++j)
+    if (seq->te[j] != seq->tr[j] - seq->te[j]) t.symmetric = 0;
+  t.tq = (int32_t)((nt + 3) / 4 * 4);
+  const size_t tq = (size_t)t.tq;
+  size_t o_h1 = align256(o_dfT + sizeof(float4) * nt * t.n3);
+  size_t o_h2 = align256(o_h1 + (t.symmetric ? sizeof(float) * tq * t.n1 : 0));
+  size_t o_hd = align256(o_h2 + (t.symmetric ? sizeof(float) * tq * t.n2 : 0));
+  size_t o_xr = align256(o_hd + (t.symmetric ? sizeof(float2) * tq * t.n3 : 0));
+  size_t o_in = align256(o_xr + (t.x_axis_pulses ? sizeof(float4) * tq * t.n4 : 0));
   // staged FP64 inputs: ta, tb, fa, ph, ax1..ax4
   const size_t n_in = 4 * nt + t.n1 + t.n2 + t.n3 + t.n4;
   size_t total = o_in + sizeof(double) * n_in;
@@ -218,6 +239,12 @@ static int build_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, uint
   t.t1T = (float2*)(base + o_t1T);
   t.t2T = (float2*)(base + o_t2T);
   t.dfT = (float4*)(base + o_dfT);
+  if (t.symmetric) {
+    t.h1 = (float*)(base + o_h1);
+    t.h2 = (float*)(base + o_h2);
+    t.hd = (float2*)(base + o_hd);
+  }
+  if (t.x_axis_pulses) t.xr = (float4*)(base + o_xr);
   std::vector<double> in(n_in);
   double* p = in.data();
   for (int32_t j = 0; j < n_tr; ++j) {
@@ -257,6 +284,11 @@ static int build_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, uint
     a.t1T = t.t1T;
     a.t2T = t.t2T;
     a.dfT = t.dfT;
+    a.tq = t.tq;
+    a.h1 = t.h1;
+    a.h2 = t.h2;
+    a.hd = t.hd;
+    a.xr = t.xr;
     int64_t work = (int64_t)nt * (t.n1 + t.n2 + t.n3 + t.n4) + t.n1;
     int blocks = (int)std::min<int64_t>((work + 255) / 256, 4096);
     hipLaunchKernelGGL(k_step_tables, dim3(blocks), dim3(256), 0, stream, a);

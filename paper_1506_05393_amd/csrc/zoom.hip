@@ -33,6 +33,16 @@ struct ZoomArgs {
   int32_t tab_n;            // readouts per table row (>= every voxel's readout count)
   const int32_t* vox_n_tr;  // per-voxel readout counts [n_vox], or NULL (all n_tr)
   int32_t x_axis;  // every RF phase a multiple of 180 deg: pulses rotate about x
+  // compact tables of symmetric TRs with x-axis pulses (all non-NULL, the
+  // voxel rows 16-byte aligned and no smoothing), else half = 0
+  int32_t half, tq;
+  const float* h1;
+  const float* h2;
+  const float2* hd;
+  const float4* xr;
+  // readouts per LDS row holding a group's voxel scaled to unit norm (read
+  // by the compact-table path), 0 = the voxel is read from global memory
+  int32_t vrow;
   int32_t dims[4];
   const float2* vox;
   int64_t ld_vox;
@@ -51,8 +61,9 @@ struct ZoomArgs {
   int32_t* n_sim;
   int32_t* counter;
   int32_t memo_cap;  // slots per wave, power of two
-  int64_t* memo_keys;  // [grid blocks][memo_cap]
-  float* memo_vals;
+  // [grid blocks][voxel groups][memo_cap] slots of 16 bytes: the key, then
+  // the value (CC) or with distance stages both values (CC, score)
+  int64_t* memo_slots;
   const mrf_zoom_schedule* sch;  // device copy (workspace)
   SmoothW sm;  // temporal smoothing of the entries (SM kernels)
   const float2* demod;  // [n_tr] (cos, sin) of the RF phases (SM kernels)
@@ -129,6 +140,11 @@ struct EngineParams {
   const float* rf;
   int32_t n_tr, inversion, memo_cap, x_axis;
   int32_t tab_n;  // readouts per table row (n_tr is this voxel's count, <= tab_n)
+  int32_t half, tq;  // compact tables (see ZoomArgs)
+  const float* h1;
+  const float* h2;
+  const float2* hd;
+  const float4* xr;
   int32_t dims[4];
 };
 
@@ -154,10 +170,11 @@ struct Engine {
   const mrf_zoom_stage* nxt;  // the stages after the running one
   int32_t n_nxt;
   const float2* vx;  // the voxel's fingerprint (global memory, read-only)
+  const float2* vs;  // vx * vinv in LDS (same FP32 products), or NULL
   float vinv;        // 1 / ||v||: the unit-norm voxel is vx * vinv
   double vn;         // ||v|| (FP64)
-  int64_t* mkey;     // this wave's memo (global memory)
-  float* mval;       // [slots] CC, or with DI [slots][2] (CC, distance score)
+  int64_t* mkey;     // this group's memo: 16-byte slots (global memory), or
+  float* mval;       // with GA separate key and value arrays (LDS)
   int32_t obj;       // objective of the stage being run (MRF_OBJ_*; DI only)
   int64_t tag;       // voxel serial << 40
   float* nbv;  // [8] neighbour values of one pruned move (LDS)
@@ -343,6 +360,13 @@ struct Engine {
         }
       }
     }
+    return finish<COMP>(dr, di, cr, ci, n2, pdr, pdi, pn2, psc);
+  }
+  // CC (and with COMP the distance score) from the dot-product sums and the
+  // entry's squared norm; the optional outputs take the sums
+  template <bool COMP>
+  __device__ float finish(float dr, float di, float cr, float ci, double n2, float* pdr,
+                          float* pdi, double* pn2, float* psc) const {
     if constexpr (COMP) {
       // the pairs as FP64 values; |<v, d>| = |<v * vinv, d>| / vinv, and
       // the distance score -||v - exp(i phi) d||^2 / ||v||^2 (best phase)
@@ -370,6 +394,135 @@ struct Engine {
       return (float)(sqrt((double)dr * dr + (double)di * di) / sqrt(n2));
     }
   }
+
+  // simulate_cc_t for symmetric TRs with x-axis pulses, from the compact
+  // tables: both halves of a TR apply the same factors, so one 16-byte load
+  // brings four readouts of 1-E1 or 1-E2, or two of the precession, and the
+  // pulses of four readouts are one scalar load when every lane uses B1 = 1
+  // (LANE_R: the B1 axis picks the row, one vector load per readout). The
+  // arithmetic is that of simulate_cc_t, operation for operation, so the
+  // values are the same. The loads run kAq quads (four readouts) ahead.
+  static constexpr int kAq = 4;
+  template <bool LANE_R, bool COMP, bool VS>
+  __device__ float simulate_half(const int32_t* i, float* pdr, float* pdi, double* pn2,
+                                 float* psc) const {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) v4 gf4;
+    typedef const __attribute__((address_space(1))) float gf1;
+    typedef const __attribute__((address_space(1))) v2 gf2;
+    typedef const __attribute__((address_space(4))) v4 cf4;
+    typedef const __attribute__((address_space(3))) v4 lf4;
+    typedef const __attribute__((address_space(3))) v2 lf2;
+    const int32_t n = pa.n_tr, tq = pa.tq;
+    gf1* p1 = (gf1*)(pa.h1 + (int64_t)i[0] * tq);
+    gf1* p2 = (gf1*)(pa.h2 + (int64_t)i[1] * tq);
+    gf2* pd = (gf2*)(pa.hd + (int64_t)i[2] * tq);
+    gf4* q1 = (gf4*)p1;
+    gf4* q2 = (gf4*)p2;
+    gf4* qd = (gf4*)pd;
+    gf4* qv = (gf4*)vx;
+    gf4* rl = (gf4*)(pa.xr + (LANE_R ? (int64_t)i[3] * tq : 0));
+    cf4* ru = (cf4*)pa.xr;
+    auto pulse = [&](int32_t j) -> v4 { return LANE_R ? rl[j] : ru[j]; };
+    Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
+    float dr = 0.0f, di = 0.0f, cr = 0.0f, ci = 0.0f;
+    double n2 = 0.0;
+    auto step = [&](float r1, float r2, float cm1, float sn, float vxr, float vxi, v4 R) {
+      {
+        const float y = m.y, z = m.z;
+        m.y = fmaf(R.y, z, R.x * y);
+        m.z = fmaf(R.w, z, R.z * y);
+      }
+      free_evolve(m, cm1, sn, r2, r1);
+      const float sx = m.x, sy = m.y;
+      // VS: the LDS copy already holds these products
+      const float vr = VS ? vxr : vxr * vinv, vi = VS ? vxi : vxi * vinv;
+      if constexpr (COMP) {
+        dot2_acc(vr, sx, dr, cr);
+        dot2_acc(vi, sy, dr, cr);
+        dot2_acc(vi, sx, di, ci);
+        dot2_acc(-vr, sy, di, ci);
+      } else {
+        dr = fmaf(vr, sx, fmaf(vi, sy, dr));
+        di = fmaf(vi, sx, fmaf(-vr, sy, di));
+      }
+      n2 = fma((double)sx, (double)sx, n2);
+      n2 = fma((double)sy, (double)sy, n2);
+      free_evolve(m, cm1, sn, r2, r1);
+    };
+    // one quad: readouts 4k .. 4k + 3
+    struct Quad {
+      v4 a, b, d0, d1, v0, v1;
+      v4 r[LANE_R ? 4 : 1];
+    };
+    auto load = [&](int32_t k, Quad& u) {
+      u.a = q1[k];
+      u.b = q2[k];
+      u.d0 = qd[2 * k];
+      u.d1 = qd[2 * k + 1];
+      if constexpr (VS) {
+        u.v0 = ((lf4*)vs)[2 * k];
+        u.v1 = ((lf4*)vs)[2 * k + 1];
+      } else {
+        u.v0 = qv[2 * k];
+        u.v1 = qv[2 * k + 1];
+      }
+      if constexpr (LANE_R) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) u.r[t] = rl[4 * k + t];
+      }
+    };
+    auto run = [&](int32_t k, const Quad& u) {
+      // k is the same on every lane that runs the loop: the pulses are
+      // scalar loads
+      const int32_t ks = __builtin_amdgcn_readfirstlane(k);
+      const v4 R0 = LANE_R ? u.r[0] : ru[4 * ks];
+      const v4 R1 = LANE_R ? u.r[1] : ru[4 * ks + 1];
+      const v4 R2 = LANE_R ? u.r[2] : ru[4 * ks + 2];
+      const v4 R3 = LANE_R ? u.r[3] : ru[4 * ks + 3];
+      step(u.a.x, u.b.x, u.d0.x, u.d0.y, u.v0.x, u.v0.y, R0);
+      step(u.a.y, u.b.y, u.d0.z, u.d0.w, u.v0.z, u.v0.w, R1);
+      step(u.a.z, u.b.z, u.d1.x, u.d1.y, u.v1.x, u.v1.y, R2);
+      step(u.a.w, u.b.w, u.d1.z, u.d1.w, u.v1.z, u.v1.w, R3);
+    };
+    const int32_t nq = n >> 2;
+    int32_t k = 0;
+    if (nq >= 2 * kAq) {
+      Quad ring[kAq];
+#pragma unroll
+      for (int t = 0; t < kAq; ++t) load(t, ring[t]);
+      // the ring holds quads k .. k + kAq - 1, and k + kAq < nq
+      for (; k + 2 * kAq <= nq; k += kAq) {
+#pragma unroll
+        for (int t = 0; t < kAq; ++t) {
+          run(k + t, ring[t]);
+          load(k + t + kAq, ring[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kAq; ++t) run(k + t, ring[t]);
+      k += kAq;
+    }
+    for (; k < nq; ++k) {
+      Quad u;
+      load(k, u);
+      run(k, u);
+    }
+    gf2* vv = (gf2*)vx;
+    for (int32_t j = 4 * nq; j < n; ++j) {
+      const v2 c = pd[j];
+      v2 v;
+      if constexpr (VS) {
+        v = ((lf2*)vs)[j];
+      } else {
+        v = vv[j];
+      }
+      step(p1[j], p2[j], c.x, c.y, v.x, v.y, pulse(j));
+    }
+    return finish<COMP>(dr, di, cr, ci, n2, pdr, pdi, pn2, psc);
+  }
+
   // GA: CC of up to kGather resident entries against the voxel, read by the
   // whole group: lane l takes readout pairs l, l + G, ... of every entry's
   // row (each load instruction covers G x 16 contiguous bytes of a row) and
@@ -453,6 +606,17 @@ struct Engine {
   // (psc receives the distance score)
   __device__ float simulate_cc(const int32_t* i, float* pdr = nullptr, float* pdi = nullptr,
                                double* pn2 = nullptr, float* psc = nullptr) const {
+    if constexpr (!SM) {
+      if (pa.half) {
+        if constexpr (G >= 16) {
+          if (vs)
+            return pa.dims[3] > 1 ? simulate_half<true, DI, true>(i, pdr, pdi, pn2, psc)
+                                  : simulate_half<false, DI, true>(i, pdr, pdi, pn2, psc);
+        }
+        return pa.dims[3] > 1 ? simulate_half<true, DI, false>(i, pdr, pdi, pn2, psc)
+                              : simulate_half<false, DI, false>(i, pdr, pdi, pn2, psc);
+      }
+    }
     if (pa.dims[3] > 1)
       return pa.x_axis ? simulate_cc_t<true, true, DI>(i, pdr, pdi, pn2, psc)
                        : simulate_cc_t<true, false, DI>(i, pdr, pdi, pn2, psc);
@@ -460,22 +624,28 @@ struct Engine {
                      : simulate_cc_t<false, false, DI>(i, pdr, pdi, pn2, psc);
   }
 
-  // Memo: this wave's private open-addressing table in global memory. A slot
-  // holds (voxel serial << 40 | entry index); slots of earlier voxels count
-  // as empty, so the table is never cleared between voxels. Loads and stores
-  // are device-coherent (they bypass the non-coherent L1).
+  // Memo: this group's private open-addressing table in global memory. A
+  // slot is 16 bytes, the key (voxel serial << 40 | entry index) and then
+  // the value(s), so a probe and its value share a cache line; slots of
+  // earlier voxels count as empty, so the table is never cleared between
+  // voxels. Loads and stores are device-coherent (they bypass the
+  // non-coherent L1).
   __device__ uint32_t memo_home(int64_t k) const {
     return (uint32_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(pa.memo_cap - 1);
+  }
+  __device__ int64_t* slot_key(uint32_t s) const { return GA ? mkey + s : mkey + 2 * (int64_t)s; }
+  __device__ float* slot_val(uint32_t s) const {
+    return GA ? mval + s : (float*)(mkey + 2 * (int64_t)s + 1);
   }
   // GA: the memo lives in LDS (one voxel group per wave), so a probe or a
   // store costs an LDS access instead of an L2 round trip.
   __device__ int64_t memo_ld_key(uint32_t s) const {
     if constexpr (GA) return mkey[s];
-    return __hip_atomic_load(mkey + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(slot_key(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // DI: both values of a slot are one 64-bit word (CC low, score high)
   __device__ float2 memo_ld_pair(uint32_t s) const {
-    const uint64_t w = __hip_atomic_load((uint64_t*)mval + s, __ATOMIC_RELAXED,
+    const uint64_t w = __hip_atomic_load((uint64_t*)slot_val(s), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
     return make_float2(__uint_as_float((uint32_t)w), __uint_as_float((uint32_t)(w >> 32)));
   }
@@ -485,14 +655,14 @@ struct Engine {
       const float2 p = memo_ld_pair(s);
       return obj == MRF_OBJ_DIST ? p.y : p.x;
     }
-    return __hip_atomic_load(mval + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(slot_val(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // rewrites a slot's key (its value stays): clears the look-ahead flag
   __device__ void memo_st_key(uint32_t s, int64_t kv) const {
     if constexpr (GA) {
       mkey[s] = kv;
     } else {
-      __hip_atomic_store(mkey + s, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(slot_key(s), kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   __device__ void memo_st(uint32_t s, int64_t kv, float v, float v2 = 0.0f) const {
@@ -502,12 +672,12 @@ struct Engine {
     } else {
       if constexpr (DI) {
         const uint64_t w = (uint64_t)__float_as_uint(v) | ((uint64_t)__float_as_uint(v2) << 32);
-        __hip_atomic_store((uint64_t*)mval + s, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store((uint64_t*)slot_val(s), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         (void)v2;
-        __hip_atomic_store(mval + s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(slot_val(s), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      __hip_atomic_store(mkey + s, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(slot_key(s), kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 
@@ -1028,6 +1198,11 @@ __host__ __device__ inline size_t zoom_group_lds() {
   return MRF_ZOOM_MAX_STARTS * (sizeof(int64_t) + sizeof(float)) + 8 * sizeof(float);
 }
 
+// Offset of the voxel rows (16-byte aligned) after the groups' LDS.
+__host__ __device__ inline size_t zoom_vrow_offset(int ng) {
+  return ((size_t)ng * zoom_group_lds() + 15) & ~(size_t)15;
+}
+
 // The gathering engine's memo: slots per wave, in LDS (a slice voxel visits
 // ~150 entries; past 3/4 of the slots values are no longer kept and n_sim
 // is reported negative, as with the global memo).
@@ -1039,8 +1214,13 @@ __host__ __device__ inline size_t zoom_gather_memo_lds() {
 // One wave per block, 64 / G voxels per wave: each group of G lanes runs its
 // own voxel's stage machine and pulls its own voxels from the queue, so the
 // lanes that a decision leaves idle in one group work for the others.
+// Groups of 8 lanes serve large voxel counts (many waves per SIMD): the
+// kernel is then held to 256 VGPRs so that two waves share a SIMD and hide
+// each other's load latency (measured on a 256 x 256 four-parameter slice:
+// 518 -> 455 ms; at 128 VGPRs the spills cost 4x). Larger groups run one
+// wave per SIMD and keep the whole register file.
 template <int G, bool SM, bool GA, bool DI>
-__global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
+__global__ __launch_bounds__(64, (G <= 8 ? 2 : 1)) void k_zoom(ZoomArgs a) {
   constexpr int NG = 64 / G;
   extern __shared__ __align__(16) unsigned char sm[];
   const int lane = threadIdx.x;
@@ -1062,13 +1242,13 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     memo_cap = kGatherMemo;
     for (int32_t i = lane; i < kGatherMemo; i += 64) mkey[i] = 0;
   } else {
-    mkey = a.memo_keys + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap;
-    // DI: two values per slot, so each group's block of values is twice as long
-    mval = a.memo_vals + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap * (DI ? 2 : 1);
+    // 16-byte slots: two int64 words each (key, then the value words)
+    mkey = a.memo_slots + ((int64_t)blockIdx.x * NG + grp) * a.memo_cap * 2;
+    mval = nullptr;
     memo_cap = a.memo_cap;
     for (int32_t i = lane; i < NG * a.memo_cap; i += 64)
-      __hip_atomic_store(a.memo_keys + (int64_t)blockIdx.x * NG * a.memo_cap + i, (int64_t)0,
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.memo_slots + ((int64_t)blockIdx.x * NG * a.memo_cap + i) * 2,
+                         (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   int64_t serial = 0;
@@ -1125,6 +1305,17 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     const double nv = sqrt(s2);
     const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.0f;
     ++serial;
+    // the scaled voxel in the group's LDS row (the earlier voxel's reads
+    // ended before the fence that closed its iteration)
+    float2* vsh = nullptr;
+    if (a.vrow && a.half) {
+      vsh = (float2*)(sm + zoom_vrow_offset(NG) + (size_t)grp * a.vrow * sizeof(float2));
+      for (int32_t j = glane; j < n; j += G) {
+        const float2 x = src[j];
+        vsh[j] = make_float2(x.x * inv, x.y * inv);
+      }
+      wave_fence();
+    }
 
     Engine<G, SM, GA, DI> e;
     e.pa.t1T = a.t1T;
@@ -1136,6 +1327,12 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     e.pa.tab_n = a.tab_n;
     e.pa.inversion = a.inversion;
     e.pa.x_axis = a.x_axis;
+    e.pa.half = a.half;
+    e.pa.tq = a.tq;
+    e.pa.h1 = a.h1;
+    e.pa.h2 = a.h2;
+    e.pa.hd = a.hd;
+    e.pa.xr = a.xr;
     if constexpr (SM) {
       e.sw = a.sm;
       e.dm = a.demod;
@@ -1145,6 +1342,7 @@ __global__ __launch_bounds__(64) void k_zoom(ZoomArgs a) {
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
     e.vx = src;
+    e.vs = vsh;
     e.vinv = inv;
     e.vn = nv;
     e.obj = MRF_OBJ_CC;
@@ -1311,7 +1509,8 @@ struct ZoomPlan {
   int blocks;
   int group;  // lanes per voxel
   int32_t cap;
-  size_t off_sched, off_keys, off_vals, total;
+  int32_t vrow;  // readouts per LDS voxel row (0: none)
+  size_t off_sched, off_slots, total;
 };
 
 // Lanes per voxel: the smallest group (most voxels per wave) that still
@@ -1327,7 +1526,6 @@ static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_en
   ZoomPlan p;
   // memo slots per voxel group: fine 4-parameter grids make long unit-step walks
   p.cap = grid_entries > ((int64_t)1 << 26) ? 32768 : 4096;
-  (void)n_tr;
   p.group = 64;
   // gathering: whole waves per voxel (each row read 1 KB per instruction)
   for (int g : kZoomGroups)
@@ -1338,17 +1536,25 @@ static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_en
   const int ng = 64 / p.group;
   p.lds = (size_t)ng * zoom_group_lds() + 16;
   if (gather) p.lds = ((p.lds + 7) & ~(size_t)7) + zoom_gather_memo_lds();
+  // groups of 16 lanes and more (one wave per SIMD, four per CU) keep their
+  // voxel in LDS when four waves' rows fit a CU's 160 KB
+  p.vrow = 0;
+  if (!gather && p.group >= 16 && n_tr > 0) {
+    const int32_t vr = (n_tr + 3) / 4 * 4;
+    const size_t with = zoom_vrow_offset(ng) + (size_t)ng * vr * sizeof(float2) + 16;
+    if (4 * with <= 160 * 1024) {
+      p.vrow = vr;
+      p.lds = with;
+    }
+  }
   const int per_cu = std::max(1, std::min(16, (int)((160 * 1024) / p.lds)));
   const int64_t waves_needed = ((int64_t)n_vox + ng - 1) / ng;
   p.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(waves_needed, (int64_t)n_cu * per_cu));
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t slots = (size_t)p.blocks * ng * p.cap;
   p.off_sched = 256;
-  p.off_keys = al(p.off_sched + sizeof(mrf_zoom_schedule));
-  p.off_vals = al(p.off_keys + sizeof(int64_t) * slots);
-  // values: one float per slot, or two (CC, distance score) for schedules
-  // with distance stages
-  p.total = al(p.off_vals + 2 * sizeof(float) * slots);
+  p.off_slots = al(p.off_sched + sizeof(mrf_zoom_schedule));
+  p.total = al(p.off_slots + 16 * slots);
   return p;
 }
 
@@ -1620,6 +1826,16 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.vox_n_tr = vox_n_tr;
   a.inversion = t->inversion;
   a.x_axis = t->x_axis_pulses;
+  a.tq = t->tq;
+  a.h1 = t->h1;
+  a.h2 = t->h2;
+  a.hd = t->hd;
+  a.xr = t->xr;
+  a.vrow = plan.vrow;
+  a.half = (!dict && !t->smooth && t->h1 && t->h2 && t->hd && t->xr &&
+            (uintptr_t)vox % 16 == 0 && ld_vox % 2 == 0)
+               ? 1
+               : 0;
   a.sm = smooth_weights(t->smooth ? t->smooth : 3, n_tr);
   a.demod = t->demod;
   a.dict = dict ? (const float4*)dict->re : nullptr;
@@ -1644,8 +1860,7 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   char* ws = (char*)workspace;
   a.counter = (int32_t*)ws;
   a.memo_cap = plan.cap;
-  a.memo_keys = (int64_t*)(ws + plan.off_keys);
-  a.memo_vals = (float*)(ws + plan.off_vals);
+  a.memo_slots = (int64_t*)(ws + plan.off_slots);
   mrf_zoom_schedule* dsch = (mrf_zoom_schedule*)(ws + plan.off_sched);
   a.sch = dsch;
   const int blocks = plan.blocks;
