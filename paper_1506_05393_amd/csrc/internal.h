@@ -68,9 +68,10 @@ struct Tables {
   float* h1 = nullptr;   // [n1][tq]  1-E1 over TE
   float* h2 = nullptr;   // [n2][tq]  1-E2 over TE
   float2* hd = nullptr;  // [n3][tq]  (cos-1, sin) over TE
-  // x-axis pulses (x_axis_pulses): (R11, R12, R21, R22) per readout, the
-  // only entries of the rotation that are not exact 0 or 1; NULL otherwise
-  float4* xr = nullptr;  // [n4][tq]
+  // x-axis pulses (x_axis_pulses): a rotation about x, whose only entries
+  // that are not exact 0 or 1 are R11 = R22 and R12 = -R21 (pulse_matrix
+  // rounds them so); (R11, R12) per readout, NULL otherwise
+  float2* xr = nullptr;  // [n4][tq]
   void* block = nullptr;  // one allocation holding all of the above
 };
 // A held reference to built tables (see get_tables).

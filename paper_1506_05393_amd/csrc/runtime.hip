@@ -98,7 +98,7 @@ struct K0Args {
   float* h1;
   float* h2;
   float2* hd;
-  float4* xr;
+  float2* xr;
 };
 
 __global__ void k_step_tables(K0Args a) {
@@ -150,7 +150,7 @@ __global__ void k_step_tables(K0Args a) {
       int b = (int)(u / a.n_tr), j = (int)(u % a.n_tr);
       float* R = a.rf + ((int64_t)b * a.n_tr + j) * 9;
       pulse_matrix(a.fa[j], a.ph[j], a.ax4[b], R);
-      if (a.xr) a.xr[(int64_t)b * a.tq + j] = make_float4(R[4], R[5], R[7], R[8]);
+      if (a.xr) a.xr[(int64_t)b * a.tq + j] = make_float2(R[4], R[5]);
     }
   }
 }
@@ -222,7 +222,7 @@ static int build_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, uint
   size_t o_h2 = align256(o_h1 + (t.symmetric ? sizeof(float) * tq * t.n1 : 0));
   size_t o_hd = align256(o_h2 + (t.symmetric ? sizeof(float) * tq * t.n2 : 0));
   size_t o_xr = align256(o_hd + (t.symmetric ? sizeof(float2) * tq * t.n3 : 0));
-  size_t o_in = align256(o_xr + (t.x_axis_pulses ? sizeof(float4) * tq * t.n4 : 0));
+  size_t o_in = align256(o_xr + (t.x_axis_pulses ? sizeof(float2) * tq * t.n4 : 0));
   // staged FP64 inputs: ta, tb, fa, ph, ax1..ax4
   const size_t n_in = 4 * nt + t.n1 + t.n2 + t.n3 + t.n4;
   size_t total = o_in + sizeof(double) * n_in;
@@ -244,7 +244,7 @@ static int build_tables(mrf_sequence* seq, const mrf_grid* g, int32_t n_tr, uint
     t.h2 = (float*)(base + o_h2);
     t.hd = (float2*)(base + o_hd);
   }
-  if (t.x_axis_pulses) t.xr = (float4*)(base + o_xr);
+  if (t.x_axis_pulses) t.xr = (float2*)(base + o_xr);
   std::vector<double> in(n_in);
   double* p = in.data();
   for (int32_t j = 0; j < n_tr; ++j) {

@@ -39,10 +39,14 @@ struct ZoomArgs {
   const float* h1;
   const float* h2;
   const float2* hd;
-  const float4* xr;
+  const float2* xr;
   // readouts per LDS row holding a group's voxel scaled to unit norm (read
   // by the compact-table path), 0 = the voxel is read from global memory
   int32_t vrow;
+  // otherwise (vrow == 0, compact-table path) the same scaled voxel in a
+  // per-group row of vrow_g readouts in the workspace
+  int32_t vrow_g;
+  float2* vscaled;
   int32_t dims[4];
   const float2* vox;
   int64_t ld_vox;
@@ -144,7 +148,7 @@ struct EngineParams {
   const float* h1;
   const float* h2;
   const float2* hd;
-  const float4* xr;
+  const float2* xr;
   int32_t dims[4];
 };
 
@@ -171,6 +175,7 @@ struct Engine {
   int32_t n_nxt;
   const float2* vx;  // the voxel's fingerprint (global memory, read-only)
   const float2* vs;  // vx * vinv in LDS (same FP32 products), or NULL
+  bool vx_scaled;    // vx already holds those products (a workspace row)
   float vinv;        // 1 / ||v||: the unit-norm voxel is vx * vinv
   double vn;         // ||v|| (FP64)
   int64_t* mkey;     // this group's memo: 16-byte slots (global memory), or
@@ -403,7 +408,9 @@ struct Engine {
   // arithmetic is that of simulate_cc_t, operation for operation, so the
   // values are the same. The loads run kAq quads (four readouts) ahead.
   static constexpr int kAq = 4;
-  template <bool LANE_R, bool COMP, bool VS>
+  // VM: where the voxel comes from: 0 vx (scaled here), 1 vx holding the
+  // scaled products (workspace row), 2 the LDS copy vs
+  template <bool LANE_R, bool COMP, int VM>
   __device__ float simulate_half(const int32_t* i, float* pdr, float* pdi, double* pn2,
                                  float* psc) const {
     typedef float v2 __attribute__((ext_vector_type(2)));
@@ -414,6 +421,7 @@ struct Engine {
     typedef const __attribute__((address_space(4))) v4 cf4;
     typedef const __attribute__((address_space(3))) v4 lf4;
     typedef const __attribute__((address_space(3))) v2 lf2;
+    constexpr bool VS = VM == 2, SCALED = VM != 0;
     const int32_t n = pa.n_tr, tq = pa.tq;
     gf1* p1 = (gf1*)(pa.h1 + (int64_t)i[0] * tq);
     gf1* p2 = (gf1*)(pa.h2 + (int64_t)i[1] * tq);
@@ -422,22 +430,25 @@ struct Engine {
     gf4* q2 = (gf4*)p2;
     gf4* qd = (gf4*)pd;
     gf4* qv = (gf4*)vx;
+    // pulses: (R11, R12) per readout, R21 = -R12 and R22 = R11
     gf4* rl = (gf4*)(pa.xr + (LANE_R ? (int64_t)i[3] * tq : 0));
     cf4* ru = (cf4*)pa.xr;
-    auto pulse = [&](int32_t j) -> v4 { return LANE_R ? rl[j] : ru[j]; };
+    gf2* r1l = (gf2*)(pa.xr + (LANE_R ? (int64_t)i[3] * tq : 0));
     Spin m = initial_spin(pa.inversion, pa.t1ti[i[0]]);
     float dr = 0.0f, di = 0.0f, cr = 0.0f, ci = 0.0f;
     double n2 = 0.0;
-    auto step = [&](float r1, float r2, float cm1, float sn, float vxr, float vxi, v4 R) {
+    auto step = [&](float r1, float r2, float cm1, float sn, float vxr, float vxi, float c,
+                    float sp) {
       {
+        // the x-axis rotation (as simulate_cc_t: R21 y is -(R12 y) exactly)
         const float y = m.y, z = m.z;
-        m.y = fmaf(R.y, z, R.x * y);
-        m.z = fmaf(R.w, z, R.z * y);
+        m.y = fmaf(sp, z, c * y);
+        m.z = fmaf(c, z, -sp * y);
       }
       free_evolve(m, cm1, sn, r2, r1);
       const float sx = m.x, sy = m.y;
-      // VS: the LDS copy already holds these products
-      const float vr = VS ? vxr : vxr * vinv, vi = VS ? vxi : vxi * vinv;
+      // the LDS or workspace copy already holds these products
+      const float vr = SCALED ? vxr : vxr * vinv, vi = SCALED ? vxi : vxi * vinv;
       if constexpr (COMP) {
         dot2_acc(vr, sx, dr, cr);
         dot2_acc(vi, sy, dr, cr);
@@ -454,7 +465,7 @@ struct Engine {
     // one quad: readouts 4k .. 4k + 3
     struct Quad {
       v4 a, b, d0, d1, v0, v1;
-      v4 r[LANE_R ? 4 : 1];
+      v4 r[LANE_R ? 2 : 1];
     };
     auto load = [&](int32_t k, Quad& u) {
       u.a = q1[k];
@@ -469,22 +480,20 @@ struct Engine {
         u.v1 = qv[2 * k + 1];
       }
       if constexpr (LANE_R) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) u.r[t] = rl[4 * k + t];
+        u.r[0] = rl[2 * k];
+        u.r[1] = rl[2 * k + 1];
       }
     };
     auto run = [&](int32_t k, const Quad& u) {
       // k is the same on every lane that runs the loop: the pulses are
       // scalar loads
       const int32_t ks = __builtin_amdgcn_readfirstlane(k);
-      const v4 R0 = LANE_R ? u.r[0] : ru[4 * ks];
-      const v4 R1 = LANE_R ? u.r[1] : ru[4 * ks + 1];
-      const v4 R2 = LANE_R ? u.r[2] : ru[4 * ks + 2];
-      const v4 R3 = LANE_R ? u.r[3] : ru[4 * ks + 3];
-      step(u.a.x, u.b.x, u.d0.x, u.d0.y, u.v0.x, u.v0.y, R0);
-      step(u.a.y, u.b.y, u.d0.z, u.d0.w, u.v0.z, u.v0.w, R1);
-      step(u.a.z, u.b.z, u.d1.x, u.d1.y, u.v1.x, u.v1.y, R2);
-      step(u.a.w, u.b.w, u.d1.z, u.d1.w, u.v1.z, u.v1.w, R3);
+      const v4 P0 = LANE_R ? u.r[0] : ru[2 * ks];
+      const v4 P1 = LANE_R ? u.r[1] : ru[2 * ks + 1];
+      step(u.a.x, u.b.x, u.d0.x, u.d0.y, u.v0.x, u.v0.y, P0.x, P0.y);
+      step(u.a.y, u.b.y, u.d0.z, u.d0.w, u.v0.z, u.v0.w, P0.z, P0.w);
+      step(u.a.z, u.b.z, u.d1.x, u.d1.y, u.v1.x, u.v1.y, P1.x, P1.y);
+      step(u.a.w, u.b.w, u.d1.z, u.d1.w, u.v1.z, u.v1.w, P1.z, P1.w);
     };
     const int32_t nq = n >> 2;
     int32_t k = 0;
@@ -518,7 +527,8 @@ struct Engine {
       } else {
         v = vv[j];
       }
-      step(p1[j], p2[j], c.x, c.y, v.x, v.y, pulse(j));
+      const v2 P = r1l[j];
+      step(p1[j], p2[j], c.x, c.y, v.x, v.y, P.x, P.y);
     }
     return finish<COMP>(dr, di, cr, ci, n2, pdr, pdi, pn2, psc);
   }
@@ -610,11 +620,14 @@ struct Engine {
       if (pa.half) {
         if constexpr (G >= 16) {
           if (vs)
-            return pa.dims[3] > 1 ? simulate_half<true, DI, true>(i, pdr, pdi, pn2, psc)
-                                  : simulate_half<false, DI, true>(i, pdr, pdi, pn2, psc);
+            return pa.dims[3] > 1 ? simulate_half<true, DI, 2>(i, pdr, pdi, pn2, psc)
+                                  : simulate_half<false, DI, 2>(i, pdr, pdi, pn2, psc);
         }
-        return pa.dims[3] > 1 ? simulate_half<true, DI, false>(i, pdr, pdi, pn2, psc)
-                              : simulate_half<false, DI, false>(i, pdr, pdi, pn2, psc);
+        if (vx_scaled)
+          return pa.dims[3] > 1 ? simulate_half<true, DI, 1>(i, pdr, pdi, pn2, psc)
+                                : simulate_half<false, DI, 1>(i, pdr, pdi, pn2, psc);
+        return pa.dims[3] > 1 ? simulate_half<true, DI, 0>(i, pdr, pdi, pn2, psc)
+                              : simulate_half<false, DI, 0>(i, pdr, pdi, pn2, psc);
       }
     }
     if (pa.dims[3] > 1)
@@ -1307,12 +1320,19 @@ __global__ __launch_bounds__(64, (G <= 8 ? 2 : 1)) void k_zoom(ZoomArgs a) {
     ++serial;
     // the scaled voxel in the group's LDS row (the earlier voxel's reads
     // ended before the fence that closed its iteration)
+    // (or in its workspace row: the group's lanes share the CU's L1, so the
+    // workgroup fence makes the row visible to them)
     float2* vsh = nullptr;
-    if (a.vrow && a.half) {
+    float2* vgl = nullptr;
+    if (a.half && a.vrow) {
       vsh = (float2*)(sm + zoom_vrow_offset(NG) + (size_t)grp * a.vrow * sizeof(float2));
+    } else if (a.half && a.vscaled) {
+      vgl = a.vscaled + ((int64_t)blockIdx.x * NG + grp) * a.vrow_g;
+    }
+    if (float2* dst = vsh ? vsh : vgl) {
       for (int32_t j = glane; j < n; j += G) {
         const float2 x = src[j];
-        vsh[j] = make_float2(x.x * inv, x.y * inv);
+        dst[j] = make_float2(x.x * inv, x.y * inv);
       }
       wave_fence();
     }
@@ -1341,8 +1361,9 @@ __global__ __launch_bounds__(64, (G <= 8 ? 2 : 1)) void k_zoom(ZoomArgs a) {
     e.pa.memo_cap = memo_cap;
     for (int q = 0; q < 4; ++q) e.pa.dims[q] = a.dims[q];
 
-    e.vx = src;
+    e.vx = vgl ? vgl : src;
     e.vs = vsh;
+    e.vx_scaled = vgl != nullptr;
     e.vinv = inv;
     e.vn = nv;
     e.obj = MRF_OBJ_CC;
@@ -1509,8 +1530,9 @@ struct ZoomPlan {
   int blocks;
   int group;  // lanes per voxel
   int32_t cap;
-  int32_t vrow;  // readouts per LDS voxel row (0: none)
-  size_t off_sched, off_slots, total;
+  int32_t vrow;    // readouts per LDS voxel row (0: none)
+  int32_t vrow_g;  // readouts per workspace voxel row (0: none)
+  size_t off_sched, off_slots, off_vrow, total;
 };
 
 // Lanes per voxel: the smallest group (most voxels per wave) that still
@@ -1547,14 +1569,20 @@ static ZoomPlan zoom_plan(int n_cu, int32_t n_vox, int32_t n_tr, int64_t grid_en
       p.lds = with;
     }
   }
-  const int per_cu = std::max(1, std::min(16, (int)((160 * 1024) / p.lds)));
+  // persistent blocks: no more than can be resident (one wave per SIMD, two
+  // for 8-lane groups), since a block that starts late finds the queue empty
+  const int resident = gather ? 16 : (p.group <= 8 ? 8 : 4);
+  const int per_cu = std::max(1, std::min(resident, (int)((160 * 1024) / p.lds)));
   const int64_t waves_needed = ((int64_t)n_vox + ng - 1) / ng;
   p.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(waves_needed, (int64_t)n_cu * per_cu));
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t slots = (size_t)p.blocks * ng * p.cap;
   p.off_sched = 256;
   p.off_slots = al(p.off_sched + sizeof(mrf_zoom_schedule));
-  p.total = al(p.off_slots + 16 * slots);
+  // scaled voxel rows in the workspace when they are not in LDS
+  p.vrow_g = (!gather && p.vrow == 0 && n_tr > 0) ? (n_tr + 3) / 4 * 4 : 0;
+  p.off_vrow = al(p.off_slots + 16 * slots);
+  p.total = al(p.off_vrow + sizeof(float2) * (size_t)p.blocks * ng * p.vrow_g);
   return p;
 }
 
@@ -1832,6 +1860,8 @@ static int zoom_search(mrf_context* ctx, const mrf_sequence* seq, const mrf_grid
   a.hd = t->hd;
   a.xr = t->xr;
   a.vrow = plan.vrow;
+  a.vrow_g = plan.vrow_g;
+  a.vscaled = plan.vrow_g ? (float2*)((char*)workspace + plan.off_vrow) : nullptr;
   a.half = (!dict && !t->smooth && t->h1 && t->h2 && t->hd && t->xr &&
             (uintptr_t)vox % 16 == 0 && ld_vox % 2 == 0)
                ? 1
