@@ -695,49 +695,82 @@ struct Engine {
   }
 
   // Wave-level evaluation: every lane with `valid` asks for the value at i.
-  // A lane with `spec` (look-ahead) is evaluated only when a lane of its
-  // group without it needs a simulation in the same call, and not when a
-  // lane asks for the same entry; its value is for the memo only.
-  __device__ float eval(bool valid, const int32_t* i, bool spec = false) {
+  // When the group simulates in this call, every lane of it that asks for
+  // nothing new (no point, or a memo hit) takes a look-ahead point instead:
+  // the free lane of rank r (counted from the group's lane 0) takes
+  // more(r, q) when that returns true. Look-ahead entries go to the memo
+  // only (never twice for one entry); each lane returns its own point's value.
+  struct NoMore {
+    __device__ bool operator()(int, int32_t*) const { return false; }
+  };
+  __device__ float eval(bool valid, const int32_t* i) { return eval(valid, i, NoMore()); }
+  template <class More>
+  __device__ float eval(bool valid, const int32_t* i, More&& more) {
     float val = -INFINITY;
-    float cc_v = -INFINITY, sc_v = -INFINITY;  // DI: both values of a new entry
-    bool need = false;
+    float nv = 0.0f, nv2 = 0.0f;  // a simulated entry's value(s), for the memo
+    bool need = false, spec = false;
     bool first_read = false;  // a decision's first read of a look-ahead entry
     int64_t k = -1;
+    int32_t pt[4] = {0, 0, 0, 0};
     const int32_t cap = pa.memo_cap;
-    if (valid && in_range(i)) {
-      k = key(i);
-      const int64_t tagged = tag | k;
-      uint32_t s = memo_home(k);
-      need = true;
-      for (int32_t probe = 0; probe < cap; ++probe) {
+    // probe the memo for k: the slot of a hit, -1 on a miss
+    auto probe = [&](int64_t kk, int64_t& mk_out) -> int32_t {
+      const int64_t tagged = tag | kk;
+      uint32_t s = memo_home(kk);
+      for (int32_t n = 0; n < cap; ++n) {
         const int64_t mk = memo_ld_key(s);
         if ((mk & ~kSpecBit) == tagged) {
-          val = memo_ld_val(s);
-          need = false;
-          if (kLookAhead && (mk & kSpecBit) && !spec) {
-            first_read = true;
-            memo_st_key(s, tagged);
-          }
-          break;
+          mk_out = mk;
+          return (int32_t)s;
         }
         if ((mk & ~kIndexMask) != tag) break;  // empty for this voxel
         s = (s + 1) & (cap - 1);
       }
+      return -1;
+    };
+    if (valid && in_range(i)) {
+      k = key(i);
+      for (int q = 0; q < 4; ++q) pt[q] = i[q];
+      int64_t mk = 0;
+      const int32_t s = probe(k, mk);
+      need = s < 0;
+      if (!need) {
+        val = memo_ld_val((uint32_t)s);
+        if (kLookAhead && (mk & kSpecBit)) {
+          first_read = true;
+          memo_st_key((uint32_t)s, tag | k);
+        }
+      }
     }
     uint64_t mspec = 0;
     if constexpr (kLookAhead) {
-      // look-ahead lanes ride along only with a needed simulation, and
-      // never twice for one entry
-      const bool real = grp_ballot<G>(need && !spec, gbase) != 0;
-      bool drop = spec && need && !real;
-      for (int o = 0; o < G; ++o) {
-        const int64_t ko = __shfl(k, o, G);
-        const int no = __shfl((int)need | ((int)spec << 1), o, G);
-        if (spec && (no & 1) && ko == k && o != lane && (!(no & 2) || o < lane)) drop = true;
+      if (grp_ballot<G>(need, gbase) != 0) {
+        const uint64_t fm = grp_ballot<G>(!need, gbase);
+        if (!need) {
+          const int r = __popcll(fm & ((1ull << lane) - 1));
+          int32_t q[4];
+          if (more(r, q) && in_range(q)) {
+            const int64_t kq = key(q);
+            int64_t mk = 0;
+            if (probe(kq, mk) < 0) {
+              need = true;
+              spec = true;
+              k = kq;
+              for (int a = 0; a < 4; ++a) pt[a] = q[a];
+            }
+          }
+        }
+        // one evaluation per entry: a look-ahead lane gives way to a lane
+        // that asks for the same entry, and to a lower look-ahead lane
+        bool drop = false;
+        for (int o = 0; o < G; ++o) {
+          const int64_t ko = __shfl(k, o, G);
+          const int no = __shfl((int)need | ((int)spec << 1), o, G);
+          if (spec && (no & 1) && ko == k && o != lane && (!(no & 2) || o < lane)) drop = true;
+        }
+        if (drop) need = spec = false;
+        mspec = grp_ballot<G>(need && spec, gbase);
       }
-      if (drop) need = false;
-      mspec = grp_ballot<G>(need && spec, gbase);
     }
     if constexpr (GA) {
       // the group reads the needed entries together, kGather at a time
@@ -761,15 +794,18 @@ struct Engine {
         gather_cc(ks, cnt, cv);
 #pragma unroll
         for (int e = 0; e < kGather; ++e)
-          if (lane == srcs[e]) val = cv[e];
+          if (lane == srcs[e]) val = nv = cv[e];
       }
     } else {
       if (need) {
         if constexpr (DI) {
-          cc_v = simulate_cc(i, nullptr, nullptr, nullptr, &sc_v);
-          val = obj == MRF_OBJ_DIST ? sc_v : cc_v;
+          float sc = 0.0f;
+          nv = simulate_cc(pt, nullptr, nullptr, nullptr, &sc);
+          nv2 = sc;
+          if (!spec) val = obj == MRF_OBJ_DIST ? sc : nv;
         } else {
-          val = simulate_cc(i);
+          nv = simulate_cc(pt);
+          if (!spec) val = nv;
         }
       }
     }
@@ -780,8 +816,8 @@ struct Engine {
       m &= m - 1;
       const bool sp = (mspec >> src) & 1;
       const int64_t ks = __shfl(k, src, G);
-      const float vv = __shfl(DI ? cc_v : val, src, G);
-      const float v2 = DI ? __shfl(sc_v, src, G) : 0.0f;
+      const float vv = __shfl(nv, src, G);
+      const float v2 = DI ? __shfl(nv2, src, G) : 0.0f;
       // look-ahead entries keep to half the slots, so the entries that
       // decisions ask for still find room
       if (memo_count * 4 < cap * 3 && (!sp || memo_count * 2 < cap)) {
@@ -1017,18 +1053,18 @@ struct Engine {
       int32_t L[4] = {c[0], c[1], c[2], c[3]}, R[4] = {c[0], c[1], c[2], c[3]};
       L[ax] -= s;
       R[ax] += s;
-      // lane 0 asks for R (pruned) or L, lane 1 for R; the others look ahead
-      int32_t P[4];
-      bool sp = false;
-      if (kLookAhead && lane >= 2) {
-        zoom1_ahead(lane - 2, ax, s, dir, P);
-        sp = true;
-      } else {
-        for (int a = 0; a < 4; ++a) P[a] = (lane == 0) != pruned ? L[a] : R[a];
-        sp = kLookAhead && pruned && lane == 1;
-      }
       if (pruned) {
-        const float vr = __shfl(eval(lane == 0 || sp, P, sp), 0, G);
+        // R first; L is the first look-ahead point
+        const float vr = __shfl(eval(lane == 0, R,
+                                     [&](int r, int32_t* q) {
+                                       if (r == 0) {
+                                         for (int a = 0; a < 4; ++a) q[a] = L[a];
+                                       } else {
+                                         zoom1_ahead(r - 1, ax, s, dir, q);
+                                       }
+                                       return true;
+                                     }),
+                                0, G);
         log_pair(vr, cval);
         if (vr > cval) {
           move_to(R, vr);
@@ -1044,7 +1080,12 @@ struct Engine {
         }
         break;
       }
-      const float v = eval(lane < 2 || sp, P, sp);
+      int32_t P[4];
+      for (int a = 0; a < 4; ++a) P[a] = lane == 0 ? L[a] : R[a];
+      const float v = eval(lane < 2, P, [&](int r, int32_t* q) {
+        zoom1_ahead(r, ax, s, dir, q);
+        return true;
+      });
       log_top2(lane < 2 ? v : -INFINITY, true);
       const float vl = __shfl(v, 0, G), vr = __shfl(v, 1, G);
       const bool right = vr > vl;
@@ -1066,15 +1107,23 @@ struct Engine {
   }
 
   // evaluate the neighbours in `mask` (bit w = neighbour w), one per lane;
-  // the move's other neighbours and lanes 8 and up look ahead (d: the last
-  // move's direction, -1 before any)
+  // the look-ahead takes the move's other neighbours first, then the
+  // points of zoom2_ahead (d: the last move's direction, -1 before any)
   __device__ void eval_nb(uint32_t mask, int a0, int a1, int s0, int s1, int d) {
     int32_t p[4];
     neighbour(lane & 7, a0, a1, s0, s1, p);
     const bool mine = lane < 8 && ((mask >> lane) & 1u);
-    bool sp = false;
-    if (kLookAhead) sp = lane < 8 ? !mine : zoom2_ahead(lane - 8, a0, a1, s0, s1, d, p);
-    const float v = eval(mine || sp, p, sp);
+    const float v = eval(mine, p, [&](int r, int32_t* q) {
+      for (int w = 0; w < 8; ++w) {
+        if ((mask >> w) & 1u) continue;
+        if (r == 0) {
+          neighbour(w, a0, a1, s0, s1, q);
+          return true;
+        }
+        --r;
+      }
+      return zoom2_ahead(r, a0, a1, s0, s1, d, q);
+    });
     if (mine) nbv[lane] = v;
     wave_fence();
   }
@@ -1089,9 +1138,9 @@ struct Engine {
       if (!pruned) {
         int32_t p[4];
         neighbour(lane & 7, a0, a1, s0, s1, p);
-        bool sp = false;
-        if (kLookAhead && lane >= 8) sp = zoom2_ahead(lane - 8, a0, a1, s0, s1, d, p);
-        const float v = eval(lane < 8 || sp, p, sp);
+        const float v = eval(lane < 8, p, [&](int r, int32_t* q) {
+          return zoom2_ahead(r, a0, a1, s0, s1, d, q);
+        });
         log_top2(lane < 8 ? v : -INFINITY, true);
         float bv;
         const int src = grp_first_max<G>(lane < 8 ? v : -INFINITY, bv, gbase);
