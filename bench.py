@@ -16,6 +16,11 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# multi-start ZOOM lattice (T1 starts, T2 starts, outer rounds): the cheapest
+# one found to agree with brute force on every pinned voxel of both small
+# workloads (searched with the oracle over 1x4 ... 4x4; 4x4 costs twice the
+# entries for the same agreement)
+MULTISTART = (2, 3, 8)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -432,7 +437,7 @@ def _agreement(idx, ref_idx, pinned):
 def oracle_agreement(api, ctx, torch, threads: int):
     """The small workload (16x16 phantom, N = 200, 50,400 entries; on-grid and
     off-grid truths) with fingerprints synthesised by the oracle: the FP64
-    oracle's brute force and ZOOM (paper schedule and the 4 x 4 multi-start
+    oracle's brute force and ZOOM (paper schedule and the 2 x 3 multi-start
     schedule), timed on all host threads and on one, against the library's
     FP32 brute force, BF16 + re-scoring, and both ZOOM schedules on the same
     fingerprints. Agreement on pinned voxels (oracle margin > 1e-5) and on
@@ -448,7 +453,7 @@ def oracle_agreement(api, ctx, torch, threads: int):
                           for v in range(ph.n_vox)])
         V = I.compose_fingerprints(clean, ph).astype(np.complex64)
         s_paper = oracle.schedule_paper(w.seq, w.grid)
-        s_multi = oracle.schedule_multistart(w.seq, w.grid, 4, 4, 8)
+        s_multi = oracle.schedule_multistart(w.seq, w.grid, *MULTISTART)
         t = time.perf_counter()
         bf = oracle.bruteforce(w.seq, w.grid, V, top_k=2, threads=threads)
         t_bf = time.perf_counter() - t
@@ -473,19 +478,19 @@ def oracle_agreement(api, ctx, torch, threads: int):
         gpu = {"fp32": api.match_bruteforce(ctx, d32, Vd, top_k=2),
                "bf16_rescore": api.match_bruteforce(ctx, d16, Vd, top_k=8, seq=sq, grid=w.grid),
                "zoom_paper": api.zoom_search(ctx, sq, w.grid, Vd, sched=s_paper),
-               "zoom_multistart_4x4": api.zoom_search(ctx, sq, w.grid, Vd, sched=s_multi)}
+               "zoom_multistart_2x3": api.zoom_search(ctx, sq, w.grid, Vd, sched=s_multi)}
         torch.cuda.synchronize()
         pin_bf = bf["margin"] > 1e-5
         res = {"oracle_seconds": {"bruteforce": t_bf, "zoom_paper": t_zp,
-                                  "zoom_multistart_4x4": t_zm, "threads": threads,
+                                  "zoom_multistart_2x3": t_zm, "threads": threads,
                                   "bruteforce_one_core": t_bf1,
-                                  "zoom_multistart_4x4_one_core": t_zm1,
+                                  "zoom_multistart_2x3_one_core": t_zm1,
                                   "one_core_sample": f"every 16th voxel ({len(sub)}), scaled"},
                "oracle_zoom_vs_bruteforce": {
                    "paper": _agreement(zp["idx"], bf["idx"], pin_bf),
-                   "multistart_4x4": _agreement(zm["idx"], bf["idx"], pin_bf),
+                   "multistart_2x3": _agreement(zm["idx"], bf["idx"], pin_bf),
                    "n_sim_mean": {"paper": float(zp["n_sim"].mean()),
-                                  "multistart_4x4": float(zm["n_sim"].mean())}}}
+                                  "multistart_2x3": float(zm["n_sim"].mean())}}}
         for name, r in gpu.items():
             idx = r["idx"].cpu().numpy()
             cc = r["cc"].cpu().numpy().astype(np.float64)
@@ -829,14 +834,12 @@ def main():
     def step(record):
         marks = [("t0", ev())]
         marks[-1][1].record()
-        api.simulate_dictionary(ctx, sq, ga, dtype="f32", out=d32)
-        marks.append(("dict_f32", ev()))
+        # the FP32 planar and the BF16 dictionary from one simulation pass
+        api.simulate_dictionary_pair(ctx, sq, ga, out=(d32, d16))
+        marks.append(("dict_pair", ev()))
         marks[-1][1].record()
         api.match_bruteforce(ctx, d32, vox, top_k=2, workspace=ws, out=out32)
         marks.append(("match_f32", ev()))
-        marks[-1][1].record()
-        api.simulate_dictionary(ctx, sq, ga, dtype="bf16", out=d16)
-        marks.append(("dict_bf16", ev()))
         marks[-1][1].record()
         api.match_bruteforce(ctx, d16, vox, top_k=8, seq=sq, grid=ga, workspace=ws, out=out16)
         marks.append(("match_bf16_rescore", ev()))
@@ -884,8 +887,8 @@ def main():
     torch.cuda.synchronize()
     zl = [a_.elapsed_time(b_) for a_, b_ in zl]
     nsim = outz["n_sim"].cpu().numpy()
-    # the 4 x 4 multi-start schedule on the same slice
-    sched_ms = api.schedule_multistart(ctx, sq, ga, 4, 4, 8)
+    # the multi-start schedule on the same slice
+    sched_ms = api.schedule_multistart(ctx, sq, ga, *MULTISTART)
     outzm = api._result_tensors(n_vox, ctx.device, with_nsim=True)
     zm = []
     for _ in range(10):
@@ -914,7 +917,18 @@ def main():
     gemm_ms, gemm_n = ctx.profile_read("k_match_f32")
     sim_ms, sim_n = ctx.profile_read("k_sim_dict")
     gemm_avg = gemm_ms / max(gemm_n, 1)
-    sim_avg = float(np.median(per_row["dict_f32"]))  # k_sim_dict runs for FP32 and BF16
+    sim_avg = float(np.median(per_row["dict_pair"]))
+    # each dictionary alone, for comparison (outside the timed steps)
+    sep = {"f32": [], "bf16": []}
+    for _ in range(3):
+        for dt, d in (("f32", d32), ("bf16", d16)):
+            a_, b_ = ev(), ev()
+            a_.record()
+            api.simulate_dictionary(ctx, sq, ga, dtype=dt, out=d)
+            b_.record()
+            torch.cuda.synchronize()
+            sep[dt].append(a_.elapsed_time(b_))
+    sep = {k: float(np.median(v)) for k, v in sep.items()}
     b16_ms, b16_n = ctx.profile_read("k_match_bf16")
     rs_ms, rs_n = ctx.profile_read("k_rescore")
     b16_avg = b16_ms / max(b16_n, 1)
@@ -925,7 +939,7 @@ def main():
     rf16 = ref16["idx"].cpu().numpy()
     flops = 8.0 * n_vox * N * E
     achieved = flops / (gemm_avg * 1e-3) / 1e12
-    dict_bytes = E * N * 8 + E * 8
+    dict_bytes = E * N * 8 + E * N * 4 + 2 * E * 8  # FP32 planes, BF16 blocks, two norms
     ms_per_step = wall * 1e3 / args.steps
     res = {
         "metric": "voxels/s at 64x64 N=1000: brute vs ZOOM, FP32 vs BF16; p99 slice latency",
@@ -941,8 +955,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "voxels": n_vox, "n_tr": N, "entries": E,
-                   "step": "dictionary generation FP32 + brute-force FP32 + dictionary generation "
-                           "BF16 + brute-force BF16 with top-8 FP32 re-scoring + MRF-ZOOM"},
+                   "step": "dictionary generation (FP32 and BF16, one pass) + brute-force FP32 "
+                           "+ brute-force BF16 with top-8 FP32 re-scoring + MRF-ZOOM + local "
+                           "refinement of both brute-force results"},
         "roofline": {"bound": "mfma", "kernel": "k_match_f32_3m", "achieved": achieved,
                      "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp32_mfma_tflops"],
@@ -980,18 +995,20 @@ def main():
                     "index_agreement_f32_bf16": float(np.mean(rf32 == rf16)),
                     "index_agreement_zoom_vs_f32": float(np.mean(idxz == rf32)),
                     "n_sim_mean_bf16": float(ref16["n_sim"].double().mean().item())},
-        "dict_gen": {"kernel": "k_sim_dict", "f32_ms": sim_avg,
-                     "f32_GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
-                     "f32_frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"],
-                     "f32_frac_write_measured": (dict_bytes / (sim_avg * 1e-3) / 1e9 /
-                                                 peaks["write_GB_per_s"] if peaks else None),
-                     "f32_traffic": counted_traffic("mrf::k_sim_dict<1, 1, true, false>", "sim.hip"),
-                     "bf16_ms": float(np.median(per_row["dict_bf16"])),
-                     "bf16_GB_per_s": (E * N * 4 + E * 8) /
-                                      (float(np.median(per_row["dict_bf16"])) * 1e-3) / 1e9},
+        "dict_gen": {"kernel": "k_sim_dict (FP32 planes and BF16 blocks from one recursion pass)",
+                     "ms": sim_avg, "bytes": dict_bytes,
+                     "GB_per_s": dict_bytes / (sim_avg * 1e-3) / 1e9,
+                     "frac_hbm": dict_bytes / (sim_avg * 1e-3) / 1e9 / PEAK["hbm_gbps"],
+                     "frac_write_measured": (dict_bytes / (sim_avg * 1e-3) / 1e9 /
+                                             peaks["write_GB_per_s"] if peaks else None),
+                     "traffic": counted_traffic("mrf::k_sim_dict<5, 1, true, false>", "sim.hip"),
+                     "separate_ms": {"f32": sep["f32"], "bf16": sep["bf16"],
+                                     "sum": sep["f32"] + sep["bf16"]}},
         "zoom_multistart": {
-            "schedule": "paper stages from a 4 x 4 start lattice over T1/T2 (ends included), "
-                        "outer rounds [df window, fine df, 2-D zooms 100/50/20/10/1 ms] <= 8",
+            "schedule": "paper stages from a 2 x 3 start lattice over T1/T2 (ends included), "
+                        "outer rounds [df window, fine df, 2-D zooms 100/50/20/10/1 ms] <= 8; "
+                        "the cheapest lattice whose oracle ZOOM matched the oracle brute force "
+                        "on every pinned voxel of both small workloads",
             "slice_ms_p50": float(np.percentile(zm, 50)),
             "slice_ms_p99": float(np.percentile(zm, 99)), "repeats": len(zm),
             "voxels_per_s": n_vox / (float(np.median(zm)) * 1e-3),
@@ -1026,7 +1043,7 @@ def main():
         log("smoothing ...")
         res["smoothing"] = smoothing_bench(
             api, ctx, torch, w, vox, d32, ws, wsz,
-            {"dict_f32": res["rows_ms"]["dict_f32"], "zoom": res["zoom"]["slice_ms_p50"],
+            {"dict_f32": sep["f32"], "zoom": res["zoom"]["slice_ms_p50"],
              "idx_f32": idx32, "idx_zoom": idxz})
     del d32, d16
     torch.cuda.empty_cache()
@@ -1060,7 +1077,7 @@ def main():
                 "small_dgs": oracle_agreement(api, ctx, torch, th),
                 "slice64_subset": slice_epsilon_agreement(
                     w, {"fp32": idx32, "bf16_rescore": idx16, "zoom_paper": idxz,
-                        "zoom_multistart_4x4": outzm["idx"].cpu().numpy(),
+                        "zoom_multistart_2x3": outzm["idx"].cpu().numpy(),
                         "fp32_refined": rf32})}
         res["cpu_baseline"] = cb
         if serve_sample is not None:
@@ -1081,10 +1098,10 @@ def main():
                 "bf16_rescore_vs_fp32": {"speedup": res["bf16"]["speedup_vs_f32"],
                                          "agreement_pinned_small": pin("bf16_rescore"),
                                          "eps_agreement_slice": sl["bf16_rescore"]["eps_agreement_1e-5"]},
-                "zoom_multistart_4x4_vs_fp32": {
+                "zoom_multistart_2x3_vs_fp32": {
                     "speedup": res["zoom_multistart"]["speedup_vs_f32"],
-                    "agreement_pinned_small": pin_bf("zoom_multistart_4x4"),
-                    "eps_agreement_slice": sl["zoom_multistart_4x4"]["eps_agreement_1e-5"]},
+                    "agreement_pinned_small": pin_bf("zoom_multistart_2x3"),
+                    "eps_agreement_slice": sl["zoom_multistart_2x3"]["eps_agreement_1e-5"]},
                 "zoom_paper_vs_fp32": {
                     "speedup": res["zoom_vs_brute"]["speedup_vs_f32"],
                     "agreement_pinned_small": pin_bf("zoom_paper"),

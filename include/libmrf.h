@@ -144,6 +144,20 @@ int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq, const mrf
                             mrf_dtype dtype, void* re, void* im, int64_t ld,
                             double* norm, int32_t unit_norm, void* stream);
 
+/* The FP32 planar (MRF_F32) and BF16 (MRF_BF16) dictionaries of one entry
+ * range from one recursion pass (Appendix Eq. A2), raw values (M0 = 1):
+ * re/im as MRF_F32 and packed as MRF_BF16 above, all with the same ld (in
+ * entries); norm (FP64 [entry_count] or NULL) receives ||d|| of the FP32
+ * values and norm_bf16 (or NULL) the norm of the stored BF16 values. Every
+ * value and norm equals what mrf_simulate_dictionary writes for each dtype
+ * with unit_norm = 0. Caller-owned device buffers; enqueued on `stream`.
+ * Errors: as mrf_simulate_dictionary for both layouts (n_tr % 4 == 0, packed
+ * 16-byte aligned, ld >= entry_count, NULL re/im/packed with entries). */
+int mrf_simulate_dictionary_pair(mrf_context* ctx, const mrf_sequence* seq,
+                                 const mrf_grid* grid, int32_t n_tr, int64_t entry_begin,
+                                 int64_t entry_count, float* re, float* im, void* packed,
+                                 int64_t ld, double* norm, double* norm_bf16, void* stream);
+
 /* CC map (Methods and Results, Experiment 1): the CC of Eq. 1 between each
  * fingerprint and every entry of [entry_begin, entry_begin + entry_count) of
  * `grid`, written out in full:

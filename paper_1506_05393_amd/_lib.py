@@ -65,6 +65,9 @@ _SIGS = [
     ("mrf_simulate_dictionary", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int64, C.c_int64, C.c_int,
       C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("mrf_simulate_dictionary_pair", C.c_int,
+     [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
+      C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mrf_cc_map", C.c_int,
      [C.c_void_p, C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_void_p, C.c_int32, C.c_int64,
       C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),

@@ -184,6 +184,32 @@ def simulate_dictionary(ctx: Context, seq: Sequence, grid, n_tr: Optional[int] =
     return d
 
 
+def simulate_dictionary_pair(ctx: Context, seq: Sequence, grid, n_tr: Optional[int] = None,
+                             entry_begin: int = 0, entry_count: Optional[int] = None,
+                             out: Optional[tuple] = None, stream=None) -> tuple:
+    """The FP32 planar and the BF16 dictionary of the same entries (raw
+    values, with their norms) from one simulation pass: (d32, d16), as
+    simulate_dictionary gives them for dtype "f32" and "bf16"."""
+    n_tr = seq.n if n_tr is None else int(n_tr)
+    g = grid if isinstance(grid, GridArg) else GridArg(grid)
+    count = g.grid.size - entry_begin if entry_count is None else int(entry_count)
+    if out is not None:
+        d32, d16 = out
+        if d32.ld != d16.ld:
+            raise ValueError("the two dictionaries must share ld")
+    else:
+        d32 = alloc_dictionary(n_tr, count, "f32", ctx.device, with_norm=True)
+        d16 = alloc_dictionary(n_tr, count, "bf16", ctx.device, with_norm=True)
+    for d in (d32, d16):
+        d.entry_base = int(entry_begin)
+    L.check(ctx._lib.mrf_simulate_dictionary_pair(
+        ctx.handle, seq.handle, g.ptr, n_tr, int(entry_begin), count, d32.re.data_ptr(),
+        d32.im.data_ptr(), d16.re.data_ptr(), d32.ld,
+        d32.norm.data_ptr() if d32.norm is not None else None,
+        d16.norm.data_ptr() if d16.norm is not None else None, _stream_ptr(stream)))
+    return d32, d16
+
+
 def cc_map(ctx: Context, seq: Sequence, grid, vox: torch.Tensor, n_tr: Optional[int] = None,
            entry_begin: int = 0, entry_count: Optional[int] = None,
            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

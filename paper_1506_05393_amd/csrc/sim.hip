@@ -123,6 +123,7 @@ struct SimArgs {
   float* im;
   uint4* packed;    // BF16 blocks
   double* norm;
+  double* norm_b;   // MODE 5: the norm of the stored BF16 values
   float* cc;        // CC map output (MODE 3)
   SmoothW sm;       // temporal smoothing weights (SM kernels)
   const float2* demod;  // [n_tr] (cos, sin) of the RF phases (SM kernels)
@@ -147,6 +148,7 @@ struct Dots {
 // the norm only, MODE 1 stores FP32 planes, MODE 4 stores FP32 entry-major
 // rows (two readouts per 16-byte store), MODE 2 stores BF16 blocks and
 // also accumulates the norm of the stored (scaled, rounded) values into nb,
+// MODE 5 stores both the FP32 planes and the BF16 blocks (and both norms),
 // MODE 3 stores nothing and accumulates v conj(d) against the fingerprint
 // `vox` (one value per readout, the same for every thread) into dt.
 // SM: the entry is smoothed over the readouts (a five-sample delay line per
@@ -244,12 +246,16 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
         }
       }
       if (ol == kChunkRows - 1) store_rows(q, o - (kChunkRows - 1), kChunkRows);
-    } else if (MODE == 1) {
-      const rsrc_t wr = make_rsrc(a.re + (int64_t)o * a.ld + blk0, nrec);
-      const rsrc_t wi = make_rsrc(a.im + (int64_t)o * a.ld + blk0, nrec);
+    }
+    if (MODE == 1 || MODE == 5) {
+      // (nrec counts 4-byte records per plane row)
+      const int32_t rec = MODE == 5 ? nrec / 4 : nrec;
+      const rsrc_t wr = make_rsrc(a.re + (int64_t)o * a.ld + blk0, rec);
+      const rsrc_t wi = make_rsrc(a.im + (int64_t)o * a.ld + blk0, rec);
       store1(ox, wr, 4u * (tid + kThreads * q));
       store1(oy, wi, 4u * (tid + kThreads * q));
-    } else if (MODE == 2) {
+    }
+    if (MODE == 2 || MODE == 5) {
       const uint32_t v = pack_bf16x2(ox, oy);
       w[q][ol & 3] = v;
       // |stored value|^2: BF16 products are exact in FP32 (v_dot2_f32_bf16)
@@ -259,7 +265,8 @@ __device__ __forceinline__ void sim_pass(const SimArgs& a, const EntryState& st,
         const rsrc_t wr = make_rsrc(a.packed + (int64_t)(o >> 2) * a.ld + blk0, nrec);
         store4(w[q], wr, 16u * (tid + kThreads * q));
       }
-    } else if (MODE == 3) {
+    }
+    if (MODE == 3) {
       pre[q] = fmaf(vo.x, ox, fmaf(vo.y, oy, pre[q]));
       pim[q] = fmaf(vo.y, ox, fmaf(-vo.x, oy, pim[q]));
     }
@@ -388,7 +395,9 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
   const int64_t blk0 = (int64_t)blockIdx.x * kBlockEntries;
   const int64_t rem = a.count - blk0;
   const int32_t nb_entries = (int32_t)(rem < kBlockEntries ? rem : kBlockEntries);
-  const int32_t nrec = nb_entries * (MODE == 2 ? 16 : 4);
+  // buffer range in bytes of one store row: 16 per entry for BF16 blocks
+  // (MODE 5: FP32 plane rows use a quarter of it), 4 for FP32 planes
+  const int32_t nrec = nb_entries * ((MODE == 2 || MODE == 5) ? 16 : 4);
   EntryState st;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
@@ -436,12 +445,13 @@ __global__ __launch_bounds__(kThreads) void k_sim_dict(SimArgs a, const float2* 
       const double den = n2[q] * dt.vn2;
       if (e < a.count) a.cc[e] = den > 0.0 ? (float)sqrt((double)num / den) : 0.0f;
     }
-  } else if (a.norm) {
+  } else {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int64_t e = blk0 + tid + kThreads * q;
       // BF16: the norm of the values actually stored
-      if (e < a.count) a.norm[e] = sqrt(MODE == 2 ? nb[q] : n2[q]);
+      if (e < a.count && a.norm) a.norm[e] = sqrt(MODE == 2 ? nb[q] : n2[q]);
+      if (MODE == 5 && e < a.count && a.norm_b) a.norm_b[e] = sqrt(nb[q]);
     }
   }
 }
@@ -641,6 +651,29 @@ int launch_sim_dict(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count
   return MRF_OK;
 }
 
+// The FP32 planar and raw BF16 dictionaries of one entry range from one
+// recursion pass (MODE 5).
+static int launch_sim_pair(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count,
+                           float* re, float* im, void* packed, int64_t ld, double* norm,
+                           double* norm_b, hipStream_t stream) {
+  if (count == 0) return MRF_OK;
+  SimArgs a;
+  int64_t blocks = 0;
+  int rc = sim_args(t, k0, count, &a, &blocks);
+  if (rc) return rc;
+  a.unit_norm = 0;
+  a.ld = ld;
+  a.re = re;
+  a.im = im;
+  a.packed = (uint4*)packed;
+  a.norm = norm;
+  a.norm_b = norm_b;
+  ProfScope prof(ctx, "k_sim_dict", stream);
+  launch_sim_mode<5>(a, t, blocks, stream);
+  MRF_HIP(hipGetLastError());
+  return MRF_OK;
+}
+
 // CC map of one fingerprint (Experiment 1): the dictionary recursion of every
 // entry, with the CC of Eq. 1 accumulated on the fly; nothing else is stored.
 static int launch_cc_map(mrf_context* ctx, const Tables& t, int64_t k0, int64_t count,
@@ -699,6 +732,32 @@ extern "C" int mrf_simulate_dictionary(mrf_context* ctx, const mrf_sequence* seq
   const Tables* t = tref.get();
   if (rc) return rc;
   return launch_sim_dict(ctx, *t, entry_begin, entry_count, dtype, re, im, ld, norm, unit_norm ? 1 : 0,
+                         (hipStream_t)stream);
+}
+
+extern "C" int mrf_simulate_dictionary_pair(mrf_context* ctx, const mrf_sequence* seq,
+                                            const mrf_grid* grid, int32_t n_tr,
+                                            int64_t entry_begin, int64_t entry_count, float* re,
+                                            float* im, void* packed, int64_t ld, double* norm,
+                                            double* norm_bf16, void* stream) {
+  MRF_CHECK_ARG(ctx && seq, "context and sequence must not be NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  MRF_CHECK_ARG(n_tr >= 1 && n_tr <= seq->n, "n_tr %d must be in [1, %d]", n_tr, seq->n);
+  MRF_CHECK_ARG(n_tr % 4 == 0, "BF16 dictionaries need n_tr %% 4 == 0 (got %d)", n_tr);
+  const int64_t E = grid_size_checked(grid);
+  MRF_CHECK_ARG(entry_begin >= 0 && entry_count >= 0 && entry_begin + entry_count <= E,
+                "entry range [%lld, %lld) outside the grid of %lld entries",
+                (long long)entry_begin, (long long)(entry_begin + entry_count), (long long)E);
+  MRF_CHECK_ARG(ld >= entry_count, "ld (%lld) must be >= entry_count (%lld)", (long long)ld,
+                (long long)entry_count);
+  MRF_CHECK_ARG(entry_count == 0 || (re && im && packed), "re, im and packed must not be NULL");
+  MRF_CHECK_ARG(((uintptr_t)packed & 15) == 0, "BF16 dictionary must be 16-byte aligned");
+  TablesRef tref;  // held until the launch is enqueued
+  rc = get_tables(const_cast<mrf_sequence*>(seq), grid, n_tr, (hipStream_t)stream, &tref);
+  const Tables* t = tref.get();
+  if (rc) return rc;
+  return launch_sim_pair(ctx, *t, entry_begin, entry_count, re, im, packed, ld, norm, norm_bf16,
                          (hipStream_t)stream);
 }
 

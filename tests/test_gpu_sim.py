@@ -228,3 +228,36 @@ def test_full_size_dictionary_sampled(ctx, orc):
         assert abs(nrm[i] - np.linalg.norm(ref)) < 5e-6 * np.linalg.norm(ref)
     del d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("case", ["x_axis", "general_b1_df150", "x_axis_b1_smooth"])
+def test_dictionary_pair_equals_both_dictionaries(ctx, case):
+    """One pass writing the FP32 planes and the BF16 blocks gives, bit for
+    bit, the two dictionaries (and norms) that two separate calls write, over
+    a ragged entry range that starts inside the grid."""
+    from paper_1506_05393_amd import api
+    if case == "x_axis":
+        seq = I.make_sequence(64, 5)
+        grid = I.make_grid([300.0, 700.0, 1500.0, 2500.0], [30.0, 80.0, 250.0],
+                           I.grid_linspace(-60, 60, 41))
+    elif case == "general_b1_df150":
+        seq = _general_phase_seq(64, 9)
+        grid = I.make_grid([300.0, 700.0, 1500.0, 2500.0], [30.0, 80.0, 250.0],
+                           I.grid_linspace(-60, 60, 150), [0.9, 1.1])
+    else:
+        base = I.make_sequence(64, 6)
+        seq = I.Sequence(base.fa_deg, base.phase_deg, base.tr_ms, base.te_ms, 1, 0.0, smooth=5)
+        grid = I.make_grid([300.0, 700.0, 1500.0, 2500.0], [30.0, 80.0, 250.0],
+                           I.grid_linspace(-60, 60, 21), [0.8, 1.0, 1.2])
+    sq = api.Sequence(ctx, seq)
+    b = 7
+    count = grid.size - b - 3  # a ragged block at both ends
+    d32, d16 = api.simulate_dictionary_pair(ctx, sq, grid, entry_begin=b, entry_count=count)
+    s32 = api.simulate_dictionary(ctx, sq, grid, dtype="f32", entry_begin=b, entry_count=count)
+    s16 = api.simulate_dictionary(ctx, sq, grid, dtype="bf16", entry_begin=b, entry_count=count)
+    torch.cuda.synchronize()
+    assert d32.ld == s32.ld and d16.ld == s16.ld
+    assert torch.equal(d32.re[:, :count], s32.re[:, :count])
+    assert torch.equal(d32.im[:, :count], s32.im[:, :count])
+    assert torch.equal(d16.re[:, :count], s16.re[:, :count])
+    assert torch.equal(d32.norm, s32.norm) and torch.equal(d16.norm, s16.norm)
