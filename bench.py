@@ -961,7 +961,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_match_f32_3m", "achieved": achieved,
                      "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp32_mfma_tflops"],
-                     "traffic": counted_traffic("mrf::k_match_f32_3m", "match.hip"),
+                     "traffic": counted_traffic("mrf::k_match_f32_3m<16>", "match.hip"),
                      "avg_ms": gemm_avg, "launches": gemm_n,
                      "algorithmic_flops_per_launch": flops,
                      "flops_note": "achieved counts 8 V N E (a complex MAC as 4 real MACs); the "
