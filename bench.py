@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=0,
                    help="cap on the requests of the serving stream (0: none)")
     p.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    p.add_argument("--serve-window-ms", type=float, default=750.0,
+                   help="batching window of the second serving run (0: skip it)")
     return p.parse_args()
 
 
@@ -170,9 +172,11 @@ def volume_bench(api, ctx, torch, n_slices: int = 8, side: int = 256):
 
 
 def serve_bench(api, ctx, torch, seconds: float, rate: float, seed: int = 4,
-                max_requests: int = 0):
+                max_requests: int = 0, window_ms: float = 0.0):
     """Request stream through the server: Poisson arrivals at `rate`/s for
-    `seconds`, slices of 32^2, 64^2, 96^2 or 128^2 voxels, N in {500, 1000},
+    `seconds` (rate x seconds arrival times, uniform over the span: a Poisson
+    process conditioned on its count), with the server's batching window
+    `window_ms`, slices of 32^2, 64^2, 96^2 or 128^2 voxels, N in {500, 1000},
     three sequences (seeds 2-4) with resident BF16 dictionaries over a
     1.6M-entry grid, half brute force (BF16 + FP32 re-scoring), half
     MRF-ZOOM (simulated on the fly). Latency = completion observed by the
@@ -202,21 +206,20 @@ def serve_bench(api, ctx, torch, seconds: float, rate: float, seed: int = 4,
             noises[(si, n)] = noise
     resident = 3 * ((grid.size + 255) // 256 * 256 * 250 * 16 + 2 * grid.size * 8)
     budget = resident + 24 * (1 << 30)
-    srv = api.Server(ctx, budget, max_inflight=64, n_streams=2, refine_bf16=True)
+    srv = api.Server(ctx, budget, max_inflight=64, n_streams=2, refine_bf16=True,
+                     batch_window_ms=window_ms)
     try:
         slots = [srv.register(sq, grid, "bf16", lengths=(500, 1000)) for sq in seqs]
         warm = [srv.submit(m, s, n, pools[(s, 32)]) for m in ("brute", "zoom") for s in slots
                 for n in (500, 1000)]
         srv.wait(warm, timeout_s=120)
         st0 = srv.stats()
-        trace = []
-        t = 0.0
-        while True:
-            t += rng.exponential(1.0 / rate)
-            if t > seconds or (max_requests and len(trace) >= max_requests):
-                break
-            trace.append((t, ("brute", "zoom")[rng.integers(2)], int(rng.integers(3)),
-                          int(rng.choice([500, 1000])), int(rng.choice(sizes))))
+        n_arr = int(round(rate * seconds))
+        if max_requests:
+            n_arr = min(n_arr, max_requests)
+        times = np.sort(rng.uniform(0.0, seconds, n_arr))
+        trace = [(float(t), ("brute", "zoom")[rng.integers(2)], int(rng.integers(3)),
+                  int(rng.choice([500, 1000])), int(rng.choice(sizes))) for t in times]
         tickets, meta, rejected = [], [], 0
         t0 = time.perf_counter()
         last_log = t0
@@ -262,9 +265,10 @@ def serve_bench(api, ctx, torch, seconds: float, rate: float, seed: int = 4,
     mr = [st["mode_requests"][k] - st0["mode_requests"][k] for k in (0, 1)]
     mx = [st["mixed_length_batches"][k] - st0["mixed_length_batches"][k] for k in (0, 1)]
     summary = {
-        "workload": f"Poisson {rate:g} req/s for {seconds:g} s, sizes 32^2..128^2, N in "
-                    f"{{500,1000}}, 3 sequences, grid {grid.size} entries, BF16 resident, half "
-                    f"brute / half ZOOM",
+        "workload": f"Poisson {rate:g} req/s for {seconds:g} s ({len(trace)} arrivals, uniform "
+                    f"over the span), sizes 32^2..128^2, N in {{500,1000}}, 3 sequences, grid "
+                    f"{grid.size} entries, BF16 resident, half brute / half ZOOM",
+        "batch_window_ms": window_ms,
         "brute_force": "BF16 GEMM, top-8 FP32 re-scoring, unit-step FP32 refinement",
         "offered_requests": len(trace),
         "submitted": int(st["submitted"] - st0["submitted"]),
@@ -1065,6 +1069,15 @@ def main():
                                                    max_requests=args.serve_requests)
         log(f"serving done: {res['serving']['done']} requests, p50 "
             f"{res['serving']['latency_ms_p50']:.1f} ms, p99 {res['serving']['latency_ms_p99']:.1f} ms")
+        if args.serve_window_ms > 0:
+            log(f"serving with a {args.serve_window_ms:g} ms batching window ...")
+            res["serving_batched"], _ = serve_bench(api, ctx, torch, args.serve_seconds,
+                                                    args.serve_rate,
+                                                    max_requests=args.serve_requests,
+                                                    window_ms=args.serve_window_ms)
+            rb = res["serving_batched"]["requests_per_batch_by_mode"]
+            log(f"batched serving done: {res['serving_batched']['done']} requests, "
+                f"{rb['brute']:.2f} / {rb['zoom']:.2f} requests per brute / ZOOM batch")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(w, args.cpu_seconds)

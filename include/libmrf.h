@@ -547,6 +547,12 @@ typedef struct {
    * then counts the entries the refinement simulated. 0: re-scored results
    * as mrf_match_bruteforce returns them. */
   int32_t refine_bf16;
+  /* Batching window, ms (>= 0): a (slot, mode) batch is launched once its
+   * oldest request has waited this long since submission, or once it is full
+   * (max_batch_vox, or the next request does not fit its reservation), or
+   * while the server drains at close; 0 launches on any idle stream at once.
+   * Larger windows trade latency for larger batches. */
+  double batch_window_ms;
 } mrf_server_config;
 
 typedef struct {

@@ -181,7 +181,8 @@ class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int32),
                 ("n_streams", C.c_int32), ("max_batch_vox", C.c_int32),
                 ("fake_device", C.c_int32), ("fake_ns_per_byte", C.c_double),
-                ("fake_fail_ticket", C.c_uint64), ("refine_bf16", C.c_int32)]
+                ("fake_fail_ticket", C.c_uint64), ("refine_bf16", C.c_int32),
+                ("batch_window_ms", C.c_double)]
 
 
 class Request(C.Structure):

@@ -557,12 +557,13 @@ class Server:
     def __init__(self, ctx: Optional[Context], budget_bytes: int, max_inflight: int = 64,
                  n_streams: int = 2, max_batch_vox: int = 0, fake: bool = False,
                  fake_ns_per_byte: float = 0.0, fake_fail_ticket: int = 0,
-                 refine_bf16: bool = False):
+                 refine_bf16: bool = False, batch_window_ms: float = 0.0):
         self._lib = L.load()
         self.ctx = ctx
         cfg = L.ServerConfig(int(budget_bytes), int(max_inflight), int(n_streams),
                              int(max_batch_vox), int(bool(fake)), float(fake_ns_per_byte),
-                             int(fake_fail_ticket), int(bool(refine_bf16)))
+                             int(fake_fail_ticket), int(bool(refine_bf16)),
+                             float(batch_window_ms))
         h = C.c_void_p()
         L.check(self._lib.mrf_server_create(ctx.handle if ctx is not None else None,
                                             C.byref(cfg), C.byref(h)))

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -452,38 +453,70 @@ void admit(mrf_server* srv) {
   }
 }
 
-// Form and launch batches on idle streams: the oldest admitted request's
-// (slot, mode) with every later admitted request of the same key, whatever
-// its readout count; the batch's buffers are laid out for its longest count.
-void launch_ready(mrf_server* srv) {
+// Form and launch batches on idle streams. Keys (slot, mode) are taken in
+// the order of their oldest admitted request; a key's batch holds that
+// request and every later admitted request of the same key, whatever its
+// readout count, until max_batch_vox or the reservations stop it (then it is
+// full); its buffers are laid out for its longest count. With a batching
+// window a key's batch waits until its oldest request is that old, unless it
+// is full or the server drains; *wake receives the earliest such deadline.
+void launch_ready(mrf_server* srv, double* wake) {
   const int64_t max_vox = srv->cfg.max_batch_vox > 0 ? srv->cfg.max_batch_vox : kDefaultMaxBatchVox;
+  const double window = srv->cfg.batch_window_ms;
   for (size_t si = 0; si < srv->running.size(); ++si) {
     while (!srv->admitted.empty() && srv->admitted.front()->state == MRF_REQ_CANCELLED)
       srv->admitted.pop_front();
     if (srv->running[si] || srv->admitted.empty()) continue;
-    Req* head = srv->admitted.front();
-    auto b = std::make_unique<Batch>();
-    b->slot = head->r.slot;
-    b->mode = head->r.mode;
-    b->n_tr = 0;
-    const Slot& s = *srv->slots[b->slot];
-    size_t reserved_sum = 0;
+    std::unique_ptr<Batch> b;
     Layout L;
-    for (Req* r : srv->admitted) {
-      if (r->state == MRF_REQ_CANCELLED) continue;
-      if (r->r.slot != b->slot || r->r.mode != b->mode) continue;
-      if (!b->reqs.empty() && b->n_vox + r->r.n_vox > max_vox) break;
-      const int32_t n_tr = std::max(b->n_tr, r->r.n_tr);
-      Layout L2;
-      if (batch_layout(srv, s, b->mode, n_tr, b->n_vox + r->r.n_vox, &L2)) break;
-      if (!b->reqs.empty() && L2.total > reserved_sum + r->footprint) break;
-      b->reqs.push_back(r);
-      b->n_vox += r->r.n_vox;
-      b->n_tr = n_tr;
-      reserved_sum += r->footprint;
-      L = L2;
+    std::vector<std::pair<int32_t, int32_t>> seen;
+    for (Req* head : srv->admitted) {
+      if (head->state == MRF_REQ_CANCELLED) continue;
+      const std::pair<int32_t, int32_t> key(head->r.slot, head->r.mode);
+      if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+      seen.push_back(key);
+      auto c = std::make_unique<Batch>();
+      c->slot = key.first;
+      c->mode = key.second;
+      c->n_tr = 0;
+      const Slot& s = *srv->slots[c->slot];
+      size_t reserved_sum = 0;
+      bool full = false;
+      Layout Lc;
+      for (Req* r : srv->admitted) {
+        if (r->state == MRF_REQ_CANCELLED) continue;
+        if (r->r.slot != c->slot || r->r.mode != c->mode) continue;
+        if (!c->reqs.empty() && c->n_vox + r->r.n_vox > max_vox) {
+          full = true;
+          break;
+        }
+        const int32_t n_tr = std::max(c->n_tr, r->r.n_tr);
+        Layout L2;
+        if (batch_layout(srv, s, c->mode, n_tr, c->n_vox + r->r.n_vox, &L2)) {
+          full = true;
+          break;
+        }
+        if (!c->reqs.empty() && L2.total > reserved_sum + r->footprint) {
+          full = true;
+          break;
+        }
+        c->reqs.push_back(r);
+        c->n_vox += r->r.n_vox;
+        c->n_tr = n_tr;
+        reserved_sum += r->footprint;
+        Lc = L2;
+      }
+      if (c->reqs.empty()) continue;
+      const double due = head->t_submit + window;
+      if (window > 0.0 && !full && !srv->stop && srv->now_ms() < due) {
+        *wake = std::min(*wake, due);
+        continue;
+      }
+      b = std::move(c);
+      L = Lc;
+      break;
     }
-    if (b->reqs.empty()) continue;
+    if (!b) return;  // nothing ready for any idle stream
     // brute force runs one GEMM per readout count: order the requests by count
     if (b->mode == MRF_SERVE_BRUTE)
       std::stable_sort(b->reqs.begin(), b->reqs.end(),
@@ -526,13 +559,18 @@ void scheduler(mrf_server* srv) {
       }
     }
     admit(srv);
-    launch_ready(srv);
+    double wake = INFINITY;  // a batching window's next deadline (ms)
+    launch_ready(srv, &wake);
     for (auto& b : srv->running) busy = busy || (bool)b;
     if (srv->stop && !busy && srv->pending.empty() && srv->admitted.empty()) break;
-    if (busy)
+    if (busy) {
       srv->cv.wait_for(lk, std::chrono::microseconds(100));
-    else
+    } else if (wake < INFINITY) {
+      const double d = std::max(wake - srv->now_ms(), 0.0);
+      srv->cv.wait_for(lk, std::chrono::microseconds((int64_t)(d * 1000.0) + 50));
+    } else {
       srv->cv.wait(lk);
+    }
   }
 }
 
@@ -573,6 +611,7 @@ extern "C" int mrf_server_create(mrf_context* ctx, const mrf_server_config* cfg,
   MRF_CHECK_ARG(cfg->max_inflight >= 1, "max_inflight must be >= 1");
   MRF_CHECK_ARG(cfg->n_streams >= 1 && cfg->n_streams <= 16, "n_streams must be in [1, 16]");
   MRF_CHECK_ARG(cfg->max_batch_vox >= 0, "max_batch_vox must be >= 0");
+  MRF_CHECK_ARG(cfg->batch_window_ms >= 0.0, "batch_window_ms must be >= 0");
   MRF_CHECK_ARG(!cfg->fake_device || cfg->fake_ns_per_byte >= 0, "fake_ns_per_byte must be >= 0");
   auto srv = std::make_unique<mrf_server>();
   srv->ctx = ctx;

@@ -219,3 +219,41 @@ def test_batches_span_readout_counts():
     assert st["mixed_length_batches"][0] >= 1 and st["mixed_length_batches"][1] >= 1
     assert st["mode_requests"] == [7, 6] and st["batches"] <= 4
     assert st["arena_peak_bytes"] <= st["peak_reserved_bytes"]
+
+
+def test_batching_window_groups_requests_and_bounds_their_wait():
+    """With idle streams, requests arriving 10 ms apart go out one per batch
+    without a window; with a 150 ms window they share batches (keyed by slot
+    and mode), and no request starts later than its window after submission
+    (plus the scheduler's wake-up), unless its batch was full."""
+    def run(window):
+        srv, slots = _server(budget_mb=400, n_streams=2, max_inflight=64,
+                             fake_ns_per_byte=0.0005, batch_window_ms=window)
+        try:
+            tickets = []
+            for i in range(12):
+                tickets.append(srv.submit("zoom", slots[0], (500, 1000)[i % 2], n_vox=1024))
+                time.sleep(0.010)
+            srv.wait(tickets, timeout_s=60)
+            polls = [srv.poll(t) for t in tickets]
+            st = srv.stats()
+        finally:
+            srv.close()
+        assert all(p[0] == "done" for p in polls)
+        return st, polls
+
+    st0, _ = run(0.0)
+    st1, polls = run(150.0)
+    assert st0["mode_batches"][1] >= 10  # one request per batch (each stream idle)
+    assert st1["mode_batches"][1] <= 3 and st1["max_batch_requests"] >= 4
+    for _, t_sub, t_start, _ in polls:
+        assert t_start - t_sub <= 150.0 + 50.0
+
+
+def test_batching_window_does_not_hold_a_draining_server():
+    """Closing the server launches a waiting batch at once."""
+    srv, slots = _server(budget_mb=400, n_streams=1, batch_window_ms=60_000.0)
+    t = srv.submit("brute", slots[0], 1000, n_vox=1024)
+    t0 = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t0 < 30.0
