@@ -24,14 +24,20 @@ namespace mrf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Workgroup tile 256 x 256: 4 waves in 2 x 2, each 128 x 128 = 4 x 4 blocks
-// of 32 x 32. One instruction covers K = 16 = 2 blocks of 4 readouts
-// (lanes 0-31: block 2s, lanes 32-63: block 2s + 1).
+// Workgroup tile 256 x 256: 8 waves in 2 x 4, each 128 x 64 = 4 x 2 blocks
+// of 32 x 32 (128 accumulators, so two waves share each SIMD and one issues
+// MFMAs while the other waits; measured 5% faster than 4 waves of 128 x 128
+// at one wave per SIMD). One instruction covers K = 16 = 2 blocks of 4
+// readouts (lanes 0-31: block 2s, lanes 32-63: block 2s + 1).
 constexpr int BBM = 256;
 constexpr int BBN = 256;
 constexpr int BKB = 4;        // 4-readout blocks per pipeline stage (16 readouts, K = 32)
-constexpr int NSTAGE = 4;     // LDS ring of stages; loads run NSTAGE-1 stages ahead
+constexpr int NSTAGE = 3;     // LDS ring of stages; loads run NSTAGE-1 stages ahead
 constexpr int BKK_MAX = 8;    // candidate list length in the epilogue
+constexpr int NW = 8;         // waves per workgroup: 2 (rows) x 4 (columns)
+constexpr int WCN = 4;        // column waves
+constexpr int TNB = 2;        // 32-column blocks per wave (64 columns)
+constexpr int LPS = 4;        // global->LDS loads per wave per stage
 
 struct MatchB16Args {
   const uint4* A;       // [nblk_pad][m_pad] 16-byte blocks
@@ -54,60 +60,58 @@ __device__ __forceinline__ void load_to_lds(const uint4* src, uint4* dst) {
   __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)dst, 16, 0, 0);
 }
 
-// Issue the loads of one stage (BKB blocks of A rows and B columns) for this wave.
+// Issue the loads of one stage (BKB blocks of A rows and B columns): wave w
+// moves 64-row (64-column) chunk w & 3 of blocks (w >> 2) and (w >> 2) + 2.
 __device__ __forceinline__ void issue_stage(const MatchB16Args& a, uint4* As, uint4* Bs, int st,
                                             int c, int row0, int64_t col0, int wave, int lane) {
+  const int ch = wave & 3;
 #pragma unroll
-  for (int i = 0; i < BKB; ++i) {
+  for (int h = 0; h < 2; ++h) {
+    const int i = (wave >> 2) + 2 * h;
     const int blk = c * BKB + i;
-    // A is zero-padded to nblk_pad blocks: every row of the tile exists
-    load_to_lds(a.A + (int64_t)blk * a.m_pad + row0 + wave * 64 + lane,
-                As + (st * BKB + i) * BBM + wave * 64);
-    // B: blocks past the last readout are clamped to a real block (their
-    // products meet zero A rows); columns past ld are clamped too (those
-    // columns are masked in the epilogue)
+    load_to_lds(a.A + (int64_t)blk * a.m_pad + row0 + ch * 64 + lane,
+                As + (st * BKB + i) * BBM + ch * 64);
     const int bb = blk < a.nblk ? blk : a.nblk - 1;
-    int64_t col = col0 + wave * 64 + lane;
+    int64_t col = col0 + ch * 64 + lane;
     col = col < a.ld ? col : a.ld - 1;
-    load_to_lds(a.B + (int64_t)bb * a.ld + col, Bs + (st * BKB + i) * BBN + wave * 64);
+    load_to_lds(a.B + (int64_t)bb * a.ld + col, Bs + (st * BKB + i) * BBN + ch * 64);
   }
 }
 
 // The entry norms of this lane's 4 tile columns (1 when the dictionary has
 // unit-norm entries; columns past the last entry read entry 0, masked later).
 __device__ __forceinline__ void load_norms(const MatchB16Args& a, int64_t col0, int wc, int lane,
-                                           double (&nrm)[4]) {
+                                           double (&nrm)[TNB]) {
 #pragma unroll
-  for (int bn = 0; bn < 4; ++bn) {
-    const int64_t e = col0 + wc * 128 + bn * 32 + (lane & 31);
+  for (int bn = 0; bn < TNB; ++bn) {
+    const int64_t e = col0 + wc * 64 + bn * 32 + (lane & 31);
     nrm[bn] = a.norm ? a.norm[e < a.n_entries ? e : 0] : 1.0;
   }
 }
 
 // The A and B fragments of MFMA group s (0 or 1) of ring slot st for this lane.
 __device__ __forceinline__ void read_frags(const uint4* As, const uint4* Bs, int st, int s, int wr,
-                                           int wc, int lane, bf16x8 (&fa)[4], bf16x8 (&fb)[4]) {
+                                           int wc, int lane, bf16x8 (&fa)[4], bf16x8 (&fb)[TNB]) {
   const bf16x8* as =
       (const bf16x8*)(As + (st * BKB + 2 * s + (lane >> 5)) * BBM + wr * 128 + (lane & 31));
   const bf16x8* bs =
-      (const bf16x8*)(Bs + (st * BKB + 2 * s + (lane >> 5)) * BBN + wc * 128 + (lane & 31));
+      (const bf16x8*)(Bs + (st * BKB + 2 * s + (lane >> 5)) * BBN + wc * 64 + (lane & 31));
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    fa[i] = as[32 * i];
-    fb[i] = bs[32 * i];
-  }
+  for (int i = 0; i < 4; ++i) fa[i] = as[32 * i];
+#pragma unroll
+  for (int j = 0; j < TNB; ++j) fb[j] = bs[32 * j];
 }
 
-__device__ __forceinline__ void mfma_group(floatx16 (&acc)[4][4], const bf16x8 (&fa)[4],
-                                           const bf16x8 (&fb)[4]) {
+__device__ __forceinline__ void mfma_group(floatx16 (&acc)[4][TNB], const bf16x8 (&fa)[4],
+                                           const bf16x8 (&fb)[TNB]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TNB; ++j)
       acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
+__global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
   // Workgroups are dealt to the 8 XCDs in turn (w & 7), and each XCD starts
   // its slots in order, one workgroup per CU. The slots that run together on
   // an XCD form a grp_rows x grp_chunks block: every voxel tile is then read
@@ -126,13 +130,13 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* As = (uint4*)smem;                  // [NSTAGE][BKB][BBM]
   uint4* Bs = As + NSTAGE * BKB * BBM;       // [NSTAGE][BKB][BBN]
-  float* Ls = (float*)(Bs + NSTAGE * BKB * BBN);  // [4 waves][64 voxels][BKK_MAX]
-  int32_t* Li = (int32_t*)(Ls + 4 * 64 * BKK_MAX);
+  float* Ls = (float*)(Bs + NSTAGE * BKB * BBN);  // [NW waves][64 voxels][BKK_MAX]
+  int32_t* Li = (int32_t*)(Ls + NW * 64 * BKK_MAX);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;
   const int kk = a.kk;
   const int row0 = rt * BBM;
   float* myLs = Ls + wave * 64 * BKK_MAX;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   // requested before the previous tile's epilogue runs, so their latency is
   // hidden behind it. Loads complete in issue order, so the norm loads (issued
   // first) have landed whenever a stage wait below is satisfied.
-  double nrm[4];
+  double nrm[TNB];
   if (ct_begin < ct_end) {
     load_norms(a, (int64_t)ct_begin * BBN, wc, lane, nrm);
     for (int p = 0; p < NSTAGE; ++p)
@@ -158,23 +162,22 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
   }
   for (int ct = ct_begin; ct < ct_end; ++ct) {
     const int64_t col0 = (int64_t)ct * BBN;
-    floatx16 acc[4][4];
+    floatx16 acc[4][TNB];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < TNB; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
     // stage 0 landed for this wave (stages 1-3 may still be in flight), then
     // for everyone (wait and barrier in one asm statement: no LDS read can be
     // moved above it)
-    if (n_kc >= 4)
-      asm volatile("s_waitcnt vmcnt(24)\n\ts_barrier" ::: "memory");
-    else if (n_kc == 3)
-      asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
-    else if (n_kc == 2)
+    static_assert(NSTAGE == 3 && LPS == 4, "the waits below count LPS loads per stage");
+    if (n_kc >= 3)
       asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+    else if (n_kc == 2)
+      asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
     else
       asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
 
@@ -184,43 +187,43 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
     // stage c + 1 has landed (one barrier); after the second group the slot
     // is refilled with stage c + NSTAGE. In the last stage the next-group
     // reads fetch a slot that is never used.
-    bf16x8 fa0[4], fb0[4], fa1[4], fb1[4];
+    bf16x8 fa0[4], fb0[TNB], fa1[4], fb1[TNB];
     read_frags(As, Bs, 0, 0, wr, wc, lane, fa0, fb0);
     for (int c = 0; c < n_kc; ++c) {
       const int st = c % NSTAGE;
       read_frags(As, Bs, st, 1, wr, wc, lane, fa1, fb1);
       mfma_group(acc, fa0, fb0);
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+      for (int g = 0; g < 4 + TNB; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
       }
+      __builtin_amdgcn_sched_group_barrier(0x008, 4 * TNB - 4 - TNB, 0);
       // this wave's reads of slot st are done and stage c + 1 landed, then
       // everyone's
       const int ahead = min(n_kc - 2 - c, NSTAGE - 2);
-      if (ahead >= 2)
-        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(16)\n\ts_barrier" ::: "memory");
-      else if (ahead == 1)
-        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(8)\n\ts_barrier" ::: "memory");
+      if (ahead >= 1)
+        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(4)\n\ts_barrier" ::: "memory");
       else
         asm volatile("s_waitcnt lgkmcnt(0) vmcnt(0)\n\ts_barrier" ::: "memory");
       read_frags(As, Bs, (c + 1) % NSTAGE, 0, wr, wc, lane, fa0, fb0);
       mfma_group(acc, fa1, fb1);
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      for (int g = 0; g < 4 + TNB; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
+      __builtin_amdgcn_sched_group_barrier(0x008, 4 * TNB - 4 - TNB, 0);
       if (c + NSTAGE < n_kc) issue_stage(a, As, Bs, st, c + NSTAGE, row0, col0, wave, lane);
     }
 
     // every wave is past its last reads of the ring: the next tile's norms and
     // first stages go out now and land during this epilogue
-    float inv[4];
-    int32_t ecol[4];
+    float inv[TNB];
+    int32_t ecol[TNB];
 #pragma unroll
-    for (int bn = 0; bn < 4; ++bn) {
-      const int64_t e = col0 + wc * 128 + bn * 32 + (lane & 31);
+    for (int bn = 0; bn < TNB; ++bn) {
+      const int64_t e = col0 + wc * 64 + bn * 32 + (lane & 31);
       ecol[bn] = (int32_t)e;
       inv[bn] = e < a.n_entries ? (nrm[bn] > 0.0 ? (float)(1.0 / (nrm[bn] * nrm[bn])) : 0.0f)
                                 : -1.0f;
@@ -237,12 +240,12 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
     // switch keeps only 64 accumulator values live in VGPRs
 #pragma unroll 1
     for (int bm = 0; bm < 4; ++bm) {
-      floatx16 blk[4];
+      floatx16 blk[TNB];
       switch (bm) {
-        case 0: blk[0] = acc[0][0]; blk[1] = acc[0][1]; blk[2] = acc[0][2]; blk[3] = acc[0][3]; break;
-        case 1: blk[0] = acc[1][0]; blk[1] = acc[1][1]; blk[2] = acc[1][2]; blk[3] = acc[1][3]; break;
-        case 2: blk[0] = acc[2][0]; blk[1] = acc[2][1]; blk[2] = acc[2][2]; blk[3] = acc[2][3]; break;
-        default: blk[0] = acc[3][0]; blk[1] = acc[3][1]; blk[2] = acc[3][2]; blk[3] = acc[3][3]; break;
+        case 0: blk[0] = acc[0][0]; blk[1] = acc[0][1]; break;
+        case 1: blk[0] = acc[1][0]; blk[1] = acc[1][1]; break;
+        case 2: blk[0] = acc[2][0]; blk[1] = acc[2][1]; break;
+        default: blk[0] = acc[3][0]; blk[1] = acc[3][1]; break;
       }
       // thresholds (the current k-th best of each voxel of this block), read
       // once; an insertion below can only raise a threshold, so a value read
@@ -257,17 +260,17 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int r = 4 * (q >> 1) + 2 * (q & 1);
-        float sc[4];
+        float sc[TNB];
 #pragma unroll
-        for (int bn = 0; bn < 4; ++bn) {
+        for (int bn = 0; bn < TNB; ++bn) {
           const float re = blk[bn][r], im = blk[bn][r + 1];
           sc[bn] = inv[bn] < 0.0f ? -1.0f : (re * re + im * im) * inv[bn];
         }
-        const float mx = fmaxf(fmaxf(sc[0], sc[1]), fmaxf(sc[2], sc[3]));
+        const float mx = fmaxf(sc[0], sc[1]);
         if (__ballot(mx > thr[q]) == 0) continue;  // common case
         const int vme = bm * 16 + 4 * (q >> 1) + 2 * (lane >> 5) + (q & 1);
 #pragma unroll
-        for (int bn = 0; bn < 4; ++bn) {
+        for (int bn = 0; bn < TNB; ++bn) {
           uint64_t m = __ballot(sc[bn] > myLs[vme * BKK_MAX + kk - 1]);
           while (m) {
             const int src = __ffsll((unsigned long long)m) - 1;
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(256) void k_match_bf16(MatchB16Args a) {
     const int vl = i / kk, p = i % kk;
     const int v = (row0 + wr * 128) / 2 + vl;
     if (v < a.n_vox_pad) {
-      const int64_t o = (((int64_t)chunk * 2 + wc) * a.n_vox_pad + v) * kk + p;
+      const int64_t o = (((int64_t)chunk * WCN + wc) * a.n_vox_pad + v) * kk + p;
       a.part_s[o] = myLs[vl * BKK_MAX + p];
       a.part_i[o] = myLi[vl * BKK_MAX + p];
     }
@@ -506,7 +509,7 @@ static PlanB plan_bf16(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int
   o = al(o + sizeof(uint4) * (size_t)p.nblk_pad * p.m_pad);
   p.off_vn = o;
   o = al(o + sizeof(double) * (size_t)p.n_vox_pad);
-  const size_t np = (size_t)p.n_chunks * 2 * p.n_vox_pad * p.kk;
+  const size_t np = (size_t)p.n_chunks * WCN * p.n_vox_pad * p.kk;
   p.off_ps = o;
   o = al(o + sizeof(float) * np);
   p.off_pi = o;
@@ -573,7 +576,7 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   a.part_s = ps;
   a.part_i = pi;
   const size_t lds = sizeof(uint4) * NSTAGE * BKB * (BBM + BBN) +
-                     (sizeof(float) + sizeof(int32_t)) * 4 * 64 * BKK_MAX;
+                     (sizeof(float) + sizeof(int32_t)) * NW * 64 * BKK_MAX;
   static bool attr = false;
   if (!attr) {
     MRF_HIP(hipFuncSetAttribute((const void*)k_match_bf16,
@@ -582,13 +585,13 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   }
   {
     ProfScope prof(ctx, "k_match_bf16", st);
-    hipLaunchKernelGGL(k_match_bf16, dim3(p.n_wg), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(k_match_bf16, dim3(p.n_wg), dim3(64 * NW), lds, st, a);
   }
   MRF_HIP(hipGetLastError());
   MergeArgs m;
   m.part_s = ps;
   m.part_i = pi;
-  m.n_lists = p.n_chunks * 2;
+  m.n_lists = p.n_chunks * WCN;
   m.n_vox = n_vox;
   m.n_vox_pad = p.n_vox_pad;
   m.kk = p.kk;
