@@ -32,7 +32,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int BBM = 256;
 constexpr int BBN = 256;
 constexpr int BKB = 4;        // 4-readout blocks per pipeline stage (16 readouts, K = 32)
-constexpr int NSTAGE = 3;     // LDS ring of stages; loads run NSTAGE-1 stages ahead
+constexpr int NSTAGE = 4;     // LDS ring of stages; loads run NSTAGE-1 stages ahead (3: 1.6% slower)
 constexpr int BKK_MAX = 8;    // candidate list length in the epilogue
 constexpr int NW = 8;         // waves per workgroup: 2 (rows) x 4 (columns)
 constexpr int WCN = 4;        // column waves
@@ -49,6 +49,7 @@ struct MatchB16Args {
   int32_t grp_rows, grp_chunks;  // workgroups resident on one XCD: grp_rows x grp_chunks
   float* part_s;        // [n_chunks][2][n_vox_pad][kk]
   int32_t* part_i;
+  uint32_t* sync;       // [n_groups][8] tile arrival counters (zeroed by k_pack_bf16)
 };
 
 typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -76,6 +77,17 @@ __device__ __forceinline__ void issue_stage(const MatchB16Args& a, uint4* As, ui
     col = col < a.ld ? col : a.ld - 1;
     load_to_lds(a.B + (int64_t)bb * a.ld + col, Bs + (st * BKB + i) * BBN + ch * 64);
   }
+}
+
+// Visiting order of a workgroup's nt column tiles: every TS-th tile first
+// (raising the top-k thresholds early, so the rest inserts few candidates),
+// then the others in order. Returns the tile offset of the k-th visit.
+constexpr int TS = 16;
+__device__ __forceinline__ int tile_at(int k, int nt) {
+  const int n1 = (nt + TS - 1) / TS;
+  if (k < n1) return k * TS;
+  const int m = k - n1;
+  return m + m / (TS - 1) + 1;
 }
 
 // The entry norms of this lane's 4 tile columns (1 when the dictionary has
@@ -126,6 +138,17 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
   const int rt = (slot / per) * a.grp_rows + within % a.grp_rows;
   const int chunk = xcd + 8 * (within / a.grp_rows);
   if (rt >= a.n_row_tiles || chunk >= a.n_chunks) return;
+  // Tile-phase alignment of the workgroups resident together on this XCD:
+  // each one counts its finished tiles into ctr and, before its next tile,
+  // waits (bounded) until every peer has finished as many. In step, the 8
+  // readers of a dictionary tile and the 4 readers of a voxel tile fetch each
+  // stage within a few microseconds of each other and the later ones hit in
+  // L2 (L2 hit rate 0.80 against 0.26 unaligned). Timing only: results do
+  // not depend on it.
+  const int grp = slot / per;
+  uint32_t* ctr = a.sync + grp * 8 + xcd;
+  const int rows_valid = min(a.grp_rows, a.n_row_tiles - grp * a.grp_rows);
+  bool align = true;  // lane 0 of wave 0 only
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* As = (uint4*)smem;                  // [NSTAGE][BKB][BBM]
@@ -160,8 +183,9 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
     for (int p = 0; p < NSTAGE; ++p)
       if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, (int64_t)ct_begin * BBN, wave, lane);
   }
+  const int n_ct = ct_end - ct_begin;
   for (int ct = ct_begin; ct < ct_end; ++ct) {
-    const int64_t col0 = (int64_t)ct * BBN;
+    const int64_t col0 = (int64_t)(ct_begin + tile_at(ct - ct_begin, n_ct)) * BBN;
     floatx16 acc[4][TNB];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -173,8 +197,10 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
     // stage 0 landed for this wave (stages 1-3 may still be in flight), then
     // for everyone (wait and barrier in one asm statement: no LDS read can be
     // moved above it)
-    static_assert(NSTAGE == 3 && LPS == 4, "the waits below count LPS loads per stage");
-    if (n_kc >= 3)
+    static_assert(NSTAGE == 4 && LPS == 4, "the waits below count LPS loads per stage");
+    if (n_kc >= 4)
+      asm volatile("s_waitcnt vmcnt(12)\n\ts_barrier" ::: "memory");
+    else if (n_kc == 3)
       asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
     else if (n_kc == 2)
       asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
@@ -202,7 +228,9 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
       // this wave's reads of slot st are done and stage c + 1 landed, then
       // everyone's
       const int ahead = min(n_kc - 2 - c, NSTAGE - 2);
-      if (ahead >= 1)
+      if (ahead >= 2)
+        asm volatile("s_waitcnt lgkmcnt(0) vmcnt(8)\n\ts_barrier" ::: "memory");
+      else if (ahead == 1)
         asm volatile("s_waitcnt lgkmcnt(0) vmcnt(4)\n\ts_barrier" ::: "memory");
       else
         asm volatile("s_waitcnt lgkmcnt(0) vmcnt(0)\n\ts_barrier" ::: "memory");
@@ -230,9 +258,11 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
     }
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (ct + 1 < ct_end) {
-      load_norms(a, col0 + BBN, wc, lane, nrm);
+      const int64_t col1 = (int64_t)(ct_begin + tile_at(ct + 1 - ct_begin, n_ct)) * BBN;
+      load_norms(a, col1, wc, lane, nrm);
       for (int p = 0; p < NSTAGE; ++p)
-        if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, col0 + BBN, wave, lane);
+        if (p < n_kc) issue_stage(a, As, Bs, p, p, row0, col1, wave, lane);
+      if (tid == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // ---- epilogue (as in the FP32 kernel) ----
@@ -283,6 +313,30 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
         }
       }
     }
+    if (ct + 1 < ct_end) {
+      if (tid == 0) {
+        // arrivals after this tile: every participant adds one per tile it
+        // ends with another tile still to do
+        const int i1 = ct - ct_begin + 1;
+        uint32_t target = 0;
+        for (int j = 0; j < a.grp_chunks; ++j) {
+          const int c2 = xcd + 8 * j;
+          if (c2 >= a.n_chunks) break;
+          const int nt = (int)((int64_t)(c2 + 1) * a.n_col_tiles / a.n_chunks) -
+                         (int)((int64_t)c2 * a.n_col_tiles / a.n_chunks);
+          target += (uint32_t)rows_valid * (uint32_t)max(min(nt - 1, i1), 0);
+        }
+        // bounded wait (50 us of the 100 MHz real-time counter): peers that
+        // are not resident (other kernels hold the CUs) only cost time, and
+        // after one timeout this workgroup stops aligning
+        const uint64_t t0 = wall_clock64();
+        while (align && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          if (wall_clock64() - t0 > 5000) align = false;
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+    }
   }
 
   for (int i = lane; i < 64 * kk; i += 64) {
@@ -300,9 +354,12 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
 __global__ __launch_bounds__(64) void k_pack_bf16(const float2* __restrict__ vox, int64_t ld_vox,
                                                   int32_t n_vox, int32_t n_tr, int32_t nblk_pad,
                                                   int32_t m_pad, uint4* __restrict__ A,
-                                                  double* __restrict__ vnorm) {
+                                                  double* __restrict__ vnorm, uint32_t* sync,
+                                                  int32_t n_sync) {
   const int v = blockIdx.x;
   const int lane = threadIdx.x;
+  if (v == 0)
+    for (int i = lane; i < n_sync; i += 64) sync[i] = 0;
   double s2 = 0.0;
   if (v < n_vox) {
     for (int j = lane; j < n_tr; j += 64) {
@@ -483,7 +540,8 @@ static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct PlanB {
   int32_t nblk, nblk_pad, m_pad, n_vox_pad, n_row_tiles, n_col_tiles, n_chunks, kk;
   int32_t grp_rows, grp_chunks, n_wg;
-  size_t off_A, off_vn, off_ps, off_pi, off_bs, off_bi, total;
+  size_t off_A, off_vn, off_ps, off_pi, off_bs, off_bi, off_sync, total;
+  int32_t n_sync;
 };
 
 static PlanB plan_bf16(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int n_cu) {
@@ -518,6 +576,9 @@ static PlanB plan_bf16(const mrf_dict_view* d, int32_t n_vox, int32_t top_k, int
   o = al(o + sizeof(float) * (size_t)p.n_vox_pad * p.kk);
   p.off_bi = o;
   o = al(o + sizeof(int32_t) * (size_t)p.n_vox_pad * p.kk);
+  p.n_sync = 8 * n_groups;
+  p.off_sync = o;
+  o = al(o + sizeof(uint32_t) * (size_t)p.n_sync);
   p.total = o;
   return p;
 }
@@ -554,7 +615,8 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   {
     ProfScope prof(ctx, "k_pack_bf16", st);
     hipLaunchKernelGGL(k_pack_bf16, dim3(p.n_vox_pad), dim3(64), 0, st, (const float2*)vox,
-                       ld_vox, n_vox, d->n_tr, p.nblk_pad, p.m_pad, A, vn);
+                       ld_vox, n_vox, d->n_tr, p.nblk_pad, p.m_pad, A, vn,
+                       (uint32_t*)(ws + p.off_sync), p.n_sync);
   }
   MRF_HIP(hipGetLastError());
   MatchB16Args a;
@@ -575,8 +637,14 @@ int match_bf16(mrf_context* ctx, const mrf_dict_view* d, const void* vox, int32_
   a.grp_chunks = p.grp_chunks;
   a.part_s = ps;
   a.part_i = pi;
+  a.sync = (uint32_t*)(ws + p.off_sync);
+  // 128 KB of ring + 32 KB of candidate lists: the whole 160 KB of a CU
   const size_t lds = sizeof(uint4) * NSTAGE * BKB * (BBM + BBN) +
                      (sizeof(float) + sizeof(int32_t)) * NW * 64 * BKK_MAX;
+  static_assert(sizeof(uint4) * NSTAGE * BKB * (BBM + BBN) +
+                        (sizeof(float) + sizeof(int32_t)) * NW * 64 * BKK_MAX <=
+                    160 * 1024,
+                "LDS budget of one CU");
   static bool attr = false;
   if (!attr) {
     MRF_HIP(hipFuncSetAttribute((const void*)k_match_bf16,
