@@ -744,7 +744,9 @@ def device_peaks(api, ctx, torch, write_gb: float = 16.0):
     n_cu = torch.cuda.get_device_properties(ctx.device).multi_processor_count
     out = torch.empty(n_cu * 2 * 256, dtype=torch.float32, device=ctx.device)
     res = {"what": "MFMA-only loops (4 independent 32x32 accumulators per wave, 2 waves per "
-                   "SIMD); write = one 16 B store per thread, 4 KB per workgroup; copy = torch copy_"}
+                   "SIMD; operands constant, and for bf16_varied varying by lane and element, "
+                   "which lowers the clock); write = one 16 B store per thread, 4 KB per "
+                   "workgroup; copy = torch copy_"}
     ctx.profile(True)
     for dt, iters, per_lane in (("f32", 120000, 16), ("bf16", 240000, 128)):
         name = "k_probe_mfma_" + dt
@@ -758,6 +760,16 @@ def device_peaks(api, ctx, torch, write_gb: float = 16.0):
         ms, n = ctx.profile_read(name)
         res[f"mfma_{dt}_tflops"] = fl / (ms / n * 1e-3) / 1e12
         res[f"mfma_{dt}_output_exact"] = bool((out == float(per_lane * iters)).all().item())
+    api.probe_mfma_varied(ctx, 1000, out)
+    torch.cuda.synchronize()
+    ctx.profile_read("k_probe_mfma_bf16_varied", reset=True)
+    fl = 0.0
+    for _ in range(3):
+        fl = api.probe_mfma_varied(ctx, 240000, out)
+    torch.cuda.synchronize()
+    ms, n = ctx.profile_read("k_probe_mfma_bf16_varied")
+    res["mfma_bf16_varied_tflops"] = fl / (ms / n * 1e-3) / 1e12
+    res["mfma_bf16_varied_output_finite"] = bool(torch.isfinite(out).all().item())
     nb = int(write_gb * 1e9) // 32 * 32
     buf = torch.empty(nb, dtype=torch.uint8, device=ctx.device)
     api.probe_write(ctx, buf)
@@ -785,6 +797,29 @@ def device_peaks(api, ctx, torch, write_gb: float = 16.0):
     del buf, x, y, w4
     torch.cuda.empty_cache()
     return res
+
+
+def vendor_gemm(torch, m: int, k: int, n: int, reps: int = 10):
+    """torch.matmul (hipBLASLt) on a BF16 GEMM of the brute-force shape (M = 2
+    rows per voxel, K = the packed readouts, N a slice of the entries), on
+    random data, timed by events: the vendor library's rate on this shape,
+    beside which the fused GEMM + top-k kernel is read."""
+    g = torch.Generator(device="cuda").manual_seed(1)
+    a = torch.randn(m, k, device="cuda", dtype=torch.bfloat16, generator=g)
+    b = torch.randn(k, n, device="cuda", dtype=torch.bfloat16, generator=g)
+    for _ in range(3):
+        c = a @ b
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"shape_mkn": [m, k, n], "ms": ms, "TFLOP_per_s": 2.0 * m * n * k / (ms * 1e-3) / 1e12}
 
 
 def copy_probe(gb: float):
@@ -911,6 +946,13 @@ def main():
     if not args.no_peaks:
         log("device peaks ...")
         peaks = device_peaks(api, ctx, torch)
+    vendor = None
+    if not args.no_peaks:
+        # the BF16 GEMM's packed shape: 2 rows per voxel, 8 values per
+        # 4-readout block with the blocks padded to 4, a 65536-entry slice
+        kb = 8 * (((w.n_tr + 3) // 4 + 3) // 4 * 4)
+        log("vendor BF16 GEMM on the same shape ...")
+        vendor = vendor_gemm(torch, 2 * n_vox, kb, 65536)
 
     per_row = {}
     step_ms = []
@@ -982,6 +1024,11 @@ def main():
                  "frac_bf16_peak": flops / (b16_avg * 1e-3) / 1e12 / PEAK["bf16_mfma_tflops"],
                  "frac_bf16_measured": (flops / (b16_avg * 1e-3) / 1e12 / peaks["mfma_bf16_tflops"]
                                         if peaks else None),
+                 "frac_bf16_varied_peak": (flops / (b16_avg * 1e-3) / 1e12 /
+                                           peaks["mfma_bf16_varied_tflops"] if peaks else None),
+                 "vendor_gemm_same_shape": vendor,
+                 "ratio_vs_vendor_gemm": (flops / (b16_avg * 1e-3) / 1e12 / vendor["TFLOP_per_s"]
+                                          if vendor else None),
                  "rescore_ms": rs_ms / max(rs_n, 1),
                  "index_agreement_vs_f32": float(np.mean(idx16 == idx32)),
                  "speedup_vs_f32": float(np.median(per_row["match_f32"]) /

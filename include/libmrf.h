@@ -621,6 +621,17 @@ int mrf_server_destroy(mrf_server* srv);
  * Errors: out_len not a positive multiple of 256, iters < 1, bad dtype ->
  * MRF_ERR_INVALID (nothing launched).
  *
+ * mrf_probe_mfma_varied ("k_probe_mfma_bf16_varied"): the MRF_BF16 loop of
+ * mrf_probe_mfma with operands that vary by lane and element: element e of
+ * operand fragment f (8 per lane, two per accumulator) in lane l is
+ * 0.375 * ((7 l + 13 f + 29 e) mod 61) - 11 rounded to BF16. The matrix
+ * cores draw more power on such data and the clock drops, so this is the
+ * BF16 rate a GEMM on real data can approach. out (device float[out_len],
+ * caller-owned) receives each lane's sum of its 64 accumulator values; the
+ * operands are multiples of 1/8 below 12 in magnitude, so for iters <= 7
+ * every partial sum is a multiple of 1/64 below 2^18 and the result is exact.
+ * *flops as above. Errors as for mrf_probe_mfma.
+ *
  * mrf_probe_write ("k_probe_write"): fills `bytes` (a multiple of 16) at dst
  * (16-byte aligned device memory, caller-owned) with one 16 B store per
  * thread, each workgroup writing one contiguous 4 KB piece; 16-byte element
@@ -629,6 +640,8 @@ int mrf_server_destroy(mrf_server* srv);
  * ---------------------------------------------------------------------- */
 int mrf_probe_mfma(mrf_context* ctx, mrf_dtype dtype, int64_t iters, float* out, int64_t out_len,
                    double* flops, void* stream);
+int mrf_probe_mfma_varied(mrf_context* ctx, int64_t iters, float* out, int64_t out_len,
+                          double* flops, void* stream);
 int mrf_probe_write(mrf_context* ctx, void* dst, int64_t bytes, uint32_t pattern, void* stream);
 
 /* ------------------------------------------------------------------------

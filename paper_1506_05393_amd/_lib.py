@@ -92,6 +92,8 @@ _SIGS = [
       C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mrf_probe_mfma", C.c_int,
      [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p]),
+    ("mrf_probe_mfma_varied", C.c_int,
+     [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p]),
     ("mrf_probe_write", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]),
     ("mrf_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
     ("mrf_profile_read", C.c_int,

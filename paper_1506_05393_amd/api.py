@@ -724,6 +724,18 @@ def probe_mfma(ctx: Context, dtype: str, iters: int, out: torch.Tensor, stream=N
     return float(fl.value)
 
 
+def probe_mfma_varied(ctx: Context, iters: int, out: torch.Tensor, stream=None) -> float:
+    """BF16 MFMA-only loop on lane- and element-varying operands (libmrf
+    mrf_probe_mfma_varied). Returns the flops the launch performs; it does
+    not wait."""
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 CUDA tensor")
+    fl = C.c_double()
+    L.check(ctx._lib.mrf_probe_mfma_varied(ctx.handle, int(iters), out.data_ptr(), out.numel(),
+                                           C.byref(fl), _stream_ptr(stream)))
+    return float(fl.value)
+
+
 def probe_write(ctx: Context, dst: torch.Tensor, pattern: int = 0x5A5A5A5A, stream=None) -> int:
     """Fill a contiguous CUDA tensor with non-temporal 16 B stores (libmrf
     mrf_probe_write). Returns the bytes written; it does not wait."""

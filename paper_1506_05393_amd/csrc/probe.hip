@@ -5,6 +5,9 @@
 //    GEMMs (v_mfma_f32_32x32x2_f32, v_mfma_f32_32x32x16_bf16): four
 //    independent accumulators per wave, so the matrix pipe never waits for
 //    a result;
+//  - the BF16 loop again with operands that differ from lane to lane and
+//    element to element: the chip lowers its clock under the power such
+//    data draws, so this is the rate a GEMM on real data can approach;
 //  - a write-only stream of 16 B stores (the dictionary generator's bound).
 #include <hip/hip_runtime.h>
 
@@ -66,6 +69,33 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mfma_bf16(int64_t iters
   out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = s;
 }
 
+// Operand element e of fragment f in lane l: 0.375 * ((7 l + 13 f + 29 e) mod 61) - 11,
+// rounded to BF16 (values in [-11, 11.5], every mantissa pattern in play).
+__global__ __launch_bounds__(kProbeThreads) void k_probe_mfma_bf16_varied(int64_t iters,
+                                                                           float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  bf16x8_t fr[2 * kProbeAcc];
+#pragma unroll
+  for (int f = 0; f < 2 * kProbeAcc; ++f)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      fr[f][e] = (__bf16)(0.375f * (float)((7 * lane + 13 * f + 29 * e) % 61) - 11.0f);
+  f32x16 acc[kProbeAcc];
+#pragma unroll
+  for (int i = 0; i < kProbeAcc; ++i) acc[i] = f32x16{};
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < kProbeAcc; ++i)
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fr[2 * i], fr[2 * i + 1], acc[i], 0, 0, 0);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < kProbeAcc; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += acc[i][r];
+  out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = s;
+}
+
 // One 16 B store per thread, each workgroup one contiguous 4 KB piece (the
 // fastest of the write-stream shapes measured: wider per-thread runs and
 // grid-stride loops were slower); element i = (pattern, i, pattern, i).
@@ -110,6 +140,26 @@ extern "C" int mrf_probe_mfma(mrf_context* ctx, mrf_dtype dtype, int64_t iters, 
     hipLaunchKernelGGL(k_probe_mfma_bf16, dim3((unsigned)blocks), dim3(kProbeThreads), 0, s,
                        iters, kProbeA, kProbeB, out);
   }
+  MRF_HIP(hipGetLastError());
+  return MRF_OK;
+}
+
+extern "C" int mrf_probe_mfma_varied(mrf_context* ctx, int64_t iters, float* out,
+                                     int64_t out_len, double* flops, void* stream) {
+  MRF_CHECK_ARG(ctx, "context must not be NULL");
+  MRF_CHECK_ARG(iters >= 1, "iters must be >= 1");
+  MRF_CHECK_ARG(out, "out must not be NULL");
+  MRF_CHECK_ARG(out_len >= kProbeThreads && out_len % kProbeThreads == 0,
+                "out_len (%lld) must be a positive multiple of %d", (long long)out_len,
+                kProbeThreads);
+  const int64_t blocks = out_len / kProbeThreads;
+  MRF_CHECK_ARG(blocks <= INT32_MAX, "out_len too large");
+  hipStream_t s = (hipStream_t)stream;
+  const double waves = (double)blocks * (kProbeThreads / 64);
+  if (flops) *flops = 32768.0 * kProbeAcc * (double)iters * waves;
+  ProfScope prof(ctx, "k_probe_mfma_bf16_varied", s);
+  hipLaunchKernelGGL(k_probe_mfma_bf16_varied, dim3((unsigned)blocks), dim3(kProbeThreads), 0, s,
+                     iters, out);
   MRF_HIP(hipGetLastError());
   return MRF_OK;
 }

@@ -56,6 +56,7 @@ def test_host_only_calls_without_gpu():
     assert lib.mrf_grid_size(api.GridArg(neg).ptr) == -1
     # argument checks of the peak probes come before any device work
     assert lib.mrf_probe_mfma(None, 0, 10, None, 256, None, None) == 1  # MRF_ERR_INVALID
+    assert lib.mrf_probe_mfma_varied(None, 10, None, 256, None, None) == 1
     assert lib.mrf_probe_write(None, None, 16, 0, None) == 1  # MRF_ERR_INVALID
 
 
