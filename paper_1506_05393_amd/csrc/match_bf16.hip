@@ -83,6 +83,7 @@ __device__ __forceinline__ void issue_stage(const MatchB16Args& a, uint4* As, ui
 // (raising the top-k thresholds early, so the rest inserts few candidates),
 // then the others in order. Returns the tile offset of the k-th visit.
 constexpr int TS = 16;
+constexpr int kMaxLate = 32;  // consecutive timed-out alignment waits before a workgroup stops aligning
 __device__ __forceinline__ int tile_at(int k, int nt) {
   const int n1 = (nt + TS - 1) / TS;
   if (k < n1) return k * TS;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
   const int grp = slot / per;
   uint32_t* ctr = a.sync + grp * 8 + xcd;
   const int rows_valid = min(a.grp_rows, a.n_row_tiles - grp * a.grp_rows);
-  bool align = true;  // lane 0 of wave 0 only
+  int n_late = 0;  // consecutive timed-out waits (lane 0 of wave 0 only)
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* As = (uint4*)smem;                  // [NSTAGE][BKB][BBM]
@@ -328,12 +329,21 @@ __global__ __launch_bounds__(512) void k_match_bf16(MatchB16Args a) {
         }
         // bounded wait (50 us of the 100 MHz real-time counter): peers that
         // are not resident (other kernels hold the CUs) only cost time, and
-        // after one timeout this workgroup stops aligning
+        // after kMaxLate timeouts in a row this workgroup stops aligning.
+        // Runs of up to 12 are normal in the first tiles of a round, whose
+        // list insertions (8 per voxel in the first tile) make workgroups
+        // uneven; later waits stay below 35 us.
         const uint64_t t0 = wall_clock64();
-        while (align && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-          if (wall_clock64() - t0 > 5000) align = false;
+        bool late = false;
+        while (n_late < kMaxLate &&
+               __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          if (wall_clock64() - t0 > 5000) {
+            late = true;
+            break;
+          }
           __builtin_amdgcn_s_sleep(2);
         }
+        n_late = late ? n_late + 1 : (n_late < kMaxLate ? 0 : n_late);
       }
       __syncthreads();
     }
