@@ -1011,7 +1011,8 @@ def main():
                      "avg_ms": gemm_avg, "launches": gemm_n,
                      "algorithmic_flops_per_launch": flops,
                      "flops_note": "achieved counts 8 V N E (a complex MAC as 4 real MACs); the "
-                                   "kernel's three-product form issues 6 V N E MFMA flops",
+                                   "kernel's three-product form issues 6 V N E MFMA flops, so frac can "
+                                   "exceed 1; issued_frac is the MFMA utilisation",
                      "issued_frac": 0.75 * achieved / PEAK["fp32_mfma_tflops"],
                      "peak_measured": peaks["mfma_f32_tflops"] if peaks else None,
                      "frac_measured": achieved / peaks["mfma_f32_tflops"] if peaks else None},
